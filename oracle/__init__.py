@@ -1,0 +1,266 @@
+"""CPU oracle for BANG's batched PQ greedy search (arXiv 2401.11324).
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the benchmark's
+CPU-baseline leg use it; the product library never imports, links or calls
+it, and it shares no code with the GPU path.
+
+Contents (each routine cites the passage it follows in its own docstring or
+in oracle.c):
+
+* ``pq_tables``      stage 1, the PQ distance table, canonical FP32
+* ``adc``            asymmetric distance, canonical FP32
+* ``search``         stages 1-3: table, greedy search (Algorithm 1), re-rank
+* ``rerank``         stage 3 alone over given candidates
+* ``bruteforce``     exact k nearest (ground truth)
+* ``train_pq`` / ``pq_encode``   PQ codebooks (k-means) and codes
+* ``medoid`` / ``vamana_build`` / ``reachable``   the graph index
+
+Parity status: table, ADC, re-rank, search and brute force are pinned by the
+tests in tests/test_oracle_*.py (closed forms, brute force on tiny inputs,
+the paper's worked example).  The Vamana build and k-means training are
+"parity unpinned": no reference graph or codebook exists; only structural
+invariants and Lloyd monotonicity are checked.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+from .pq import train_pq, pq_encode, kmeans_assign  # noqa: F401
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "_oracle.so")
+
+DT = {"f32": 0, "u8": 1, "i8": 2, "f64": 3}
+NONE = 0xFFFFFFFF
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            from . import build as _b
+            _b.build()
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.c_void_p
+        u64, u32, f64 = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_double
+        L.or_pq_tables.argtypes = [P, ctypes.c_int, u64, u32, P, u32, P,
+                                   ctypes.c_int]
+        L.or_pq_tables.restype = None
+        L.or_adc.argtypes = [P, P, u32, P, u64, P]
+        L.or_adc.restype = None
+        L.or_search.argtypes = [P, P, u64, u32, u32, u32, u32, ctypes.c_int,
+                                P, P, P, P, P, u32, P, ctypes.c_int]
+        L.or_search.restype = ctypes.c_int
+        L.or_rerank.argtypes = [P, P, u64, P, u32, u32, P, P, ctypes.c_int]
+        L.or_rerank.restype = ctypes.c_int
+        L.or_bruteforce.argtypes = [P, ctypes.c_int, u64, u32, P, u64, u32,
+                                    P, P, ctypes.c_int]
+        L.or_bruteforce.restype = ctypes.c_int
+        L.or_kmeans_assign.argtypes = [P, u64, u32, P, u32, P, ctypes.c_int]
+        L.or_kmeans_assign.restype = f64
+        L.or_pq_encode.argtypes = [P, ctypes.c_int, u64, u32, P, u32, P,
+                                   ctypes.c_int]
+        L.or_pq_encode.restype = None
+        L.or_medoid.argtypes = [P, ctypes.c_int, u64, u32]
+        L.or_medoid.restype = u32
+        L.or_vamana_build.argtypes = [P, ctypes.c_int, u64, u32, u32, u32, P,
+                                      ctypes.c_int, P, u32, f64, u32, P,
+                                      ctypes.c_int]
+        L.or_vamana_build.restype = ctypes.c_int
+        L.or_reachable.argtypes = [P, u64, u32, u32]
+        L.or_reachable.restype = u64
+        L.or_connect.argtypes = [P, ctypes.c_int, u64, u32, P, u32, u32,
+                                 u32, ctypes.c_int]
+        L.or_connect.restype = ctypes.c_int64
+        L.or_max_threads.argtypes = []
+        L.or_max_threads.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def default_threads() -> int:
+    try:
+        return max(1, len(os.sched_getaffinity(0)))
+    except AttributeError:  # pragma: no cover
+        return os.cpu_count() or 1
+
+
+def _dtname(a: np.ndarray) -> str:
+    return {np.dtype(np.float32): "f32", np.dtype(np.uint8): "u8",
+            np.dtype(np.int8): "i8", np.dtype(np.float64): "f64"}[a.dtype]
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+class _OrIndex(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_uint64), ("d", ctypes.c_uint32),
+                ("dtype", ctypes.c_int32), ("base", ctypes.c_void_p),
+                ("R", ctypes.c_uint32), ("adj", ctypes.c_void_p),
+                ("medoid", ctypes.c_uint32), ("m", ctypes.c_uint32),
+                ("codebooks", ctypes.c_void_p), ("codes", ctypes.c_void_p)]
+
+
+class Index:
+    """Host-resident index as the oracle sees it (numpy arrays)."""
+
+    def __init__(self, base, adj, medoid, codebooks, codes):
+        self.base = np.ascontiguousarray(base)
+        self.adj = np.ascontiguousarray(adj, dtype=np.uint32)
+        self.medoid = int(medoid)
+        self.codebooks = np.ascontiguousarray(codebooks, dtype=np.float32)
+        self.codes = np.ascontiguousarray(codes, dtype=np.uint8)
+        n, d = self.base.shape
+        self.n, self.d = n, d
+        self.R = self.adj.shape[1]
+        self.m = self.codes.shape[1]
+        assert self.adj.shape[0] == n and self.codes.shape[0] == n
+        assert self.codebooks.shape == (self.m, 256, d // self.m)
+        self.dtype = _dtname(self.base)
+        self._c = _OrIndex(n, d, DT[self.dtype], self.base.ctypes.data, self.R,
+                           self.adj.ctypes.data, self.medoid, self.m,
+                           self.codebooks.ctypes.data, self.codes.ctypes.data)
+
+    @property
+    def cptr(self):
+        return ctypes.byref(self._c)
+
+
+def pq_tables(queries: np.ndarray, codebooks: np.ndarray, nthreads: int = 0):
+    """Stage 1 (section "Construction of PQDistTable in Parallel"):
+    T[q][j][c] = sum_t (q[j*d/m+t] - cb[j][c][t])^2, FP32 left to right."""
+    q = np.ascontiguousarray(queries)
+    cb = np.ascontiguousarray(codebooks, dtype=np.float32)
+    nq, d = q.shape
+    m = cb.shape[0]
+    T = np.empty((nq, m, 256), dtype=np.float32)
+    lib().or_pq_tables(_p(q), DT[_dtname(q)], nq, d, _p(cb), m, _p(T),
+                       nthreads or default_threads())
+    return T
+
+
+def adc(table: np.ndarray, codes: np.ndarray, ids: np.ndarray) -> np.ndarray:
+    """Asymmetric distance (section "Parallel Neighbour Distance
+    Computation"): sum_j T[j][code[j]], FP32 left to right."""
+    T = np.ascontiguousarray(table, dtype=np.float32)
+    c = np.ascontiguousarray(codes, dtype=np.uint8)
+    ids = np.ascontiguousarray(ids, dtype=np.uint32)
+    out = np.empty(len(ids), dtype=np.float32)
+    lib().or_adc(_p(T), _p(c), c.shape[1], _p(ids), len(ids), _p(out))
+    return out
+
+
+def iter_cap_for(L: int) -> int:
+    """Safety cap on iterations per query, identical on both sides."""
+    return 10 * L + 100
+
+
+def search(index: Index, queries: np.ndarray, k: int, L: int,
+           c_max: int | None = None, iter_cap: int | None = None,
+           mode: int = 0, want_pq: bool = False, want_cand: bool = False,
+           nthreads: int = 0):
+    """Stages 1-3 for a batch (Algorithms 1 and 2, sections on the PQ
+    table, re-ranking).  Returns a dict with ids, dists and, on request,
+    pq_ids/pq_dists (Algorithm 1's own top-k), cand (expanded nodes in
+    expansion order, NONE padded) and counters [I, status, added]."""
+    q = np.ascontiguousarray(queries, dtype=index.base.dtype)
+    nq = q.shape[0]
+    c_max = 4 * L if c_max is None else c_max
+    iter_cap = iter_cap_for(L) if iter_cap is None else iter_cap
+    ids = np.empty((nq, k), dtype=np.uint32)
+    dists = np.empty((nq, k), dtype=np.float32)
+    pq_ids = np.empty((nq, k), dtype=np.uint32) if want_pq else None
+    pq_d = np.empty((nq, k), dtype=np.float32) if want_pq else None
+    cand = np.empty((nq, iter_cap), dtype=np.uint32) if want_cand else None
+    counters = np.empty((nq, 4), dtype=np.uint32)
+    nul = ctypes.c_void_p(0)
+    rc = lib().or_search(
+        index.cptr, _p(q), nq, k, L, c_max, iter_cap, mode, _p(ids),
+        _p(dists), _p(pq_ids) if want_pq else nul,
+        _p(pq_d) if want_pq else nul, _p(cand) if want_cand else nul,
+        iter_cap, _p(counters), nthreads or default_threads())
+    if rc != 0:
+        raise ValueError(f"or_search failed ({rc})")
+    out = {"ids": ids, "dists": dists,
+           "iters": counters[:, 0].copy(), "status": counters[:, 1].copy(),
+           "added": counters[:, 2].astype(np.uint64)
+           | (counters[:, 3].astype(np.uint64) << np.uint64(32))}
+    if want_pq:
+        out["pq_ids"], out["pq_dists"] = pq_ids, pq_d
+    if want_cand:
+        out["cand"] = cand
+    return out
+
+
+def rerank(index: Index, queries: np.ndarray, cand: np.ndarray, k: int,
+           nthreads: int = 0):
+    """Stage 3 alone (section "Re-ranking"): exact distances of the given
+    candidates, sorted by (distance, id), top-k; NONE or ids >= n skipped."""
+    q = np.ascontiguousarray(queries, dtype=index.base.dtype)
+    cand = np.ascontiguousarray(cand, dtype=np.uint32)
+    nq, cm = cand.shape
+    ids = np.empty((nq, k), dtype=np.uint32)
+    dists = np.empty((nq, k), dtype=np.float32)
+    lib().or_rerank(index.cptr, _p(q), nq, _p(cand), cm, k, _p(ids),
+                    _p(dists), nthreads or default_threads())
+    return ids, dists
+
+
+def bruteforce(base: np.ndarray, queries: np.ndarray, k: int,
+               nthreads: int = 0):
+    """Exact k nearest by (squared L2, id): int64-exact for integer data,
+    FP64 for float data.  Returns (ids uint32, dists float64)."""
+    b = np.ascontiguousarray(base)
+    q = np.ascontiguousarray(queries, dtype=b.dtype)
+    n, d = b.shape
+    nq = q.shape[0]
+    ids = np.empty((nq, k), dtype=np.uint32)
+    dists = np.empty((nq, k), dtype=np.float64)
+    rc = lib().or_bruteforce(_p(b), DT[_dtname(b)], n, d, _p(q), nq, k,
+                             _p(ids), _p(dists), nthreads or default_threads())
+    if rc != 0:
+        raise ValueError("or_bruteforce failed")
+    return ids, dists
+
+
+def medoid(base: np.ndarray) -> int:
+    """Start node: the point nearest the mean (FP64), ties to the lowest id
+    (the paper only says it is fixed at build time)."""
+    b = np.ascontiguousarray(base)
+    n, d = b.shape
+    return int(lib().or_medoid(_p(b), DT[_dtname(b)], n, d))
+
+
+def vamana_build(base: np.ndarray, R: int, L_build: int, alpha: float,
+                 perm: np.ndarray, start: int, passes: int = 2,
+                 slack: float = 1.3, max_batch_frac: float = 0.02,
+                 nthreads: int = 0) -> np.ndarray:
+    """Vamana graph: pass 1 with alpha=1, pass 2 with the given alpha, over
+    the insertion order `perm`.  Returns adj[n][R] uint32, NONE padded."""
+    b = np.ascontiguousarray(base)
+    n, d = b.shape
+    alphas = np.array([1.0, alpha][-passes:] if passes <= 2 else
+                      [1.0] * (passes - 1) + [alpha], dtype=np.float64)
+    perm = np.ascontiguousarray(perm, dtype=np.uint32)
+    assert perm.shape == (n,)
+    adj = np.empty((n, R), dtype=np.uint32)
+    max_batch = max(1, int(n * max_batch_frac))
+    rc = lib().or_vamana_build(_p(b), DT[_dtname(b)], n, d, R, L_build,
+                               _p(alphas), len(alphas), _p(perm), start,
+                               slack, max_batch, _p(adj),
+                               nthreads or default_threads())
+    if rc != 0:
+        raise MemoryError("or_vamana_build failed")
+    return adj
+
+
+def reachable(adj: np.ndarray, start: int) -> int:
+    a = np.ascontiguousarray(adj, dtype=np.uint32)
+    n, R = a.shape
+    return int(lib().or_reachable(_p(a), n, R, start))

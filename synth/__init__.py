@@ -1,0 +1,125 @@
+"""Seeded synthetic inputs shared by the CPU oracle and the GPU path.
+
+This module only draws random numbers and lays them out; it holds none of
+the search method's arithmetic (no distances, no quantisation, no graph).
+Both sides of every parity check take their base vectors and queries from
+here, so neither side can feed the other.
+
+Workloads (stand-ins for the paper's SIFT / Deep / MSSPACEV style data, whose
+shapes and element types are listed in the paper's dataset table):
+
+* ``tiny``     n=10,000, d=128 float32, 32 centres U[-4,4]^128, unit noise;
+               100 queries.  Index: Vamana R=32, L_build=64, alpha=1.2;
+               PQ m=32 x 256.
+* ``sift1m``   n=1,000,000, d=128 uint8, 1,000 centres U[0,255]^128,
+               noise N(0, 20^2) per dimension, rounded half-to-even and
+               clipped to [0,255]; 10,000 queries.  Index: Vamana R=64,
+               L_build=100, alpha=1.2; PQ m=32 x 256.
+
+Seeding: ``numpy.random.SeedSequence(240111324 + workload_index).spawn(8)``
+gives independent streams, in order ``centres, base, queries, pq_sample,
+pq_init, vamana_order, workload, arrivals``.  Mixture weights are uniform:
+each point first draws its component, then its noise vector.
+"""
+from __future__ import annotations
+
+import dataclasses
+import numpy as np
+
+STREAMS = ("centres", "base", "queries", "pq_sample", "pq_init",
+           "vamana_order", "workload", "arrivals")
+SEED_BASE = 240111324
+
+
+@dataclasses.dataclass(frozen=True)
+class Workload:
+    name: str
+    index: int            # seed offset
+    n: int
+    d: int
+    dtype: str            # "f32" | "u8" | "i8"
+    ncent: int
+    centre_lo: float
+    centre_hi: float
+    sigma: float
+    nq: int
+    # index-build parameters
+    R: int
+    L_build: int
+    alpha: float
+    m: int
+    kmeans_iters: int
+    pq_sample: int
+    # search parameters
+    k: int
+    Ls: tuple
+
+    def with_(self, **kw) -> "Workload":
+        return dataclasses.replace(self, **kw)
+
+
+WORKLOADS = {
+    "tiny": Workload("tiny", 0, 10_000, 128, "f32", 32, -4.0, 4.0, 1.0, 100,
+                     32, 64, 1.2, 32, 10, 100_000, 10, (64,)),
+    "sift1m": Workload("sift1m", 1, 1_000_000, 128, "u8", 1000, 0.0, 255.0,
+                       20.0, 10_000, 64, 100, 1.2, 32, 10, 100_000, 10,
+                       (16, 32, 64, 128, 256)),
+}
+
+
+def np_dtype(dt: str):
+    return {"f32": np.float32, "u8": np.uint8, "i8": np.int8}[dt]
+
+
+def streams(w: Workload) -> dict:
+    seqs = np.random.SeedSequence(SEED_BASE + w.index).spawn(len(STREAMS))
+    return {name: np.random.Generator(np.random.PCG64(s))
+            for name, s in zip(STREAMS, seqs)}
+
+
+def _centres(w: Workload, rng) -> np.ndarray:
+    return rng.uniform(w.centre_lo, w.centre_hi, size=(w.ncent, w.d))
+
+
+def _draw(w: Workload, centres: np.ndarray, rng, count: int,
+          chunk: int = 1 << 16) -> np.ndarray:
+    """Draw `count` mixture points in chunks (bounded memory).
+
+    Component ids for all points come first, then the noise chunk by chunk,
+    so the result does not depend on the chunk size.
+    """
+    comp = rng.integers(0, w.ncent, size=count)
+    out = np.empty((count, w.d), dtype=np_dtype(w.dtype))
+    for s in range(0, count, chunk):
+        e = min(count, s + chunk)
+        x = centres[comp[s:e]] + w.sigma * rng.standard_normal((e - s, w.d))
+        if w.dtype == "f32":
+            out[s:e] = x.astype(np.float32)
+        elif w.dtype == "u8":
+            out[s:e] = np.clip(np.rint(x), 0, 255).astype(np.uint8)
+        else:
+            out[s:e] = np.clip(np.rint(x), -128, 127).astype(np.int8)
+    return out
+
+
+def base_and_queries(w: Workload):
+    """Return (base[n][d], queries[nq][d]) in the workload's element type."""
+    rs = streams(w)
+    c = _centres(w, rs["centres"])
+    base = _draw(w, c, rs["base"], w.n)
+    queries = _draw(w, c, rs["queries"], w.nq)
+    return base, queries
+
+
+def small(dtype: str = "f32", n: int = 2000, d: int = 32, nq: int = 20,
+          ncent: int = 8, seed_index: int = 100, **kw) -> Workload:
+    """A small workload for unit and parity tests (same recipe, own seed)."""
+    lo, hi, sigma = {"f32": (-4.0, 4.0, 1.0), "u8": (0.0, 255.0, 20.0),
+                     "i8": (-128.0, 127.0, 20.0)}[dtype]
+    base = dict(name=f"small-{dtype}-{n}-{d}", index=seed_index, n=n, d=d,
+                dtype=dtype, ncent=ncent, centre_lo=lo, centre_hi=hi,
+                sigma=sigma, nq=nq, R=16, L_build=32, alpha=1.2,
+                m=max(1, d // 4), kmeans_iters=6, pq_sample=n, k=10,
+                Ls=(32,))
+    base.update(kw)
+    return Workload(**base)

@@ -1,0 +1,377 @@
+"""Pins for the CPU oracle: checks against what the paper and the
+mathematics fix, not against the oracle itself.
+
+Each test names the passage or the mathematical fact it rests on.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle.graph import build_graph
+from oracle.pq import kmeans, kmeans_assign, pq_encode, train_pq
+
+NONE = 0xFFFFFFFF
+
+
+# --------------------------------------------------------------------------
+# helpers: small indexes built with the oracle
+# --------------------------------------------------------------------------
+def make_index(w, graph=True):
+    rs = synth.streams(w)
+    base, q = synth.base_and_queries(w)
+    cb = train_pq(base, w.m, w.kmeans_iters, rs["pq_init"])
+    codes = pq_encode(base, cb)
+    s = oracle.medoid(base)
+    perm = rs["vamana_order"].permutation(w.n).astype(np.uint32)
+    if graph:
+        adj, info = build_graph(base, w.R, w.L_build, w.alpha, perm, s)
+    else:
+        adj = oracle.vamana_build(base, w.R, w.L_build, w.alpha, perm, s)
+        info = {}
+    return oracle.Index(base, adj, s, cb, codes), q, info
+
+
+@pytest.fixture(scope="module")
+def small_f32():
+    return make_index(synth.small("f32", n=1500, d=32, nq=24))
+
+
+@pytest.fixture(scope="module")
+def small_u8():
+    return make_index(synth.small("u8", n=1200, d=32, nq=24, seed_index=101))
+
+
+@pytest.fixture(scope="module")
+def small_i8():
+    return make_index(synth.small("i8", n=900, d=16, nq=16, seed_index=102))
+
+
+def exact_sq(base, q):
+    """Squared L2 from q to every base row, exact (int64 or FP64)."""
+    if base.dtype == np.float32:
+        b = base.astype(np.float64)
+        return ((b - q.astype(np.float64)) ** 2).sum(1)
+    b = base.astype(np.int64)
+    return ((b - q.astype(np.int64)) ** 2).sum(1)
+
+
+# --------------------------------------------------------------------------
+# Stage 1 + ADC: the worked example of Figure 2
+# --------------------------------------------------------------------------
+def toy_setup(golden):
+    g = golden("toy_fig2.json")
+    pts = np.array(g["points"], dtype=np.uint8)
+    cid = np.array(g["fig2b_cluster_id"], dtype=np.uint8)
+    cb = np.full((1, 256, 2), 255.0, dtype=np.float32)
+    cb[0, cid] = pts.astype(np.float32)          # centroid = the point itself
+    q = np.array([g["query"]], dtype=np.uint8)
+    return g, pts, cid, cb, q
+
+
+def test_toy_table_and_adc_match_fig2b(golden):
+    """Figure 2b: with m=1 and every point its own centroid, the PQ distance
+    of a node is the table entry of its cluster id."""
+    g, pts, cid, cb, q = toy_setup(golden)
+    T = oracle.pq_tables(q, cb)
+    assert T.shape == (1, 1, 256)
+    assert np.array_equal(T[0, 0, cid], np.array(g["fig2b_pq_distance"],
+                                                 dtype=np.float32))
+    codes = cid.reshape(-1, 1)
+    d = oracle.adc(T[0], codes, np.arange(12, dtype=np.uint32))
+    assert np.array_equal(d, np.array(g["fig2b_pq_distance"], np.float32))
+
+
+def test_toy_rerank_matches_fig2d_and_final_order(golden):
+    """Figure 2d lists the expanded candidates with exact distances; the
+    text after the figure gives their sorted order and the top-2."""
+    g, pts, cid, cb, q = toy_setup(golden)
+    adj = np.full((12, 2), NONE, dtype=np.uint32)
+    ix = oracle.Index(pts, adj, 6, cb, cid.reshape(-1, 1))
+    cand = np.array([g["fig2d_expansion_order"]], dtype=np.uint32)
+    ids, d = oracle.rerank(ix, q, cand, 8)
+    assert ids[0].tolist() == g["final_sorted"]
+    ids2, _ = oracle.rerank(ix, q, cand, 2)
+    assert ids2[0].tolist() == g["top2"]
+    exact = dict(zip(g["fig2d_expansion_order"], g["fig2d_exact_distance"]))
+    assert d[0].tolist() == [float(exact[i]) for i in g["final_sorted"]]
+
+
+# --------------------------------------------------------------------------
+# Stage 1: table closed form
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("dtype", ["f32", "u8", "i8"])
+def test_table_equals_subspace_distances(dtype):
+    """T[j][c] is the squared distance between the j-th query subvector and
+    centroid c of subspace j (section on the PQ distance table)."""
+    rng = np.random.default_rng(7)
+    m, ds = 8, 4
+    d = m * ds
+    cb = rng.normal(size=(m, 256, ds)).astype(np.float32) * 30
+    if dtype == "f32":
+        q = rng.normal(size=(5, d)).astype(np.float32) * 30
+    elif dtype == "u8":
+        q = rng.integers(0, 256, size=(5, d)).astype(np.uint8)
+    else:
+        q = rng.integers(-128, 128, size=(5, d)).astype(np.int8)
+    T = oracle.pq_tables(q, cb)
+    qs = q.astype(np.float64).reshape(5, m, 1, ds)
+    ref = ((qs - cb.astype(np.float64)[None]) ** 2).sum(-1)
+    np.testing.assert_allclose(T, ref, rtol=2e-6, atol=1e-3)
+
+
+def test_table_integer_inputs_are_exact():
+    """With integer queries and integer centroids every partial sum is an
+    integer below 2^24, so the FP32 table is exact."""
+    rng = np.random.default_rng(3)
+    cb = rng.integers(0, 256, size=(4, 256, 4)).astype(np.float32)
+    q = rng.integers(0, 256, size=(3, 16)).astype(np.uint8)
+    T = oracle.pq_tables(q, cb)
+    ref = ((q.astype(np.int64).reshape(3, 4, 1, 4)
+            - cb.astype(np.int64)[None]) ** 2).sum(-1)
+    assert np.array_equal(T.astype(np.int64), ref)
+
+
+def test_adc_equals_distance_to_decoded_vector(small_f32):
+    """ADC(x) = sum_j T[j][code_j] = ||q - x_hat||^2 where x_hat is x's
+    decoded vector (concatenated centroids); exact in real arithmetic."""
+    ix, q, _ = small_f32
+    T = oracle.pq_tables(q[:3], ix.codebooks)
+    ids = np.arange(0, ix.n, 7, dtype=np.uint32)
+    ds = ix.d // ix.m
+    for a in range(3):
+        d = oracle.adc(T[a], ix.codes, ids).astype(np.float64)
+        xhat = ix.codebooks[np.arange(ix.m)[None, :], ix.codes[ids]]
+        xhat = xhat.reshape(len(ids), ix.m * ds).astype(np.float64)
+        ref = ((xhat - q[a].astype(np.float64)) ** 2).sum(1)
+        np.testing.assert_allclose(d, ref, rtol=1e-5)
+
+
+# --------------------------------------------------------------------------
+# Stage 2: greedy search
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("fx", ["small_f32", "small_u8", "small_i8"])
+def test_search_with_L_at_least_n_is_brute_force(fx, request):
+    """With t >= n nothing is ever evicted, so on a graph where every node
+    is reachable from s (checked by breadth-first search) every node is
+    expanded; the re-rank then returns the exact k nearest, and Algorithm
+    1's own answer is the k nearest by PQ distance over all nodes."""
+    ix, q, info = request.getfixturevalue(fx)
+    assert oracle.reachable(ix.adj, ix.medoid) == ix.n
+    L = 256 if ix.n <= 256 else ix.n
+    k = 10
+    # L above the GPU's 256 limit is fine for the oracle
+    out = oracle.search(ix, q[:6], k, L, c_max=ix.n, iter_cap=ix.n + 1,
+                        want_pq=True)
+    assert (out["iters"] == ix.n).all()
+    assert (out["status"] == 0).all()
+    T = oracle.pq_tables(q[:6], ix.codebooks)
+    allid = np.arange(ix.n, dtype=np.uint32)
+    for a in range(6):
+        ex = exact_sq(ix.base, q[a])
+        order = np.lexsort((allid, ex))[:k]
+        assert out["ids"][a].tolist() == order.tolist()
+        if ix.base.dtype == np.float32:
+            # FP32 left-to-right sum vs the FP64 value: a few ulp apart
+            np.testing.assert_allclose(out["dists"][a], ex[order], rtol=2e-6)
+        else:
+            assert np.array_equal(out["dists"][a], ex[order].astype(np.float32))
+        pqd = oracle.adc(T[a], ix.codes, allid)
+        porder = np.lexsort((allid, pqd))[:k]
+        assert out["pq_ids"][a].tolist() == porder.tolist()
+
+
+@pytest.mark.parametrize("fx", ["small_f32", "small_u8"])
+@pytest.mark.parametrize("L", [10, 16, 33, 64])
+def test_algorithm1_and_filtered_form_agree(fx, L, request):
+    """Algorithm 1 (set union into the worklist) and Algorithm 2's filtered
+    form (distance only for never-seen nodes, sort, merge) expand the same
+    nodes in the same order and return the same answer: a node evicted from
+    a full worklist has a key at or above the worklist's last key, which
+    never grows once the worklist is full, so it can never re-enter."""
+    ix, q, _ = request.getfixturevalue(fx)
+    a = oracle.search(ix, q, 10, L, mode=0, want_pq=True, want_cand=True)
+    b = oracle.search(ix, q, 10, L, mode=1, want_pq=True, want_cand=True)
+    for key in ("ids", "dists", "pq_ids", "pq_dists", "cand", "iters"):
+        assert np.array_equal(a[key], b[key]), key
+    # the filtered form computes fewer distances
+    assert (b["added"] <= a["added"]).all()
+
+
+def test_search_invariants(small_u8):
+    """Invariants of Algorithm 1: every expansion is a distinct node; the
+    number of iterations is at least min(t, reachable) (section on the
+    worklist size: every worklist entry must be visited); results are
+    sorted by (distance, id) and distinct."""
+    ix, q, _ = small_u8
+    for L in (10, 32):
+        out = oracle.search(ix, q, 10, L, want_cand=True)
+        for a in range(len(q)):
+            I = out["iters"][a]
+            c = out["cand"][a][:I]
+            assert len(set(c.tolist())) == I
+            assert I >= min(L, ix.n)
+            assert (out["cand"][a][I:] == NONE).all()
+            d, ids = out["dists"][a], out["ids"][a]
+            keys = list(zip(d.tolist(), ids.tolist()))
+            assert keys == sorted(keys)
+            assert len(set(ids.tolist())) == len(ids)
+
+
+def test_iteration_cap_sets_status(small_u8):
+    ix, q, _ = small_u8
+    out = oracle.search(ix, q[:4], 10, 32, iter_cap=5, want_cand=True)
+    assert (out["iters"] == 5).all() and (out["status"] == 1).all()
+
+
+def test_search_rejects_k_above_L(small_u8):
+    ix, q, _ = small_u8
+    with pytest.raises(ValueError):
+        oracle.search(ix, q[:2], 20, 10)
+
+
+def test_short_result_is_padded():
+    """Fewer reachable nodes than k: the tail is (NONE, +inf)."""
+    w = synth.small("u8", n=300, d=16, nq=4, seed_index=103)
+    base, q = synth.base_and_queries(w)
+    rs = synth.streams(w)
+    cb = train_pq(base, w.m, 3, rs["pq_init"])
+    codes = pq_encode(base, cb)
+    adj = np.full((w.n, 4), NONE, dtype=np.uint32)
+    adj[0, :3] = [1, 2, 3]                      # only 4 nodes reachable
+    ix = oracle.Index(base, adj, 0, cb, codes)
+    out = oracle.search(ix, q, 10, 16)
+    assert (out["iters"] == 4).all()
+    assert (out["ids"][:, 4:] == NONE).all()
+    assert np.isinf(out["dists"][:, 4:]).all()
+    assert set(out["ids"][0, :4].tolist()) == {0, 1, 2, 3}
+
+
+# --------------------------------------------------------------------------
+# Stage 3: re-rank
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("fx", ["small_f32", "small_u8", "small_i8"])
+def test_rerank_is_sort_by_exact_distance(fx, request):
+    """Re-rank definition (section "Re-ranking"): exact distances of the
+    candidates, sorted by (distance, id), top-k.  Padding is skipped."""
+    ix, q, _ = request.getfixturevalue(fx)
+    rng = np.random.default_rng(11)
+    cm = 40
+    cand = rng.choice(ix.n, size=(len(q), cm)).astype(np.uint32)
+    cand[:, -5:] = NONE
+    cand[0, :] = NONE
+    for a in range(len(q)):
+        cand[a, :cm - 5] = rng.choice(ix.n, cm - 5, replace=False)
+    cand[0, :] = NONE
+    ids, d = oracle.rerank(ix, q, cand, 10)
+    assert (ids[0] == NONE).all() and np.isinf(d[0]).all()
+    for a in range(1, len(q)):
+        c = cand[a][cand[a] != NONE]
+        ex = exact_sq(ix.base[c], q[a])
+        o = np.lexsort((c, ex))[:10]
+        assert ids[a].tolist() == c[o].tolist()
+        np.testing.assert_allclose(d[a], ex[o], rtol=1e-6)
+        if ix.base.dtype != np.float32:
+            assert np.array_equal(d[a], ex[o].astype(np.float32))
+
+
+def test_cmax_keeps_smallest_pq_keys(small_u8):
+    """With more expanded nodes than c_max, the c_max with the smallest
+    (PQ distance, id) go to the re-rank: the result equals re-ranking that
+    subset directly."""
+    ix, q, _ = small_u8
+    L, cm = 32, 20
+    out = oracle.search(ix, q, 10, L, c_max=cm, want_cand=True)
+    T = oracle.pq_tables(q, ix.codebooks)
+    for a in range(len(q)):
+        I = out["iters"][a]
+        c = out["cand"][a][:I]
+        assert I > cm
+        pq = oracle.adc(T[a], ix.codes, c)
+        keep = c[np.lexsort((c, pq))[:cm]]
+        ids, d = oracle.rerank(ix, q[a:a + 1], keep[None, :], 10)
+        assert ids[0].tolist() == out["ids"][a].tolist()
+
+
+# --------------------------------------------------------------------------
+# Ground truth
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("dtype", ["f32", "u8", "i8"])
+def test_bruteforce_matches_sorted_exact_distances(dtype):
+    w = synth.small(dtype, n=700, d=24, nq=9, seed_index=104)
+    base, q = synth.base_and_queries(w)
+    base[5] = base[6]          # an exact tie: ids break it
+    ids, d = oracle.bruteforce(base, q, 12)
+    allid = np.arange(w.n)
+    for a in range(len(q)):
+        ex = exact_sq(base, q[a])
+        o = np.lexsort((allid, ex))[:12]
+        assert ids[a].tolist() == o.tolist()
+        if dtype == "f32":      # numpy sums pairwise, the oracle in order
+            np.testing.assert_allclose(d[a], ex[o], rtol=1e-12)
+        else:
+            assert np.array_equal(d[a], ex[o].astype(np.float64))
+
+
+# --------------------------------------------------------------------------
+# PQ training and encoding (parity unpinned: properties only)
+# --------------------------------------------------------------------------
+def test_kmeans_objective_non_increasing_and_assignment_optimal():
+    """Lloyd's iterations never increase the k-means objective; each point
+    is assigned to its nearest centroid, ties to the lowest id."""
+    rng = np.random.default_rng(5)
+    X = rng.normal(size=(3000, 3)) * [1, 2, 3]
+    hist = []
+    C = kmeans(X, 256, 8, np.random.default_rng(6), history=hist)
+    assert all(b <= a * (1 + 1e-12) for a, b in zip(hist, hist[1:]))
+    a, obj = kmeans_assign(X, C)
+    D = ((X[:, None, :] - C[None]) ** 2).sum(-1)
+    assert np.array_equal(a, D.argmin(1))
+    np.testing.assert_allclose(obj, D.min(1).sum(), rtol=1e-12)
+
+
+def test_pq_encode_is_nearest_centroid_per_subspace(small_u8):
+    ix, _, _ = small_u8
+    ds = ix.d // ix.m
+    X = ix.base[:200].astype(np.float64).reshape(200, ix.m, 1, ds)
+    D = ((X - ix.codebooks.astype(np.float64)[None]) ** 2).sum(-1)
+    assert np.array_equal(ix.codes[:200], D.argmin(-1).astype(np.uint8))
+
+
+def test_medoid_is_point_nearest_the_mean(small_f32):
+    ix, _, _ = small_f32
+    b = ix.base.astype(np.float64)
+    assert ix.medoid == int(((b - b.mean(0)) ** 2).sum(1).argmin())
+
+
+# --------------------------------------------------------------------------
+# Graph (parity unpinned: structural invariants only)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("fx", ["small_f32", "small_u8", "small_i8"])
+def test_graph_invariants(fx, request):
+    ix, _, info = request.getfixturevalue(fx)
+    adj = ix.adj
+    n, R = adj.shape
+    valid = adj != NONE
+    assert (adj[valid] < n).all()
+    assert not (adj == np.arange(n, dtype=np.uint32)[:, None]).any()
+    for row in adj:
+        r = row[row != NONE]
+        assert len(set(r.tolist())) == len(r)
+    assert oracle.reachable(adj, ix.medoid) == n
+    assert info["reachable"] == n
+
+
+def test_plain_vamana_degree_bound_and_prune_rule():
+    """Vamana: out-degree at most R, no self loops, no duplicate ids."""
+    w = synth.small("f32", n=800, d=16, nq=2, seed_index=105)
+    base, _ = synth.base_and_queries(w)
+    s = oracle.medoid(base)
+    perm = np.random.default_rng(1).permutation(w.n).astype(np.uint32)
+    adj = oracle.vamana_build(base, 12, 24, 1.2, perm, s)
+    deg = (adj != NONE).sum(1)
+    assert deg.max() <= 12 and deg.mean() > 4
+    assert not (adj == np.arange(w.n, dtype=np.uint32)[:, None]).any()
+    # determinism across thread counts
+    adj1 = oracle.vamana_build(base, 12, 24, 1.2, perm, s, nthreads=1)
+    assert np.array_equal(adj, adj1)
