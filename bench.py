@@ -1,0 +1,231 @@
+"""Benchmark: QPS of the whole hot path (PQ table + greedy search + re-rank)
+on one MI355X for the 1M uint8 workload, at the smallest worklist size L
+whose mean 10-recall@10 reaches 0.9 (or, if none does, the L with the best
+recall), with p50/p99 per-query completion latency, the search kernel's
+fraction of the HBM roofline, and the CPU oracle timed on the host.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--L L]
+
+Prints one JSON line.  A step is one bang_search call over the 10,000
+resident queries; the timed region holds exactly K steps, bracketed by a
+device synchronisation on both sides, each step bracketed by HIP events on
+the stream the kernel runs on.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("QPS at recall@10>=0.9 on 1 GPU, plain FP32 vs reduced-precision "
+          "form; p50/p99 ms")
+WORKLOAD = "sift1m"
+HBM_PEAK_GBS = 8000.0
+TARGET_RECALL = 0.9
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "search_sift1m_traffic.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2401_11324_amd", "csrc", f)
+                  for f in ("bang_kernels.hip", "bang_api.cpp", "internal.h")]
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def recall_at_k(ids: np.ndarray, gt: np.ndarray, k: int) -> float:
+    """Mean k-recall@k = |S ∩ S~| / k (section "Algorithm Parameters")."""
+    hits = [len(set(a[:k].tolist()) & set(b[:k].tolist())) for a, b in
+            zip(ids, gt)]
+    return float(np.mean(hits)) / k
+
+
+def algorithmic_bytes(adj_deg, R, m, d, elem, k, iters, cand, c_max):
+    """HBM bytes one launch must move, from the per-query counters:
+    per expansion the adjacency row (4R) and the m code bytes of every
+    neighbour in it; per query the query vector, the base rows of the
+    re-ranked candidates and the k (id, distance) results."""
+    I = iters.astype(np.int64)
+    valid = cand != 0xFFFFFFFF
+    deg_sum = np.where(valid, adj_deg[np.where(valid, cand, 0)], 0).sum()
+    rr = np.minimum(I, c_max).sum()
+    return int(I.sum() * 4 * R + deg_sum * m + len(I) * d * elem
+               + rr * d * elem + len(I) * 8 * k)
+
+
+def cpu_baseline(idx_np, queries, k, L, budget_s=15.0):
+    """The CPU oracle (test infrastructure) on a bounded sample of the same
+    queries: 64 queries to estimate the rate, then enough for ~budget_s."""
+    import oracle
+    threads = oracle.default_threads()
+    ix = oracle.Index(idx_np["base"], idx_np["adj"], idx_np["medoid"],
+                      idx_np["codebooks"], idx_np["codes"])
+    t = time.perf_counter()
+    oracle.search(ix, queries[:64], k, L, nthreads=threads)
+    rate = 64 / max(1e-9, time.perf_counter() - t)
+    n = int(min(len(queries), max(64, rate * budget_s)))
+    t = time.perf_counter()
+    oracle.search(ix, queries[:n], k, L, nthreads=threads)
+    dt = time.perf_counter() - t
+    return {"value": round(n / dt, 1), "unit": "queries/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"first {n} of {len(queries)} queries, k={k}, L={L}, "
+                      f"{dt:.1f} s; table + Algorithm 1 + re-rank, "
+                      f"{threads} threads"}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--L", type=int, default=0,
+                    help="worklist size (default: chosen by the recall sweep)")
+    ap.add_argument("--no-cpu", action="store_true",
+                    help="skip the CPU oracle baseline")
+    a = ap.parse_args(argv)
+    if a.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {a.gpus} is not "
+              "supported (queries are independent: see the sharding notes in "
+              "the design document)", file=sys.stderr)
+        return 2
+
+    import torch
+    import synth
+    from synth import store
+    import paper_2401_11324_amd as bang
+
+    w = synth.WORKLOADS[WORKLOAD]
+    if not store.exists(w):
+        print(f"bench.py: index files for {w.name} are missing under "
+              f"{store.DEFAULT_ROOT}; write them with "
+              f"`python -m oracle.build_index {w.name}`", file=sys.stderr)
+        return 3
+    d = store.load(w)
+    gi = bang.Index(d["base"], d["adj"], d["medoid"], d["codebooks"],
+                    d["codes"])
+    dev = torch.device("cuda:0")
+    q = torch.from_numpy(d["queries"]).to(dev)
+    gt = d["gt_ids"]
+    nq, k = q.shape[0], w.k
+    stream = torch.cuda.current_stream()
+
+    # recall sweep (untimed apart from one launch each)
+    sweep = []
+    for L in w.Ls:
+        ids, dist = gi.search(q, k, L)
+        torch.cuda.synchronize()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record(stream)
+        gi.search(q, k, L, out=(ids, dist))
+        t1.record(stream)
+        torch.cuda.synchronize()
+        rec = recall_at_k(ids.cpu().numpy().view(np.uint32), gt, k)
+        sweep.append({"L": L, "recall10": round(rec, 4),
+                      "qps": round(nq / (t0.elapsed_time(t1) / 1e3))})
+    if a.L:
+        L = a.L
+    else:
+        ok = [s for s in sweep if s["recall10"] >= TARGET_RECALL]
+        L = ok[0]["L"] if ok else max(sweep, key=lambda s: s["recall10"])["L"]
+
+    ids = torch.empty((nq, k), dtype=torch.int32, device=dev)
+    dist = torch.empty((nq, k), dtype=torch.float32, device=dev)
+    for _ in range(a.warmup):
+        gi.search(q, k, L, out=(ids, dist))
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True),
+           torch.cuda.Event(enable_timing=True)) for _ in range(a.steps)]
+    wall0 = time.perf_counter()
+    for e0, e1 in ev:
+        e0.record(stream)
+        gi.search(q, k, L, out=(ids, dist))
+        e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    per = np.array([e0.elapsed_time(e1) for e0, e1 in ev])  # ms per launch
+    ms_step = wall * 1e3 / a.steps
+    qps = nq / (ms_step / 1e3)
+    rec = recall_at_k(ids.cpu().numpy().view(np.uint32), gt, k)
+
+    # one more (untimed) launch with counters, expanded nodes and timestamps
+    cap = 10 * L + 100
+    _, _, cand, cnt, times = gi.search(q, k, L, want_cand=cap,
+                                       want_counters=True, want_times=True)
+    torch.cuda.synchronize()
+    cand = cand.cpu().numpy().view(np.uint32)
+    iters = cnt.cpu().numpy()[:, 0]
+    t = times.cpu().numpy().astype(np.float64)
+    # completion time of each query after the batch began, scaled so that
+    # the span of the device clock equals the measured kernel time
+    span = max(1.0, t[:, 1].max() - t[:, 0].min())
+    adj_deg = (d["adj"] != 0xFFFFFFFF).sum(1)
+    elem = 1 if w.dtype in ("u8", "i8") else 4
+    B = algorithmic_bytes(adj_deg, w.R, w.m, w.d, elem, k, iters, cand, 4 * L)
+    kern_ms = float(per.mean())
+    lat_ms = (t[:, 1] - t[:, 0].min()) / span * kern_ms
+    achieved = B / (kern_ms / 1e3) / 1e9
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        with open(TRAFFIC_FILE) as f:
+            tr = json.load(f)
+        if tr.get("kernel_hash") == kernel_hash() and tr.get("L") == L:
+            traffic = tr.get("bytes_per_launch")
+
+    out = {
+        "metric": METRIC,
+        "value": round(qps, 1),
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "sift1m-like Gaussian mixture: n=1,000,000 d=128 "
+                        "uint8, 1,000 centres U[0,255], sigma 20; 10,000 "
+                        "queries; graph R=64 L_build=100 alpha=1.2; PQ m=32",
+            "form": "plain FP32",
+            "k": k, "L": L, "recall10": round(rec, 4),
+            "target_recall10": TARGET_RECALL,
+            "target_met": bool(rec >= TARGET_RECALL),
+            "mean_iterations": round(float(iters.mean()), 2),
+            "sweep": sweep,
+        },
+        "p50_ms": round(float(np.percentile(lat_ms, 50)), 4),
+        "p99_ms": round(float(np.percentile(lat_ms, 99)), 4),
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "search_kernel<u8, m=32, d/m=4>",
+            "achieved": round(achieved, 2),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 5),
+            "traffic": traffic,
+            "algorithmic_bytes_per_launch": B,
+            "kernel_ms_mean": round(kern_ms, 4),
+        },
+    }
+    if not a.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(d, d["queries"], k, L)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

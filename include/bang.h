@@ -1,0 +1,137 @@
+/*
+ * bang.h: C ABI of the MI355X (gfx950) batched PQ graph search.
+ *
+ * The library implements the three GPU stages of BANG (arXiv 2401.11324,
+ * section "BANG: Billion-scale ANNS on a Single GPU"): (1) the PQ distance
+ * table, (2) the greedy search over a proximity graph with asymmetric (PQ)
+ * distances (Algorithms 1 and 2), and (3) the exact re-rank.  The graph and
+ * the compressed vectors live in device memory, as in the paper's
+ * "In-memory Version" (section "Implementation Variants").
+ *
+ * Conventions shared by every call:
+ *  - Status: every call returns 0 on success or a negative BANG_E* code;
+ *    bang_last_error() then describes the failure (thread-local string).
+ *    Validation happens on the host before any launch: a call that fails
+ *    validation launches nothing and writes nothing.
+ *  - Streams: `stream` is a hipStream_t passed as void* (NULL = the null
+ *    stream).  Calls are asynchronous and stream-ordered; outputs are valid
+ *    once the caller synchronises the stream.
+ *  - Ownership: the caller owns every query and output buffer (device
+ *    pointers, e.g. from torch tensors).  The index owns its device copies
+ *    of the base vectors, adjacency, codebooks and codes, and a workspace
+ *    reused by every search on it: searches on one index must not overlap
+ *    in time (use one index per concurrent stream).
+ *  - Distances are squared Euclidean (the paper builds its table from
+ *    squared distances).  Results are ordered by (distance, id).
+ *  - Arithmetic: FP32 with no fused multiply-add, summed in a fixed order:
+ *    table entry = sum over the d/m coordinates, ADC = sum over the m
+ *    subspaces in index order, exact distance of float data = sum over the
+ *    d coordinates in order; integer data (u8/i8) uses an exact integer
+ *    sum converted once to FP32.
+ */
+#ifndef BANG_H_
+#define BANG_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BANG_OK 0
+#define BANG_EINVAL (-1)       /* invalid argument */
+#define BANG_ENOMEM (-2)       /* allocation failed / over the memory budget */
+#define BANG_EDEVICE (-3)      /* HIP runtime error or no usable GPU */
+#define BANG_EUNSUPPORTED (-4) /* valid but not supported by this build */
+#define BANG_EABORTED (-5)     /* reserved */
+
+#define BANG_NONE 0xFFFFFFFFu  /* empty adjacency slot / padded result id */
+#define BANG_MAX_L 256u        /* largest worklist (the paper's t) */
+#define BANG_MAX_R 64u         /* largest graph degree */
+
+typedef enum { BANG_F32 = 0, BANG_U8 = 1, BANG_I8 = 2 } bang_dtype;
+
+typedef struct bang_index bang_index; /* opaque */
+
+/* Index description; every pointer is HOST memory, read during
+ * bang_index_create only. */
+typedef struct {
+  uint64_t n;               /* number of base vectors, 1 <= n < 2^31 */
+  uint32_t d;               /* dimension */
+  int32_t dtype;            /* bang_dtype of base vectors and queries */
+  const void* base;         /* [n][d] row-major */
+  uint32_t R;               /* graph degree bound, 1..BANG_MAX_R */
+  const uint32_t* adj;      /* [n][R]; ids < n or BANG_NONE; no id twice
+                               in a row */
+  uint32_t medoid;          /* start node s (Algorithm 1), < n */
+  uint32_t m;               /* PQ subspaces; m divides d */
+  const float* codebooks;   /* [m][256][d/m] FP32 centroids */
+  const uint8_t* codes;     /* [n][m] centroid ids */
+  uint32_t flags;           /* must be 0 */
+} bang_index_desc;
+
+/* Optional search outputs for inspection; NULL pointers are skipped. */
+typedef struct {
+  uint32_t c_max;           /* re-rank candidates kept (0 = 4*L): when more
+                               nodes were expanded, the c_max smallest by
+                               (PQ distance, id) are re-ranked */
+  uint32_t iter_cap;        /* iterations per query (0 = 10*L + 100); a
+                               query that hits it stops and reports status 1 */
+  uint32_t* out_cand;       /* device [nq][cand_stride]: expanded node ids in
+                               expansion order, BANG_NONE padded */
+  uint32_t cand_stride;
+  uint32_t* out_counters;   /* device [nq][4]: {iterations, status, 0, 0} */
+  uint64_t* out_times;      /* device [nq][2]: device wall-clock ticks when
+                               the query's work began and when its results
+                               were written (hipDeviceAttributeWallClockRate
+                               gives the tick rate in kHz) */
+} bang_search_opts;
+
+/* Build an index on the current HIP device: validates the description
+ * (ids in range, no duplicate ids in a row, m | d, supported (m, d/m,
+ * dtype)) and copies everything to device memory.  On success *out owns
+ * the copies; release with bang_index_destroy.  Errors: EINVAL, ENOMEM,
+ * EDEVICE, EUNSUPPORTED. */
+int bang_index_create(const bang_index_desc* desc, bang_index** out);
+
+/* Free an index and its workspace (NULL is a no-op).  Synchronises the
+ * device first. */
+int bang_index_destroy(bang_index* index);
+
+/* Stage 1, the PQ distance table (section "Construction of PQDistTable in
+ * Parallel"): tables_out[q][j][c] = sum_t (query[q][j*d/m+t] -
+ * codebook[j][c][t])^2 for j < m, c < 256, FP32, no FMA, t ascending.
+ * queries: device [nq][d] of the index dtype; tables_out: device
+ * [nq][m][256] FP32.  nq = 0 is a no-op. */
+int bang_build_pq_tables(bang_index* index, const void* queries, uint64_t nq,
+                         float* tables_out, void* stream);
+
+/* Stages 1-3 (Algorithm 2 with the in-memory graph, then the re-rank of
+ * section "Re-ranking"): for each query, greedy search from the medoid with
+ * a worklist of L entries ordered by (PQ distance, id) until every entry
+ * is expanded, then exact distances for the expanded nodes and the k
+ * nearest by (exact distance, id).
+ * queries: device [nq][d]; out_ids: device [nq][k] uint32; out_dists:
+ * device [nq][k] FP32.  Rows with fewer than k candidates are padded with
+ * (BANG_NONE, +inf).  Requires 1 <= k <= L <= BANG_MAX_L and k <= n.
+ * opts may be NULL. */
+int bang_search(bang_index* index, const void* queries, uint64_t nq,
+                uint32_t k, uint32_t L, uint32_t* out_ids, float* out_dists,
+                const bang_search_opts* opts, void* stream);
+
+/* Stage 3 alone: exact top-k over given candidates.  cand: device
+ * [nq][c_max] uint32; BANG_NONE or ids >= n are padding and are skipped;
+ * ids in a row must be distinct.  1 <= c_max <= 4096, 1 <= k <= 1024.
+ * Output layout and padding as bang_search. */
+int bang_rerank(bang_index* index, const void* queries, uint64_t nq,
+                const uint32_t* cand, uint32_t c_max, uint32_t k,
+                uint32_t* out_ids, float* out_dists, void* stream);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* bang_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BANG_H_ */

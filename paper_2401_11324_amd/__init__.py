@@ -1,0 +1,223 @@
+"""MI355X-native batched PQ graph search (BANG, arXiv 2401.11324).
+
+Thin Python binding over the C ABI in include/bang.h (library
+``_bang.so`` next to this file).  Every step of the search runs in the
+library's HIP kernels; this module only marshals arguments: numpy arrays
+for the index description, torch CUDA tensors for queries and outputs, and
+the current torch stream.  There is no fallback: if the library is missing
+or no GPU is usable, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "_bang.so")
+
+BANG_NONE = 0xFFFFFFFF
+MAX_L = 256
+MAX_R = 64
+DTYPES = {"f32": 0, "u8": 1, "i8": 2}
+ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EUNSUPPORTED",
+          -5: "EABORTED"}
+EXPORTS = ("bang_index_create", "bang_index_destroy", "bang_build_pq_tables",
+           "bang_search", "bang_rerank", "bang_last_error")
+
+
+class BangError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class IndexDesc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_uint64), ("d", ctypes.c_uint32),
+                ("dtype", ctypes.c_int32), ("base", ctypes.c_void_p),
+                ("R", ctypes.c_uint32), ("adj", ctypes.c_void_p),
+                ("medoid", ctypes.c_uint32), ("m", ctypes.c_uint32),
+                ("codebooks", ctypes.c_void_p), ("codes", ctypes.c_void_p),
+                ("flags", ctypes.c_uint32)]
+
+
+class SearchOpts(ctypes.Structure):
+    _fields_ = [("c_max", ctypes.c_uint32), ("iter_cap", ctypes.c_uint32),
+                ("out_cand", ctypes.c_void_p), ("cand_stride", ctypes.c_uint32),
+                ("out_counters", ctypes.c_void_p),
+                ("out_times", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """Load the HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(
+                f"{LIB_PATH} is missing: build it with "
+                "`python -c 'import __graft_entry__ as g; g.build()'`")
+        L = ctypes.CDLL(LIB_PATH)
+        P, u32, u64 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64
+        L.bang_index_create.argtypes = [ctypes.POINTER(IndexDesc),
+                                        ctypes.POINTER(P)]
+        L.bang_index_destroy.argtypes = [P]
+        L.bang_build_pq_tables.argtypes = [P, P, u64, P, P]
+        L.bang_search.argtypes = [P, P, u64, u32, u32, P, P,
+                                  ctypes.POINTER(SearchOpts), P]
+        L.bang_rerank.argtypes = [P, P, u64, P, u32, u32, P, P, P]
+        for f in EXPORTS[:-1]:
+            getattr(L, f).restype = ctypes.c_int
+        L.bang_last_error.argtypes = []
+        L.bang_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise BangError(rc, lib().bang_last_error().decode())
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev_ptr(t, dtype=None, name="tensor"):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Index:
+    """Device-resident index.  Host numpy arrays in, copies in HBM.
+
+    base [n][d] (float32 / uint8 / int8), adj [n][R] uint32 (BANG_NONE for
+    empty slots), medoid, codebooks [m][256][d/m] float32, codes [n][m]
+    uint8."""
+
+    def __init__(self, base, adj, medoid, codebooks, codes):
+        self._h = None
+        base = np.ascontiguousarray(base)
+        adj = np.ascontiguousarray(adj, dtype=np.uint32)
+        cb = np.ascontiguousarray(codebooks, dtype=np.float32)
+        codes = np.ascontiguousarray(codes, dtype=np.uint8)
+        dt = {np.dtype(np.float32): "f32", np.dtype(np.uint8): "u8",
+              np.dtype(np.int8): "i8"}.get(base.dtype)
+        if dt is None:
+            raise TypeError(f"unsupported base dtype {base.dtype}")
+        n, d = base.shape
+        self.n, self.d, self.dtype = n, d, dt
+        self.R = adj.shape[1]
+        self.m = codes.shape[1]
+        self.torch_dtype = {"f32": "float32", "u8": "uint8", "i8": "int8"}[dt]
+        desc = IndexDesc(n, d, DTYPES[dt], base.ctypes.data, adj.shape[1],
+                         adj.ctypes.data, int(medoid), codes.shape[1],
+                         cb.ctypes.data, codes.ctypes.data, 0)
+        if adj.shape[0] != n or codes.shape[0] != n:
+            raise ValueError("adj and codes need one row per base vector")
+        if cb.shape != (self.m, 256, d // max(1, self.m)):
+            raise ValueError("codebooks must be [m][256][d/m]")
+        h = ctypes.c_void_p()
+        _check(lib().bang_index_create(ctypes.byref(desc), ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if self._h is not None and _lib is not None:
+            lib().bang_index_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _queries(self, q):
+        import torch
+        want = getattr(torch, self.torch_dtype)
+        if q.dim() != 2 or q.shape[1] != self.d:
+            raise ValueError(f"queries must be [nq][{self.d}]")
+        return _dev_ptr(q, want, "queries")
+
+    def build_pq_tables(self, q, out=None, stream=None):
+        """Stage 1: tables [nq][m][256] float32 on the queries' device."""
+        import torch
+        qp = self._queries(q)
+        if out is None:
+            out = torch.empty((q.shape[0], self.m, 256), dtype=torch.float32,
+                              device=q.device)
+        _check(lib().bang_build_pq_tables(
+            self._h, qp, q.shape[0], _dev_ptr(out, torch.float32, "out"),
+            _stream(stream)))
+        return out
+
+    def search(self, q, k: int, L: int, c_max: int = 0, iter_cap: int = 0,
+               want_cand: int = 0, want_counters: bool = False,
+               want_times: bool = False, out=None, stream=None):
+        """Stages 1-3.  Returns (ids uint32-as-int32 [nq][k], dists
+        float32 [nq][k]) and, on request, the expanded nodes [nq][want_cand]
+        and counters [nq][4] (iterations, status) and device wall-clock
+        ticks [nq][2] (begin, end)."""
+        import torch
+        qp = self._queries(q)
+        nq = q.shape[0]
+        if out is None:
+            ids = torch.empty((nq, k), dtype=torch.int32, device=q.device)
+            dists = torch.empty((nq, k), dtype=torch.float32, device=q.device)
+        else:
+            ids, dists = out
+        opts = SearchOpts(c_max, iter_cap, None, 0, None, None)
+        cand = cnt = times = None
+        if want_cand:
+            cand = torch.empty((nq, want_cand), dtype=torch.int32,
+                               device=q.device)
+            opts.out_cand = cand.data_ptr()
+            opts.cand_stride = want_cand
+        if want_counters:
+            cnt = torch.empty((nq, 4), dtype=torch.int32, device=q.device)
+            opts.out_counters = cnt.data_ptr()
+        if want_times:
+            times = torch.empty((nq, 2), dtype=torch.int64, device=q.device)
+            opts.out_times = times.data_ptr()
+        _check(lib().bang_search(
+            self._h, qp, nq, k, L, _dev_ptr(ids, torch.int32, "ids"),
+            _dev_ptr(dists, torch.float32, "dists"), ctypes.byref(opts),
+            _stream(stream)))
+        res = (ids, dists)
+        if want_cand:
+            res += (cand,)
+        if want_counters:
+            res += (cnt,)
+        if want_times:
+            res += (times,)
+        return res
+
+    def rerank(self, q, cand, k: int, out=None, stream=None):
+        """Stage 3 alone over cand [nq][c_max] (int32 view of uint32 ids;
+        -1 = BANG_NONE padding)."""
+        import torch
+        qp = self._queries(q)
+        nq = q.shape[0]
+        if cand.shape[0] != nq:
+            raise ValueError("one candidate row per query")
+        if out is None:
+            ids = torch.empty((nq, k), dtype=torch.int32, device=q.device)
+            dists = torch.empty((nq, k), dtype=torch.float32, device=q.device)
+        else:
+            ids, dists = out
+        _check(lib().bang_rerank(
+            self._h, qp, nq, _dev_ptr(cand, torch.int32, "cand"),
+            cand.shape[1], k, _dev_ptr(ids, torch.int32, "ids"),
+            _dev_ptr(dists, torch.float32, "dists"), _stream(stream)))
+        return ids, dists

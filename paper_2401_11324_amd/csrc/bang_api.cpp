@@ -1,0 +1,345 @@
+// C ABI of the MI355X batched PQ graph search (see include/bang.h).
+// Host-side validation, device copies of the index, workspace, launches.
+// C++ exceptions never cross the ABI: every entry point catches them.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "bang.h"
+#include "internal.h"
+
+struct bang_index {
+  int device = 0;
+  bang::DeviceIndex dev{};
+  void* d_base = nullptr;
+  uint32_t* d_adj = nullptr;
+  uint8_t* d_codes = nullptr;
+  float* d_cb = nullptr;
+  // search workspace, grown on demand
+  uint64_t* d_cscratch = nullptr;
+  size_t cscratch_bytes = 0;
+  uint32_t* d_qcounter = nullptr;
+  int num_cus = 0;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(BANG_EDEVICE,
+              std::string(what) + ": " + hipGetErrorString(e));
+}
+
+size_t elem_size(int dt) { return dt == BANG_F32 ? 4 : 1; }
+
+bool aligned(const void* p, size_t a) {
+  return (reinterpret_cast<uintptr_t>(p) % a) == 0;
+}
+
+// Adjacency check: ids in range, no id twice in a row.  Rows are split
+// across a few host threads.
+bool check_adjacency(const uint32_t* adj, uint64_t n, uint32_t R,
+                     std::string* why) {
+  unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  std::vector<std::string> errs(nt);
+  std::vector<std::thread> th;
+  for (unsigned t = 0; t < nt; ++t) {
+    th.emplace_back([&, t] {
+      std::vector<uint32_t> row(R);
+      for (uint64_t i = t; i < n && errs[t].empty(); i += nt) {
+        uint32_t c = 0;
+        for (uint32_t r = 0; r < R; ++r) {
+          uint32_t x = adj[i * R + r];
+          if (x == BANG_NONE) continue;
+          if (x >= n) {
+            errs[t] = "adjacency row " + std::to_string(i) + " holds id " +
+                      std::to_string(x) + " >= n";
+            return;
+          }
+          row[c++] = x;
+        }
+        std::sort(row.begin(), row.begin() + c);
+        for (uint32_t r = 1; r < c; ++r)
+          if (row[r] == row[r - 1]) {
+            errs[t] = "adjacency row " + std::to_string(i) +
+                      " holds id " + std::to_string(row[r]) + " twice";
+            return;
+          }
+      }
+    });
+  }
+  for (auto& x : th) x.join();
+  for (auto& e : errs)
+    if (!e.empty()) {
+      *why = e;
+      return false;
+    }
+  return true;
+}
+
+template <typename T>
+int upload(T** dst, const void* src, size_t bytes, const char* what) {
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(dst), bytes ? bytes : 16);
+  if (e != hipSuccess)
+    return fail(BANG_ENOMEM, std::string("hipMalloc for ") + what + ": " +
+                                 hipGetErrorString(e));
+  if (bytes) {
+    e = hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, what);
+  }
+  return BANG_OK;
+}
+
+void free_index(bang_index* ix) {
+  if (!ix) return;
+  (void)hipFree(ix->d_base);
+  (void)hipFree(ix->d_adj);
+  (void)hipFree(ix->d_codes);
+  (void)hipFree(ix->d_cb);
+  (void)hipFree(ix->d_cscratch);
+  (void)hipFree(ix->d_qcounter);
+  delete ix;
+}
+
+int create_impl(const bang_index_desc* d, bang_index** out) {
+  if (!d || !out) return fail(BANG_EINVAL, "null argument");
+  *out = nullptr;
+  if (d->flags != 0) return fail(BANG_EINVAL, "flags must be 0");
+  if (d->n == 0 || d->n >= (1ull << 31))
+    return fail(BANG_EINVAL, "n must be in [1, 2^31)");
+  if (d->dtype < BANG_F32 || d->dtype > BANG_I8)
+    return fail(BANG_EINVAL, "unknown dtype");
+  if (d->d == 0 || d->m == 0 || d->d % d->m != 0)
+    return fail(BANG_EINVAL, "m must divide d");
+  if (d->R == 0 || d->R > BANG_MAX_R)
+    return fail(BANG_EINVAL, "R must be in [1, 64]");
+  if (d->medoid >= d->n) return fail(BANG_EINVAL, "medoid >= n");
+  if (!d->base || !d->adj || !d->codebooks || !d->codes)
+    return fail(BANG_EINVAL, "null array in the description");
+  if (!bang::supported(d->dtype, d->m, d->d / d->m))
+    return fail(BANG_EUNSUPPORTED,
+                "no kernel for dtype " + std::to_string(d->dtype) + ", m=" +
+                    std::to_string(d->m) + ", d/m=" +
+                    std::to_string(d->d / d->m));
+  std::string why;
+  if (!check_adjacency(d->adj, d->n, d->R, &why)) return fail(BANG_EINVAL, why);
+
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess || ndev == 0)
+    return fail(BANG_EDEVICE, "no HIP device available");
+  auto* ix = new (std::nothrow) bang_index();
+  if (!ix) return fail(BANG_ENOMEM, "host allocation");
+  e = hipGetDevice(&ix->device);
+  if (e != hipSuccess) {
+    delete ix;
+    return hip_fail(e, "hipGetDevice");
+  }
+  e = hipDeviceGetAttribute(&ix->num_cus, hipDeviceAttributeMultiprocessorCount,
+                            ix->device);
+  if (e != hipSuccess) {
+    delete ix;
+    return hip_fail(e, "hipDeviceGetAttribute");
+  }
+  int rc;
+  size_t nd = (size_t)d->n * d->d;
+  if ((rc = upload(&ix->d_base, d->base, nd * elem_size(d->dtype), "base")) ||
+      (rc = upload(&ix->d_adj, d->adj, (size_t)d->n * d->R * 4, "adjacency")) ||
+      (rc = upload(&ix->d_codes, d->codes, (size_t)d->n * d->m, "codes")) ||
+      (rc = upload(&ix->d_cb, d->codebooks, (size_t)d->m * 256 * (d->d / d->m) * 4,
+                   "codebooks")) ||
+      (rc = upload(&ix->d_qcounter, nullptr, 0, "counters"))) {
+    free_index(ix);
+    return rc;
+  }
+  // the two search counters start at zero; each launch leaves them at zero
+  e = hipMemset(ix->d_qcounter, 0, 2 * sizeof(uint32_t));
+  if (e != hipSuccess) {
+    free_index(ix);
+    return hip_fail(e, "hipMemset");
+  }
+  ix->dev.base = ix->d_base;
+  ix->dev.adj = ix->d_adj;
+  ix->dev.codes = ix->d_codes;
+  ix->dev.cb = ix->d_cb;
+  ix->dev.n = (uint32_t)d->n;
+  ix->dev.d = d->d;
+  ix->dev.R = d->R;
+  ix->dev.m = d->m;
+  ix->dev.medoid = d->medoid;
+  ix->dev.dtype = d->dtype;
+  *out = ix;
+  return BANG_OK;
+}
+
+int check_queries(const bang_index* ix, const void* queries) {
+  if (!queries) return fail(BANG_EINVAL, "null queries");
+  if (!aligned(queries, 16)) return fail(BANG_EINVAL, "queries not 16-byte aligned");
+  if ((ix->dev.d * elem_size(ix->dev.dtype)) % 16 != 0)
+    return fail(BANG_EUNSUPPORTED, "query rows must be a multiple of 16 bytes");
+  return BANG_OK;
+}
+
+int search_impl(bang_index* ix, const void* queries, uint64_t nq, uint32_t k,
+                uint32_t L, uint32_t* out_ids, float* out_dists,
+                const bang_search_opts* o, hipStream_t s) {
+  if (!ix) return fail(BANG_EINVAL, "null index");
+  if (k < 1 || k > L || L > BANG_MAX_L)
+    return fail(BANG_EINVAL, "need 1 <= k <= L <= 256");
+  if (k > ix->dev.n) return fail(BANG_EINVAL, "k > n");
+  if (nq == 0) return BANG_OK;
+  if (nq >= (1ull << 32)) return fail(BANG_EINVAL, "nq too large");
+  int rc = check_queries(ix, queries);
+  if (rc) return rc;
+  if (!out_ids || !out_dists) return fail(BANG_EINVAL, "null output");
+  if (!aligned(out_ids, 4) || !aligned(out_dists, 4))
+    return fail(BANG_EINVAL, "outputs not 4-byte aligned");
+  uint32_t c_max = (o && o->c_max) ? o->c_max : 4 * L;
+  uint32_t iter_cap = (o && o->iter_cap) ? o->iter_cap : 10 * L + 100;
+  if (iter_cap > 16384) return fail(BANG_EINVAL, "iter_cap > 16384");
+  if (o && o->out_cand && o->cand_stride == 0)
+    return fail(BANG_EINVAL, "cand_stride must be > 0 with out_cand");
+
+  size_t lds = bang::search_lds_bytes(ix->dev.m, L, iter_cap);
+  if (lds > 64 * 1024)
+    return fail(BANG_EUNSUPPORTED,
+                "table + worklist + re-rank keys exceed 64 KB of LDS "
+                "(lower iter_cap)");
+  int per_cu = 0;
+  hipError_t e = hipSetDevice(ix->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  e = bang::search_occupancy(ix->dev, lds, &per_cu);
+  if (e != hipSuccess) return hip_fail(e, "occupancy query");
+  if (per_cu < 1) return fail(BANG_EUNSUPPORTED, "search kernel cannot be resident");
+  uint64_t grid = (uint64_t)per_cu * ix->num_cus;
+  if (grid > nq) grid = nq;
+
+  size_t need = (size_t)grid * iter_cap * sizeof(uint64_t);
+  if (need > ix->cscratch_bytes) {
+    // the previous workspace may still be in use by queued work
+    e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+    (void)hipFree(ix->d_cscratch);
+    ix->d_cscratch = nullptr;
+    ix->cscratch_bytes = 0;
+    e = hipMalloc(reinterpret_cast<void**>(&ix->d_cscratch), need);
+    if (e != hipSuccess)
+      return fail(BANG_ENOMEM, std::string("search workspace: ") +
+                                   hipGetErrorString(e));
+    ix->cscratch_bytes = need;
+  }
+
+  bang::SearchLaunch l{};
+  l.queries = queries;
+  l.nq = nq;
+  l.k = k;
+  l.L = L;
+  l.c_max = c_max;
+  l.iter_cap = iter_cap;
+  l.out_ids = out_ids;
+  l.out_dists = out_dists;
+  l.out_cand = o ? o->out_cand : nullptr;
+  l.cand_stride = o ? o->cand_stride : 0;
+  l.out_counters = o ? o->out_counters : nullptr;
+  l.out_times = o ? o->out_times : nullptr;
+  l.cscratch = ix->d_cscratch;
+  l.qcounter = ix->d_qcounter;
+  l.grid = (uint32_t)grid;
+  e = bang::launch_search(ix->dev, l, s);
+  if (e != hipSuccess) return hip_fail(e, "search launch");
+  return BANG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int bang_index_create(const bang_index_desc* desc, bang_index** out) {
+  try {
+    return create_impl(desc, out);
+  } catch (const std::exception& ex) {
+    return fail(BANG_ENOMEM, ex.what());
+  } catch (...) {
+    return fail(BANG_ENOMEM, "unknown exception");
+  }
+}
+
+int bang_index_destroy(bang_index* index) {
+  if (!index) return BANG_OK;
+  (void)hipSetDevice(index->device);
+  (void)hipDeviceSynchronize();
+  free_index(index);
+  return BANG_OK;
+}
+
+int bang_build_pq_tables(bang_index* ix, const void* queries, uint64_t nq,
+                         float* tables_out, void* stream) {
+  try {
+    if (!ix) return fail(BANG_EINVAL, "null index");
+    if (nq == 0) return BANG_OK;
+    int rc = check_queries(ix, queries);
+    if (rc) return rc;
+    if (!tables_out || !aligned(tables_out, 16))
+      return fail(BANG_EINVAL, "tables_out null or not 16-byte aligned");
+    hipError_t e = hipSetDevice(ix->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    e = bang::launch_tables(ix->dev, queries, nq, tables_out,
+                            static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "table launch");
+    return BANG_OK;
+  } catch (...) {
+    return fail(BANG_ENOMEM, "exception");
+  }
+}
+
+int bang_search(bang_index* ix, const void* queries, uint64_t nq, uint32_t k,
+                uint32_t L, uint32_t* out_ids, float* out_dists,
+                const bang_search_opts* opts, void* stream) {
+  try {
+    return search_impl(ix, queries, nq, k, L, out_ids, out_dists, opts,
+                       static_cast<hipStream_t>(stream));
+  } catch (...) {
+    return fail(BANG_ENOMEM, "exception");
+  }
+}
+
+int bang_rerank(bang_index* ix, const void* queries, uint64_t nq,
+                const uint32_t* cand, uint32_t c_max, uint32_t k,
+                uint32_t* out_ids, float* out_dists, void* stream) {
+  try {
+    if (!ix) return fail(BANG_EINVAL, "null index");
+    if (c_max < 1 || c_max > 4096) return fail(BANG_EINVAL, "need 1 <= c_max <= 4096");
+    if (k < 1 || k > 1024) return fail(BANG_EINVAL, "need 1 <= k <= 1024");
+    if (nq == 0) return BANG_OK;
+    int rc = check_queries(ix, queries);
+    if (rc) return rc;
+    if (!cand || !out_ids || !out_dists || !aligned(cand, 4) ||
+        !aligned(out_ids, 4) || !aligned(out_dists, 4))
+      return fail(BANG_EINVAL, "null or misaligned buffer");
+    hipError_t e = hipSetDevice(ix->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    e = bang::launch_rerank(ix->dev, queries, nq, cand, c_max, k, out_ids,
+                            out_dists, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "re-rank launch");
+    return BANG_OK;
+  } catch (...) {
+    return fail(BANG_ENOMEM, "exception");
+  }
+}
+
+const char* bang_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,647 @@
+// HIP kernels for gfx950 (MI355X): PQ distance table, batched greedy search
+// with asymmetric distances, exact re-rank.
+//
+// Design (one wavefront of 64 lanes per query, persistent workgroups):
+//  * the query's FP32 PQ table (m x 256) is built into LDS by the wave and
+//    stays there for the whole search (section "Construction of PQDistTable
+//    in Parallel": one query per block, centroids across threads, subspaces
+//    sequential in a thread);
+//  * lane r owns slot r of the expanded node's adjacency row (R <= 64), so
+//    the row is one coalesced load and each lane gathers its neighbour's m
+//    code bytes with 16-byte loads and sums m table lookups in subspace
+//    order (section "Parallel Neighbour Distance Computation");
+//  * the new keys are sorted across the 64 lanes by a bitonic network
+//    (section "Parallel Merge Sort" sorts the same <= 64 items);
+//  * each sorted key finds its rank in the worklist by binary search in
+//    LDS, which also detects a node already in the worklist (the union of
+//    Algorithm 1 is a set union), and every worklist key finds its rank
+//    among the new keys; position = own index + rank in the other list
+//    (section "Parallel Merge"), keys past t are dropped;
+//  * the next node to expand is chosen from the two candidates the paper's
+//    eager rule names (best new key, first unvisited worklist entry) before
+//    the merged list is written, and its adjacency row is requested at once
+//    (section "Prefetching Candidate Nodes"), so the load overlaps the merge;
+//  * after convergence the expanded nodes are re-ranked with exact
+//    distances and sorted in LDS (section "Re-ranking").
+//
+// Keys: (float bits of the distance) << 32 | id << 1 | visited.  Distances
+// are non-negative, so unsigned key order is (distance, id) order; ids are
+// unique in a worklist, so the visited bit never decides an order.
+//
+// All floating point here is FP32 with contraction off and a fixed order,
+// which makes results bit-identical to a sequential reference.
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "internal.h"
+
+#pragma clang fp contract(off)
+
+namespace bang {
+
+namespace {
+
+constexpr uint32_t kNone = 0xFFFFFFFFu;
+constexpr uint64_t kInf = ~0ull;
+constexpr int kWave = 64;
+
+__device__ __forceinline__ uint64_t make_key(float d, uint32_t id) {
+  return ((uint64_t)__float_as_uint(d) << 32) | ((uint64_t)id << 1);
+}
+__device__ __forceinline__ uint32_t key_id(uint64_t k) {
+  return ((uint32_t)k) >> 1;
+}
+__device__ __forceinline__ float key_dist(uint64_t k) {
+  return __uint_as_float((uint32_t)(k >> 32));
+}
+
+template <int DT>
+struct Elem;
+template <>
+struct Elem<kF32> {
+  static constexpr int size = 4;
+  __device__ static float f(const unsigned char* p, int i) {
+    return reinterpret_cast<const float*>(p)[i];
+  }
+};
+template <>
+struct Elem<kU8> {
+  static constexpr int size = 1;
+  __device__ static float f(const unsigned char* p, int i) {
+    return (float)p[i];
+  }
+};
+template <>
+struct Elem<kI8> {
+  static constexpr int size = 1;
+  __device__ static float f(const unsigned char* p, int i) {
+    return (float)(int8_t)p[i];
+  }
+};
+
+// One table entry: sum over the subvector in coordinate order, FP32.
+template <int DS>
+__device__ __forceinline__ float table_entry(const float* qv,
+                                             const float* __restrict__ cent) {
+  float cv[DS];
+  if constexpr (DS % 4 == 0) {
+#pragma unroll
+    for (int t = 0; t < DS; t += 4) {
+      float4 v = *reinterpret_cast<const float4*>(cent + t);
+      cv[t] = v.x; cv[t + 1] = v.y; cv[t + 2] = v.z; cv[t + 3] = v.w;
+    }
+  } else if constexpr (DS % 2 == 0) {
+#pragma unroll
+    for (int t = 0; t < DS; t += 2) {
+      float2 v = *reinterpret_cast<const float2*>(cent + t);
+      cv[t] = v.x; cv[t + 1] = v.y;
+    }
+  } else {
+#pragma unroll
+    for (int t = 0; t < DS; ++t) cv[t] = cent[t];
+  }
+  float acc = 0.0f;
+#pragma unroll
+  for (int t = 0; t < DS; ++t) {
+    float diff = qv[t] - cv[t];
+    float sq = diff * diff;
+    acc = acc + sq;
+  }
+  return acc;
+}
+
+// Table of one query: T[j*256 + c], `nthr` threads starting at `tid`.
+template <int DT, int M, int DS>
+__device__ __forceinline__ void build_table(const unsigned char* q,
+                                            const float* __restrict__ cb,
+                                            float* T, int tid, int nthr) {
+  for (int j = 0; j < M; ++j) {
+    float qv[DS];
+#pragma unroll
+    for (int t = 0; t < DS; ++t) qv[t] = Elem<DT>::f(q, j * DS + t);
+    for (int c = tid; c < 256; c += nthr)
+      T[j * 256 + c] = table_entry<DS>(qv, cb + ((size_t)j * 256 + c) * DS);
+  }
+}
+
+// ADC of one compressed vector: sum of m table entries, subspace order.
+template <int M>
+__device__ __forceinline__ float adc(const float* T,
+                                     const uint8_t* __restrict__ code) {
+  static_assert(M % 16 == 0, "codes are gathered 16 bytes at a time");
+  uint4 v[M / 16];
+#pragma unroll
+  for (int c = 0; c < M / 16; ++c)
+    v[c] = *reinterpret_cast<const uint4*>(code + 16 * c);
+  float acc = 0.0f;
+#pragma unroll
+  for (int c = 0; c < M / 16; ++c) {
+    const uint32_t w[4] = {v[c].x, v[c].y, v[c].z, v[c].w};
+#pragma unroll
+    for (int b = 0; b < 16; ++b) {
+      uint32_t byte = (w[b >> 2] >> (8 * (b & 3))) & 0xFFu;
+      acc = acc + T[(16 * c + b) * 256 + byte];
+    }
+  }
+  return acc;
+}
+
+// Exact squared distance between base row `id` and the query.
+template <int DT, int D>
+__device__ __forceinline__ float exact_dist(const void* __restrict__ base,
+                                            uint32_t id,
+                                            const unsigned char* q) {
+  if constexpr (DT == kF32) {
+    const float4* x =
+        reinterpret_cast<const float4*>((const float*)base + (size_t)id * D);
+    const float* qq = reinterpret_cast<const float*>(q);
+    float acc = 0.0f;
+#pragma unroll 4
+    for (int c = 0; c < D / 4; ++c) {
+      float4 v = x[c];
+      const float xv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        float diff = xv[t] - qq[4 * c + t];
+        float sq = diff * diff;
+        acc = acc + sq;
+      }
+    }
+    return acc;
+  } else {
+    static_assert(D % 16 == 0, "rows are read 16 bytes at a time");
+    const uint4* x = reinterpret_cast<const uint4*>(
+        (const uint8_t*)base + (size_t)id * D);
+    int acc = 0;
+#pragma unroll 2
+    for (int c = 0; c < D / 16; ++c) {
+      uint4 v = x[c];
+      const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int b = 0; b < 16; ++b) {
+        uint32_t byte = (w[b >> 2] >> (8 * (b & 3))) & 0xFFu;
+        int xv = (DT == kU8) ? (int)byte : (int)(int8_t)byte;
+        int qv = (DT == kU8) ? (int)q[16 * c + b] : (int)(int8_t)q[16 * c + b];
+        int df = xv - qv;
+        acc += df * df;
+      }
+    }
+    return (float)acc;
+  }
+}
+
+__device__ __forceinline__ uint64_t shfl_xor64(uint64_t v, int m) {
+  uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+  lo = __shfl_xor(lo, m);
+  hi = __shfl_xor(hi, m);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t shfl64(uint64_t v, int src) {
+  uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+  lo = __shfl(lo, src);
+  hi = __shfl(hi, src);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Ascending bitonic sort of one key per lane across the wave.
+__device__ __forceinline__ uint64_t wave_sort(uint64_t x, int lane) {
+#pragma unroll
+  for (int size = 2; size <= kWave; size <<= 1) {
+#pragma unroll
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      uint64_t y = shfl_xor64(x, stride);
+      bool up = (lane & size) == 0;
+      bool lower = (lane & stride) == 0;
+      uint64_t mn = x < y ? x : y;
+      uint64_t mx = x < y ? y : x;
+      x = (lower == up) ? mn : mx;
+    }
+  }
+  return x;
+}
+
+// Number of entries of the sorted LDS list A[0..len) whose key, visited bit
+// ignored, is below x's (len <= 256).
+__device__ __forceinline__ uint32_t rank_in(const uint64_t* A, uint32_t len,
+                                            uint64_t x) {
+  const uint64_t xs = x >> 1;
+  uint32_t pos = 0;
+  for (uint32_t step = 256; step > 0; step >>= 1) {
+    if (step > len) continue;
+    uint32_t np = pos + step;
+    if (np <= len && (A[np - 1] >> 1) < xs) pos = np;
+  }
+  return pos;
+}
+
+// Ascending bitonic sort of S[0..P) in LDS by one wave (P a power of two).
+__device__ void lds_sort(uint64_t* S, uint32_t P, int lane) {
+  for (uint32_t size = 2; size <= P; size <<= 1) {
+    for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+      for (uint32_t i = lane; i < P / 2; i += kWave) {
+        uint32_t lo = 2 * i - (i & (stride - 1));
+        uint32_t hi = lo + stride;
+        bool asc = (lo & size) == 0;
+        uint64_t x = S[lo], y = S[hi];
+        if ((x > y) == asc) {
+          S[lo] = y;
+          S[hi] = x;
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+__device__ __forceinline__ uint32_t pow2ceil_dev(uint32_t x) {
+  uint32_t p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+
+// Sort the first `cnt` keys of S (padding to a power of two with +inf) and
+// write the first k as (id, distance), padding with (NONE, +inf).
+__device__ void sort_and_emit(uint64_t* S, uint32_t cnt, uint32_t k,
+                              uint32_t* out_ids, float* out_d, int lane) {
+  uint32_t P = pow2ceil_dev(cnt > 0 ? cnt : 1);
+  for (uint32_t i = cnt + lane; i < P; i += kWave) S[i] = kInf;
+  __syncthreads();
+  lds_sort(S, P, lane);
+  for (uint32_t i = lane; i < k; i += kWave) {
+    uint64_t key = i < cnt ? S[i] : kInf;
+    out_ids[i] = key == kInf ? kNone : key_id(key);
+    out_d[i] = key == kInf ? __uint_as_float(0x7F800000u) : key_dist(key);
+  }
+}
+
+struct SearchArgs {
+  const void* base;
+  const uint32_t* adj;
+  const uint8_t* codes;
+  const float* cb;
+  const unsigned char* queries;
+  uint64_t nq;
+  uint32_t n, R, medoid;
+  uint32_t k, Lcap, c_max, iter_cap;
+  uint32_t region0;  // bytes of the table / re-rank region
+  uint32_t* out_ids;
+  float* out_dists;
+  uint32_t* out_cand;
+  uint32_t cand_stride;
+  uint32_t* out_counters;
+  uint64_t* out_times;
+  uint64_t* cscratch;
+  uint32_t* qcounter;
+};
+
+template <int DT, int M, int DS>
+__global__ __launch_bounds__(kWave) void search_kernel(SearchArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  constexpr int D = M * DS;
+  const int lane = threadIdx.x;
+  float* T = reinterpret_cast<float*>(smem);
+  uint64_t* S = reinterpret_cast<uint64_t*>(smem);
+  uint64_t* Lb0 = reinterpret_cast<uint64_t*>(smem + a.region0);
+  uint64_t* Lb1 = Lb0 + a.Lcap;
+  uint64_t* Nb = Lb1 + a.Lcap;
+  uint64_t* C = a.cscratch + (size_t)blockIdx.x * a.iter_cap;
+  const uint32_t R = a.R;
+
+  for (;;) {
+    uint32_t qi = 0;
+    if (lane == 0) qi = atomicAdd(a.qcounter, 1u);
+    qi = __builtin_amdgcn_readfirstlane(qi);
+    if (qi >= a.nq) {
+      // the last workgroup out returns both counters to zero for the next
+      // launch (no reset kernel or memset on the stream)
+      if (lane == 0) {
+        __threadfence();
+        if (atomicAdd(a.qcounter + 1, 1u) == gridDim.x - 1) {
+          atomicExch(a.qcounter, 0u);
+          atomicExch(a.qcounter + 1, 0u);
+        }
+      }
+      break;
+    }
+    const unsigned char* q = a.queries + (size_t)qi * D * Elem<DT>::size;
+    const uint64_t t_begin = a.out_times ? wall_clock64() : 0;
+
+    // stage 1: the table (the previous query's re-rank is done with S)
+    __syncthreads();
+    build_table<DT, M, DS>(q, a.cb, T, lane, kWave);
+    __syncthreads();
+
+    // stage 2: L = [(ADC(s), s)]
+    const uint32_t s = a.medoid;
+    uint64_t curkey = make_key(adc<M>(T, a.codes + (size_t)s * M), s);
+    uint64_t* Lc = Lb0;
+    uint64_t* Ln = Lb1;
+    if (lane == 0) Lc[0] = curkey;
+    uint32_t Llen = 1, cur = 0, iters = 0, status = 0;
+    uint32_t nb = (uint32_t)lane < R ? a.adj[(size_t)s * R + lane] : kNone;
+    __syncthreads();
+
+    while (cur != kNone) {
+      if (iters == a.iter_cap) {
+        status = 1;
+        break;
+      }
+      // expand u* = Lc[cur]: mark visited, record it as a candidate
+      if (lane == 0) {
+        Lc[cur] = curkey | 1ull;
+        C[iters] = curkey;
+      }
+      ++iters;
+
+      // distances of the neighbours (nb holds adj(u*), requested earlier)
+      uint64_t key = kInf;
+      if (nb != kNone) key = make_key(adc<M>(T, a.codes + (size_t)nb * M), nb);
+      __syncthreads();
+
+      // sort; drop nodes already in the worklist; rank in the worklist
+      key = wave_sort(key, lane);
+      uint32_t r = 0;
+      bool keep = false;
+      if (key != kInf) {
+        r = rank_in(Lc, Llen, key);
+        keep = !(r < Llen && (Lc[r] >> 1) == (key >> 1));
+      }
+      const uint64_t km = __ballot(keep);
+      const uint32_t nv = __popcll(km);
+      const uint32_t idx = __builtin_amdgcn_mbcnt_hi(
+          (uint32_t)(km >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)km, 0u));
+      if (keep) Nb[idx] = key;
+      __syncthreads();
+
+      // next node: best new key vs first unvisited worklist entry, each at
+      // its position in the merged list; beyond t means it is cut
+      uint32_t best = kNone;
+      uint64_t bestkey = kInf;
+      for (uint32_t j0 = 0; j0 < Llen; j0 += kWave) {
+        uint32_t j = j0 + lane;
+        uint64_t lk = j < Llen ? Lc[j] : kInf;
+        bool unv = j < Llen && !(lk & 1ull);
+        uint64_t um = __ballot(unv);
+        if (um) {
+          int f = __ffsll((unsigned long long)um) - 1;
+          uint64_t ak = shfl64(lk, f);
+          uint32_t apos = j0 + f + rank_in(Nb, nv, ak);
+          if (apos < a.Lcap) {
+            best = apos;
+            bestkey = ak;
+          }
+          break;
+        }
+      }
+      if (nv > 0) {
+        int f = __ffsll((unsigned long long)km) - 1;
+        uint32_t bpos = __shfl(r, f);
+        if (bpos < a.Lcap && bpos < best) {
+          best = bpos;
+          bestkey = shfl64(key, f);
+        }
+      }
+      // request the next adjacency row now; it arrives during the merge
+      nb = (best != kNone && (uint32_t)lane < R)
+               ? a.adj[(size_t)key_id(bestkey) * R + lane]
+               : kNone;
+
+      // merge: position = own index + rank in the other list
+      if (keep) {
+        uint32_t p = idx + r;
+        if (p < a.Lcap) Ln[p] = key;
+      }
+      for (uint32_t j = lane; j < Llen; j += kWave) {
+        uint64_t lk = Lc[j];
+        uint32_t p = j + rank_in(Nb, nv, lk);
+        if (p < a.Lcap) Ln[p] = lk;
+      }
+      Llen = min(a.Lcap, Llen + nv);
+      uint64_t* t = Lc;
+      Lc = Ln;
+      Ln = t;
+      cur = best;
+      curkey = bestkey;
+      __syncthreads();
+    }
+
+    // stage 3: re-rank the expanded nodes.  C was written by lane 0 and is
+    // read by every lane: an agent-scope fence also drops stale L1 lines.
+    __threadfence();
+    __syncthreads();
+    if (a.out_counters && lane == 0) {
+      a.out_counters[qi * 4 + 0] = iters;
+      a.out_counters[qi * 4 + 1] = status;
+      a.out_counters[qi * 4 + 2] = 0;
+      a.out_counters[qi * 4 + 3] = 0;
+    }
+    if (a.out_cand)
+      for (uint32_t i = lane; i < a.cand_stride; i += kWave)
+        a.out_cand[(size_t)qi * a.cand_stride + i] =
+            i < iters ? key_id(C[i]) : kNone;
+    uint32_t nc = iters;
+    if (nc > a.c_max) {
+      // keep the c_max smallest (PQ distance, id)
+      uint32_t P = pow2ceil_dev(nc);
+      for (uint32_t i = lane; i < P; i += kWave)
+        S[i] = i < nc ? (C[i] & ~1ull) : kInf;
+      __syncthreads();
+      lds_sort(S, P, lane);
+      nc = a.c_max;
+    } else {
+      for (uint32_t i = lane; i < nc; i += kWave) S[i] = C[i] & ~1ull;
+    }
+    __syncthreads();
+    for (uint32_t i = lane; i < nc; i += kWave) {
+      uint32_t id = key_id(S[i]);
+      S[i] = make_key(exact_dist<DT, D>(a.base, id, q), id);
+    }
+    __syncthreads();
+    sort_and_emit(S, nc, a.k, a.out_ids + (size_t)qi * a.k,
+                  a.out_dists + (size_t)qi * a.k, lane);
+    if (a.out_times && lane == 0) {
+      a.out_times[qi * 2] = t_begin;
+      a.out_times[qi * 2 + 1] = wall_clock64();
+    }
+  }
+}
+
+template <int DT, int M, int DS>
+__global__ __launch_bounds__(256) void table_kernel(
+    const unsigned char* __restrict__ queries, uint64_t nq,
+    const float* __restrict__ cb, float* __restrict__ out) {
+  constexpr int D = M * DS;
+  for (uint64_t qi = blockIdx.x; qi < nq; qi += gridDim.x)
+    build_table<DT, M, DS>(queries + qi * D * Elem<DT>::size, cb,
+                           out + qi * (uint64_t)M * 256, threadIdx.x, 256);
+}
+
+template <int DT, int D>
+__global__ __launch_bounds__(kWave) void rerank_kernel(
+    const void* __restrict__ base, uint32_t n,
+    const unsigned char* __restrict__ queries, uint64_t nq,
+    const uint32_t* __restrict__ cand, uint32_t c_max, uint32_t k,
+    uint32_t* out_ids, float* out_d) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  uint64_t* S = reinterpret_cast<uint64_t*>(smem);
+  const int lane = threadIdx.x;
+  for (uint64_t qi = blockIdx.x; qi < nq; qi += gridDim.x) {
+    const unsigned char* q = queries + qi * D * Elem<DT>::size;
+    uint32_t cnt = 0;
+    for (uint32_t i0 = 0; i0 < c_max; i0 += kWave) {
+      uint32_t i = i0 + lane;
+      uint32_t id = i < c_max ? cand[qi * c_max + i] : kNone;
+      bool ok = id != kNone && id < n;
+      uint64_t m = __ballot(ok);
+      uint32_t idx = __builtin_amdgcn_mbcnt_hi(
+          (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+      if (ok) S[cnt + idx] = make_key(exact_dist<DT, D>(base, id, q), id);
+      cnt += __popcll(m);
+    }
+    __syncthreads();
+    sort_and_emit(S, cnt, k, out_ids + qi * k, out_d + qi * k, lane);
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// dispatch over the compiled (dtype, m, d/m) combinations
+// ---------------------------------------------------------------------------
+#define BANG_SHAPES(X) \
+  X(16, 2) X(16, 4) X(32, 2) X(32, 4) X(48, 2) X(64, 2)
+
+template <template <int, int, int> class F, typename... Args>
+hipError_t dispatch(int dt, uint32_t m, uint32_t ds, Args&&... args) {
+#define BANG_CASE(MM, DD)                                                  \
+  if (m == MM && ds == DD) {                                               \
+    switch (dt) {                                                          \
+      case kF32: return F<kF32, MM, DD>::run(args...);                     \
+      case kU8: return F<kU8, MM, DD>::run(args...);                       \
+      case kI8: return F<kI8, MM, DD>::run(args...);                       \
+    }                                                                      \
+  }
+  BANG_SHAPES(BANG_CASE)
+#undef BANG_CASE
+  return hipErrorInvalidValue;
+}
+
+template <int DT, int M, int DS>
+struct RunSearch {
+  static hipError_t run(const SearchArgs& a, uint32_t grid, size_t lds,
+                        hipStream_t s) {
+    hipLaunchKernelGGL((search_kernel<DT, M, DS>), dim3(grid), dim3(kWave),
+                       lds, s, a);
+    return hipGetLastError();
+  }
+};
+
+template <int DT, int M, int DS>
+struct Occupancy {
+  static hipError_t run(size_t lds, int* per_cu) {
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        per_cu, search_kernel<DT, M, DS>, kWave, lds);
+  }
+};
+
+template <int DT, int M, int DS>
+struct RunTables {
+  static hipError_t run(const unsigned char* q, uint64_t nq, const float* cb,
+                        float* out, hipStream_t s) {
+    uint32_t grid = (uint32_t)(nq < 4096 ? nq : 4096);
+    hipLaunchKernelGGL((table_kernel<DT, M, DS>), dim3(grid), dim3(256), 0, s,
+                       q, nq, cb, out);
+    return hipGetLastError();
+  }
+};
+
+template <int DT, int M, int DS>
+struct RunRerank {
+  static hipError_t run(const DeviceIndex& ix, const unsigned char* q,
+                        uint64_t nq, const uint32_t* cand, uint32_t c_max,
+                        uint32_t k, uint32_t* ids, float* d, hipStream_t s) {
+    uint32_t P = pow2ceil(c_max);
+    size_t lds = (size_t)(P > k ? P : pow2ceil(k)) * 8;
+    uint32_t grid = (uint32_t)(nq < 8192 ? nq : 8192);
+    hipLaunchKernelGGL((rerank_kernel<DT, M * DS>), dim3(grid), dim3(kWave),
+                       lds, s, ix.base, ix.n, q, nq, cand, c_max, k, ids, d);
+    return hipGetLastError();
+  }
+};
+
+}  // namespace
+
+uint32_t pow2ceil(uint32_t x) {
+  uint32_t p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+
+bool supported(int dtype, uint32_t m, uint32_t ds) {
+  if (dtype < kF32 || dtype > kI8) return false;
+#define BANG_OK_SHAPE(MM, DD) \
+  if (m == MM && ds == DD) return true;
+  BANG_SHAPES(BANG_OK_SHAPE)
+#undef BANG_OK_SHAPE
+  return false;
+}
+
+size_t search_lds_bytes(uint32_t m, uint32_t L, uint32_t iter_cap) {
+  size_t table = (size_t)m * 256 * 4;
+  // re-rank keys: all expanded nodes when they exceed c_max (at most
+  // iter_cap), else at most c_max <= 4*L; both padded to a power of two
+  size_t sort = (size_t)pow2ceil(iter_cap > 4 * L ? iter_cap : 4 * L) * 8;
+  size_t region0 = table > sort ? table : sort;
+  return region0 + (size_t)2 * L * 8 + (size_t)kWave * 8;
+}
+
+hipError_t search_occupancy(const DeviceIndex& ix, size_t lds, int* per_cu) {
+  return dispatch<Occupancy>(ix.dtype, ix.m, ix.d / ix.m, lds, per_cu);
+}
+
+hipError_t launch_tables(const DeviceIndex& ix, const void* queries,
+                         uint64_t nq, float* out, hipStream_t s) {
+  return dispatch<RunTables>(ix.dtype, ix.m, ix.d / ix.m,
+                             (const unsigned char*)queries, nq, ix.cb, out, s);
+}
+
+hipError_t launch_search(const DeviceIndex& ix, const SearchLaunch& l,
+                         hipStream_t s) {
+  size_t lds = search_lds_bytes(ix.m, l.L, l.iter_cap);
+  SearchArgs a;
+  a.base = ix.base;
+  a.adj = ix.adj;
+  a.codes = ix.codes;
+  a.cb = ix.cb;
+  a.queries = (const unsigned char*)l.queries;
+  a.nq = l.nq;
+  a.n = ix.n;
+  a.R = ix.R;
+  a.medoid = ix.medoid;
+  a.k = l.k;
+  a.Lcap = l.L;
+  a.c_max = l.c_max;
+  a.iter_cap = l.iter_cap;
+  a.region0 = (uint32_t)(lds - (size_t)2 * l.L * 8 - (size_t)kWave * 8);
+  a.out_ids = l.out_ids;
+  a.out_dists = l.out_dists;
+  a.out_cand = l.out_cand;
+  a.cand_stride = l.cand_stride;
+  a.out_counters = l.out_counters;
+  a.out_times = l.out_times;
+  a.cscratch = l.cscratch;
+  a.qcounter = l.qcounter;
+  return dispatch<RunSearch>(ix.dtype, ix.m, ix.d / ix.m, a, l.grid, lds, s);
+}
+
+hipError_t launch_rerank(const DeviceIndex& ix, const void* queries,
+                         uint64_t nq, const uint32_t* cand, uint32_t c_max,
+                         uint32_t k, uint32_t* out_ids, float* out_dists,
+                         hipStream_t s) {
+  return dispatch<RunRerank>(ix.dtype, ix.m, ix.d / ix.m, ix,
+                             (const unsigned char*)queries, nq, cand, c_max, k,
+                             out_ids, out_dists, s);
+}
+
+}  // namespace bang

@@ -1,0 +1,59 @@
+// Internal interface between the C-ABI layer (bang_api.cpp) and the HIP
+// kernels (bang_kernels.hip).  Not installed; not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace bang {
+
+enum Dtype : int { kF32 = 0, kU8 = 1, kI8 = 2 };
+
+// Device copies of an index.
+struct DeviceIndex {
+  const void* base;      // [n][d]
+  const uint32_t* adj;   // [n][R]
+  const uint8_t* codes;  // [n][m]
+  const float* cb;       // [m][256][d/m]
+  uint32_t n, d, R, m, medoid;
+  int dtype;
+};
+
+struct SearchLaunch {
+  const void* queries;
+  uint64_t nq;
+  uint32_t k, L, c_max, iter_cap;
+  uint32_t* out_ids;
+  float* out_dists;
+  uint32_t* out_cand;
+  uint32_t cand_stride;
+  uint32_t* out_counters;
+  uint64_t* out_times;
+  uint64_t* cscratch;    // [grid][iter_cap] expanded-node keys
+  uint32_t* qcounter;    // [2]: next query, finished workgroups; zero
+                         // between launches (the kernel resets them)
+  uint32_t grid;         // workgroups (one wave each)
+};
+
+// True if (dtype, m, d/m) has a compiled kernel.
+bool supported(int dtype, uint32_t m, uint32_t dsub);
+
+// LDS bytes the search kernel needs for a worklist of L and an iteration cap.
+size_t search_lds_bytes(uint32_t m, uint32_t L, uint32_t iter_cap);
+
+// Resident workgroups per CU for the search kernel at this LDS size.
+hipError_t search_occupancy(const DeviceIndex& ix, size_t lds, int* per_cu);
+
+hipError_t launch_tables(const DeviceIndex& ix, const void* queries,
+                         uint64_t nq, float* out, hipStream_t s);
+hipError_t launch_search(const DeviceIndex& ix, const SearchLaunch& a,
+                         hipStream_t s);
+hipError_t launch_rerank(const DeviceIndex& ix, const void* queries,
+                         uint64_t nq, const uint32_t* cand, uint32_t c_max,
+                         uint32_t k, uint32_t* out_ids, float* out_dists,
+                         hipStream_t s);
+
+uint32_t pow2ceil(uint32_t x);
+
+}  // namespace bang

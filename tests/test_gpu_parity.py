@@ -1,0 +1,252 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the
+same seeded inputs.  The bar is bit-exact: ids, distances, the order of
+expanded nodes and the iteration counts must be identical, because both
+sides compute FP32 sums in the same fixed order with no fused
+multiply-add.  (The stated tolerance for distances is 1e-5 relative; the
+design reaches exact equality, which the tests require.)"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle.graph import build_graph
+from oracle.pq import pq_encode, train_pq
+from synth import store
+
+pytestmark = pytest.mark.gpu
+NONE = 0xFFFFFFFF
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a visible GPU")
+    import paper_2401_11324_amd as bang  # raises if the library is missing
+    bang.lib()
+
+
+def bang_mod():
+    import paper_2401_11324_amd as bang
+    return bang
+
+
+def make_index(w):
+    rs = synth.streams(w)
+    base, q = synth.base_and_queries(w)
+    cb = train_pq(base, w.m, w.kmeans_iters, rs["pq_init"])
+    codes = pq_encode(base, cb)
+    s = oracle.medoid(base)
+    perm = rs["vamana_order"].permutation(w.n).astype(np.uint32)
+    adj, _ = build_graph(base, w.R, w.L_build, w.alpha, perm, s)
+    return oracle.Index(base, adj, s, cb, codes), q
+
+
+SMALL = {
+    # (dtype, d, m): covers the three element types and d/m = 2 and 4
+    "f32-d32-m16": synth.small("f32", n=1500, d=32, nq=37, m=16, R=24,
+                               seed_index=110),
+    "u8-d64-m16": synth.small("u8", n=2000, d=64, nq=41, m=16, R=32,
+                              seed_index=111),
+    "i8-d96-m48": synth.small("i8", n=1200, d=96, nq=29, m=48, R=20,
+                              seed_index=112),
+    "u8-d128-m32": synth.small("u8", n=3000, d=128, nq=45, m=32, R=64,
+                               ncent=12, seed_index=113),
+}
+
+
+@pytest.fixture(scope="module")
+def small_indexes():
+    out = {}
+    for name, w in SMALL.items():
+        ix, q = make_index(w)
+        out[name] = (ix, q, bang_mod().Index(ix.base, ix.adj, ix.medoid,
+                                             ix.codebooks, ix.codes))
+    return out
+
+
+def to_dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def u32(t):
+    return t.cpu().numpy().view(np.uint32)
+
+
+def f32bits(a):
+    return np.ascontiguousarray(a, dtype=np.float32).view(np.uint32)
+
+
+def run_and_compare(ix, gi, q, k, L, c_max=0, iter_cap=0, label=""):
+    cap = iter_cap or oracle.iter_cap_for(L)
+    qt = to_dev(q)
+    ids, d, cand, cnt = gi.search(qt, k, L, c_max=c_max, iter_cap=iter_cap,
+                                  want_cand=cap, want_counters=True)
+    torch.cuda.synchronize()
+    ref = oracle.search(ix, q, k, L, c_max=c_max or None,
+                        iter_cap=iter_cap or None, want_cand=True)
+    ids, d, cand, cnt = u32(ids), d.cpu().numpy(), u32(cand), u32(cnt)
+    assert np.array_equal(cnt[:, 0], ref["iters"]), label
+    assert np.array_equal(cnt[:, 1], ref["status"]), label
+    assert np.array_equal(cand, ref["cand"]), label
+    assert np.array_equal(ids, ref["ids"]), label
+    assert np.array_equal(f32bits(d), f32bits(ref["dists"])), label
+    return ref
+
+
+# --------------------------------------------------------------------------
+# stage 1
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("name", list(SMALL))
+def test_tables_bit_exact(small_indexes, name):
+    ix, q, gi = small_indexes[name]
+    T = gi.build_pq_tables(to_dev(q))
+    torch.cuda.synchronize()
+    ref = oracle.pq_tables(q, ix.codebooks)
+    assert np.array_equal(f32bits(T.cpu().numpy()), f32bits(ref))
+
+
+# --------------------------------------------------------------------------
+# stages 1-3
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("name", list(SMALL))
+@pytest.mark.parametrize("k,L", [(1, 1), (10, 10), (10, 16), (5, 33),
+                                 (10, 64), (10, 100), (32, 256)])
+def test_search_bit_exact(small_indexes, name, k, L):
+    ix, q, gi = small_indexes[name]
+    run_and_compare(ix, gi, q, k, L, label=f"{name} k={k} L={L}")
+
+
+@pytest.mark.parametrize("name", ["u8-d128-m32", "f32-d32-m16"])
+def test_iteration_cap_and_candidate_cap(small_indexes, name):
+    """A query stopped by the iteration cap reports status 1; with more
+    expanded nodes than c_max only the c_max nearest by PQ key are
+    re-ranked.  Both sides apply the same caps."""
+    ix, q, gi = small_indexes[name]
+    ref = run_and_compare(ix, gi, q, 10, 64, iter_cap=20)
+    assert (ref["status"] == 1).all()
+    ref = run_and_compare(ix, gi, q, 10, 64, c_max=12)
+    assert (ref["iters"] > 12).all()
+
+
+def test_short_results_are_padded():
+    w = synth.small("u8", n=400, d=32, nq=5, m=16, seed_index=114)
+    base, q = synth.base_and_queries(w)
+    cb = train_pq(base, 16, 3, synth.streams(w)["pq_init"])
+    codes = pq_encode(base, cb)
+    adj = np.full((w.n, 8), NONE, dtype=np.uint32)
+    adj[3, :3] = [10, 20, 30]
+    adj[20, 0] = 3
+    ix = oracle.Index(base, adj, 3, cb, codes)
+    gi = bang_mod().Index(base, adj, 3, cb, codes)
+    ref = run_and_compare(ix, gi, q, 10, 16)
+    assert (ref["ids"][:, 4:] == NONE).all()
+
+
+def test_empty_batch_is_a_no_op(small_indexes):
+    ix, q, gi = small_indexes["u8-d64-m16"]
+    ids, d = gi.search(to_dev(q[:0]), 10, 32)
+    torch.cuda.synchronize()
+    assert ids.shape == (0, 10)
+
+
+def test_invalid_arguments_raise(small_indexes):
+    bang = bang_mod()
+    ix, q, gi = small_indexes["u8-d64-m16"]
+    qt = to_dev(q)
+    for k, L in [(0, 10), (11, 10), (10, 257)]:
+        with pytest.raises(bang.BangError):
+            gi.search(qt, k, L)
+    with pytest.raises(TypeError):
+        gi.search(qt.float(), 10, 32)
+
+
+def test_deterministic_and_independent_of_batch_order(small_indexes):
+    """Each query's result depends on that query alone: two runs agree bit
+    for bit, and permuting the batch permutes the results."""
+    ix, q, gi = small_indexes["u8-d128-m32"]
+    qt = to_dev(q)
+    a_ids, a_d = gi.search(qt, 10, 64)
+    b_ids, b_d = gi.search(qt, 10, 64)
+    a_ids, a_d = u32(a_ids), f32bits(a_d.cpu().numpy())
+    assert np.array_equal(a_ids, u32(b_ids))
+    assert np.array_equal(a_d, f32bits(b_d.cpu().numpy()))
+    perm = np.random.default_rng(0).permutation(len(q))
+    p_ids, p_d = gi.search(to_dev(q[perm]), 10, 64)
+    assert np.array_equal(u32(p_ids), a_ids[perm])
+    assert np.array_equal(f32bits(p_d.cpu().numpy()), a_d[perm])
+    one_ids, _ = gi.search(to_dev(q[5:6]), 10, 64)
+    assert np.array_equal(u32(one_ids)[0], a_ids[5])
+
+
+# --------------------------------------------------------------------------
+# stage 3 alone
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("name", list(SMALL))
+def test_rerank_bit_exact(small_indexes, name):
+    ix, q, gi = small_indexes[name]
+    rng = np.random.default_rng(3)
+    cm = 77
+    cand = np.full((len(q), cm), NONE, dtype=np.uint32)
+    for a in range(len(q)):
+        c = rng.choice(ix.n, cm - 7, replace=False)
+        cand[a, :cm - 7] = c
+    cand[1, :] = NONE                      # nothing to rank
+    cand[2, 3] = ix.n + 5                  # out of range: skipped
+    for k in (1, 10, 80):
+        ids, d = gi.rerank(to_dev(q), to_dev(cand.view(np.int32)), k)
+        torch.cuda.synchronize()
+        rid, rd = oracle.rerank(ix, q, cand, k)
+        assert np.array_equal(u32(ids), rid)
+        assert np.array_equal(f32bits(d.cpu().numpy()), f32bits(rd))
+
+
+# --------------------------------------------------------------------------
+# the benchmark's workloads
+# --------------------------------------------------------------------------
+def load_workload(name):
+    w = synth.WORKLOADS[name]
+    if not store.exists(w):
+        from oracle.build_index import build
+        build(w)
+    d = store.load(w)
+    ix = oracle.Index(d["base"], d["adj"], d["medoid"], d["codebooks"],
+                      d["codes"])
+    return w, ix, d
+
+
+def test_tiny_workload_bit_exact():
+    """10k float32 points, 100 queries, k=10, L=64: every query compared."""
+    w, ix, d = load_workload("tiny")
+    gi = bang_mod().Index(ix.base, ix.adj, ix.medoid, ix.codebooks, ix.codes)
+    for L in w.Ls:
+        run_and_compare(ix, gi, d["queries"], w.k, L, label=f"tiny L={L}")
+
+
+def test_sift1m_full_batch_sampled_bit_exact():
+    """1M uint8 points: the full 10,000-query batch runs in the launch
+    configuration the benchmark times; a seeded sample of queries is
+    recomputed one by one by the oracle and compared bit for bit."""
+    w, ix, d = load_workload("sift1m")
+    gi = bang_mod().Index(ix.base, ix.adj, ix.medoid, ix.codebooks, ix.codes)
+    q = d["queries"]
+    qt = to_dev(q)
+    sample = np.sort(np.random.default_rng(2024).choice(len(q), 160,
+                                                        replace=False))
+    for L in w.Ls:
+        cap = oracle.iter_cap_for(L)
+        ids, dist, cand, cnt = gi.search(qt, w.k, L, want_cand=cap,
+                                         want_counters=True)
+        torch.cuda.synchronize()
+        ref = oracle.search(ix, q[sample], w.k, L, want_cand=True)
+        assert np.array_equal(u32(cnt)[sample, 0], ref["iters"]), L
+        assert np.array_equal(u32(cand)[sample], ref["cand"]), L
+        assert np.array_equal(u32(ids)[sample], ref["ids"]), L
+        assert np.array_equal(f32bits(dist.cpu().numpy()[sample]),
+                              f32bits(ref["dists"])), L
+        # every query, not only the sample: results sorted, distinct
+        allids = u32(ids)
+        dd = dist.cpu().numpy()
+        assert (np.diff(dd, axis=1) >= 0).all()
+        assert all(len(set(r)) == len(r) for r in allids[:500])
