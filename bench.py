@@ -84,6 +84,22 @@ def cpu_baseline(idx_np, queries, k, L, budget_s=15.0):
                       f"{threads} threads"}
 
 
+def copy_probe(mib: int) -> int:
+    """A plain copy of `mib` MiB between two device buffers (reads and
+    writes exactly that many bytes); its FETCH_SIZE / WRITE_SIZE readings
+    turn the counters into bytes."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.arange(n, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_mib": mib, "bytes_each_way": n * 4,
+                      "dispatches": 3}), flush=True)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -93,7 +109,16 @@ def main(argv=None):
                     help="worklist size (default: chosen by the recall sweep)")
     ap.add_argument("--no-cpu", action="store_true",
                     help="skip the CPU oracle baseline")
+    ap.add_argument("--no-sweep", action="store_true",
+                    help="skip the recall sweep (needs --L)")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB mebibytes "
+                         "(calibrates the HBM byte counters) and exit")
     a = ap.parse_args(argv)
+    if a.copy_probe:
+        return copy_probe(a.copy_probe)
+    if a.no_sweep and not a.L:
+        ap.error("--no-sweep needs --L")
     if a.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {a.gpus} is not "
               "supported (queries are independent: see the sharding notes in "
@@ -122,7 +147,7 @@ def main(argv=None):
 
     # recall sweep (untimed apart from one launch each)
     sweep = []
-    for L in w.Ls:
+    for L in ([] if a.no_sweep else w.Ls):
         ids, dist = gi.search(q, k, L)
         torch.cuda.synchronize()
         t0 = torch.cuda.Event(enable_timing=True)
