@@ -19,7 +19,7 @@ struct bang_index {
   int device = 0;
   bang::DeviceIndex dev{};
   void* d_base = nullptr;
-  uint32_t* d_adj = nullptr;
+  unsigned char* d_rows = nullptr;
   uint8_t* d_codes = nullptr;
   float* d_cb = nullptr;
   // search workspace, grown on demand
@@ -106,7 +106,7 @@ int upload(T** dst, const void* src, size_t bytes, const char* what) {
 void free_index(bang_index* ix) {
   if (!ix) return;
   (void)hipFree(ix->d_base);
-  (void)hipFree(ix->d_adj);
+  (void)hipFree(ix->d_rows);
   (void)hipFree(ix->d_codes);
   (void)hipFree(ix->d_cb);
   (void)hipFree(ix->d_cscratch);
@@ -156,23 +156,43 @@ int create_impl(const bang_index_desc* d, bang_index** out) {
   }
   int rc;
   size_t nd = (size_t)d->n * d->d;
+  uint32_t* d_adj = nullptr;
   if ((rc = upload(&ix->d_base, d->base, nd * elem_size(d->dtype), "base")) ||
-      (rc = upload(&ix->d_adj, d->adj, (size_t)d->n * d->R * 4, "adjacency")) ||
+      (rc = upload(&d_adj, d->adj, (size_t)d->n * d->R * 4, "adjacency")) ||
       (rc = upload(&ix->d_codes, d->codes, (size_t)d->n * d->m, "codes")) ||
       (rc = upload(&ix->d_cb, d->codebooks, (size_t)d->m * 256 * (d->d / d->m) * 4,
                    "codebooks")) ||
       (rc = upload(&ix->d_qcounter, nullptr, 0, "counters"))) {
+    (void)hipFree(d_adj);
     free_index(ix);
     return rc;
   }
   // the two search counters start at zero; each launch leaves them at zero
   e = hipMemset(ix->d_qcounter, 0, 2 * sizeof(uint32_t));
+  // rows: each node's adjacency followed by its neighbours' codes, so one
+  // coalesced load per expansion brings both (layout in internal.h)
+  const size_t row_bytes = (size_t)d->n * bang::row_stride_bytes(d->R, d->m);
+  if (e == hipSuccess) {
+    e = hipMalloc(reinterpret_cast<void**>(&ix->d_rows), row_bytes);
+    if (e != hipSuccess) {
+      (void)hipFree(d_adj);
+      free_index(ix);
+      return fail(BANG_ENOMEM, std::string("hipMalloc for packed rows: ") +
+                                   hipGetErrorString(e));
+    }
+    e = hipMemset(ix->d_rows, 0, row_bytes);
+  }
+  if (e == hipSuccess)
+    e = bang::launch_pack(d_adj, ix->d_codes, (uint32_t)d->n, d->R, d->m,
+                          ix->d_rows, nullptr);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  (void)hipFree(d_adj);
   if (e != hipSuccess) {
     free_index(ix);
-    return hip_fail(e, "hipMemset");
+    return hip_fail(e, "packing adjacency rows");
   }
   ix->dev.base = ix->d_base;
-  ix->dev.adj = ix->d_adj;
+  ix->dev.rows = ix->d_rows;
   ix->dev.codes = ix->d_codes;
   ix->dev.cb = ix->d_cb;
   ix->dev.n = (uint32_t)d->n;

@@ -34,6 +34,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "internal.h"
 
 #pragma clang fp contract(off)
@@ -205,25 +207,51 @@ __device__ __forceinline__ uint64_t shfl64(uint64_t v, int src) {
   return ((uint64_t)hi << 32) | lo;
 }
 
-// Ascending bitonic sort of one key per lane across the wave.
-__device__ __forceinline__ uint64_t wave_sort(uint64_t x, int lane) {
-#pragma unroll
-  for (int size = 2; size <= kWave; size <<= 1) {
-#pragma unroll
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      uint64_t y = shfl_xor64(x, stride);
-      bool up = (lane & size) == 0;
-      bool lower = (lane & stride) == 0;
-      uint64_t mn = x < y ? x : y;
-      uint64_t mx = x < y ? y : x;
-      x = (lower == up) ? mn : mx;
-    }
-  }
-  return x;
+// Cross-lane helpers on DPP (data-parallel primitives; no LDS round trip).
+// dpp_ctrl encodings of the GFX9 family: row_shr:n = 0x110 + n,
+// row_bcast:15 = 0x142, row_bcast:31 = 0x143.
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ uint32_t dpp(uint32_t old, uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)v, CTRL,
+                                               ROW_MASK, 0xF, false);
+}
+
+// Exclusive prefix sum of one value per lane across the wave.
+__device__ __forceinline__ uint32_t wave_exclusive_scan(uint32_t x) {
+  uint32_t v = x;
+  v += dpp<0x111>(0u, v);  // row_shr:1
+  v += dpp<0x112>(0u, v);  // row_shr:2
+  v += dpp<0x114>(0u, v);  // row_shr:4
+  v += dpp<0x118>(0u, v);  // row_shr:8
+  v += dpp<0x142, 0xA>(0u, v);  // row_bcast:15 into rows 1 and 3
+  v += dpp<0x143, 0xC>(0u, v);  // row_bcast:31 into rows 2 and 3
+  return v - x;
+}
+
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ uint64_t min_dpp(uint64_t v) {
+  const uint32_t lo = dpp<CTRL, ROW_MASK>(0xFFFFFFFFu, (uint32_t)v);
+  const uint32_t hi = dpp<CTRL, ROW_MASK>(0xFFFFFFFFu, (uint32_t)(v >> 32));
+  const uint64_t t = ((uint64_t)hi << 32) | lo;
+  return t < v ? t : v;
+}
+
+// Minimum of one u64 per lane across the wave, returned to every lane.
+__device__ __forceinline__ uint64_t wave_min64(uint64_t v) {
+  v = min_dpp<0x111>(v);
+  v = min_dpp<0x112>(v);
+  v = min_dpp<0x114>(v);
+  v = min_dpp<0x118>(v);
+  v = min_dpp<0x142, 0xA>(v);
+  v = min_dpp<0x143, 0xC>(v);
+  const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, 63);
+  const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(v >> 32), 63);
+  return ((uint64_t)hi << 32) | lo;
 }
 
 // Number of entries of the sorted LDS list A[0..len) whose key, visited bit
-// ignored, is below x's (len <= 256).
+// ignored, is below x's (len <= 256).  Branch-free binary lifting: the
+// step sequence depends only on len, which is uniform across the wave.
 __device__ __forceinline__ uint32_t rank_in(const uint64_t* A, uint32_t len,
                                             uint64_t x) {
   const uint64_t xs = x >> 1;
@@ -278,13 +306,15 @@ __device__ void sort_and_emit(uint64_t* S, uint32_t cnt, uint32_t k,
 
 struct SearchArgs {
   const void* base;
-  const uint32_t* adj;
+  const unsigned char* rows;  // packed rows: ids, then the neighbours' codes
   const uint8_t* codes;
   const float* cb;
   const unsigned char* queries;
   uint64_t nq;
   uint32_t n, R, medoid;
+  uint32_t row_stride, row_ids;  // bytes per row; bytes of the id part
   uint32_t k, Lcap, c_max, iter_cap;
+  uint32_t lblock;   // worklist entries per lane, ceil(Lcap / 64) <= 4
   uint32_t region0;  // bytes of the table / re-rank region
   uint32_t* out_ids;
   float* out_dists;
@@ -296,18 +326,57 @@ struct SearchArgs {
   uint32_t* qcounter;
 };
 
+constexpr int kMaxBlock = 4;  // 64 lanes x 4 = the largest worklist, 256
+
+// Adjacency row of node u and, in the same row, the codes of its
+// neighbours: one coalesced load per lane, no dependent gather.
+template <int M>
+__device__ __forceinline__ void load_row(const SearchArgs& a, uint32_t u,
+                                         int lane, uint32_t& nb,
+                                         uint4 (&code)[M / 16]) {
+  const unsigned char* row = a.rows + (size_t)u * a.row_stride;
+  if ((uint32_t)lane < a.R) {
+    nb = reinterpret_cast<const uint32_t*>(row)[lane];
+    const uint4* c = reinterpret_cast<const uint4*>(row + a.row_ids + lane * M);
+#pragma unroll
+    for (int i = 0; i < M / 16; ++i) code[i] = c[i];
+  } else {
+    nb = kNone;
+  }
+}
+
+// ADC from codes already in registers: m table lookups, subspace order.
+template <int M>
+__device__ __forceinline__ float adc_regs(const float* T,
+                                          const uint4 (&v)[M / 16]) {
+  float acc = 0.0f;
+#pragma unroll
+  for (int c = 0; c < M / 16; ++c) {
+    const uint32_t w[4] = {v[c].x, v[c].y, v[c].z, v[c].w};
+#pragma unroll
+    for (int b = 0; b < 16; ++b) {
+      uint32_t byte = (w[b >> 2] >> (8 * (b & 3))) & 0xFFu;
+      acc = acc + T[(16 * c + b) * 256 + byte];
+    }
+  }
+  return acc;
+}
+
 template <int DT, int M, int DS>
 __global__ __launch_bounds__(kWave) void search_kernel(SearchArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int D = M * DS;
   const int lane = threadIdx.x;
+  const uint32_t B = a.lblock;
   float* T = reinterpret_cast<float*>(smem);
   uint64_t* S = reinterpret_cast<uint64_t*>(smem);
   uint64_t* Lb0 = reinterpret_cast<uint64_t*>(smem + a.region0);
-  uint64_t* Lb1 = Lb0 + a.Lcap;
-  uint64_t* Nb = Lb1 + a.Lcap;
+  uint64_t* Lb1 = Lb0 + kWave * B;
+  uint64_t* Nb = Lb1 + kWave * B;
+  uint32_t* H = reinterpret_cast<uint32_t*>(Nb + kWave);  // kWave*B + 1
   uint64_t* C = a.cscratch + (size_t)blockIdx.x * a.iter_cap;
-  const uint32_t R = a.R;
+
+  for (uint32_t t = lane; t <= kWave * B; t += kWave) H[t] = 0u;
 
   for (;;) {
     uint32_t qi = 0;
@@ -330,17 +399,19 @@ __global__ __launch_bounds__(kWave) void search_kernel(SearchArgs a) {
 
     // stage 1: the table (the previous query's re-rank is done with S)
     __syncthreads();
+    const uint32_t s = a.medoid;
+    uint32_t nb;
+    uint4 code[M / 16];
+    load_row<M>(a, s, lane, nb, code);  // in flight during the table build
     build_table<DT, M, DS>(q, a.cb, T, lane, kWave);
     __syncthreads();
 
     // stage 2: L = [(ADC(s), s)]
-    const uint32_t s = a.medoid;
     uint64_t curkey = make_key(adc<M>(T, a.codes + (size_t)s * M), s);
     uint64_t* Lc = Lb0;
     uint64_t* Ln = Lb1;
     if (lane == 0) Lc[0] = curkey;
     uint32_t Llen = 1, cur = 0, iters = 0, status = 0;
-    uint32_t nb = (uint32_t)lane < R ? a.adj[(size_t)s * R + lane] : kNone;
     __syncthreads();
 
     while (cur != kNone) {
@@ -355,73 +426,109 @@ __global__ __launch_bounds__(kWave) void search_kernel(SearchArgs a) {
       }
       ++iters;
 
-      // distances of the neighbours (nb holds adj(u*), requested earlier)
-      uint64_t key = kInf;
-      if (nb != kNone) key = make_key(adc<M>(T, a.codes + (size_t)nb * M), nb);
-      __syncthreads();
+      // this lane's block of the worklist, lane owns [lane*B, lane*B + B)
+      // (the buffer holds 64*B entries, so the read is in bounds even past
+      // Llen; such entries are masked to +inf)
+      uint64_t lk[kMaxBlock];
+#pragma unroll
+      for (int t = 0; t < kMaxBlock; ++t) {
+        const uint32_t j = lane * B + t;
+        lk[t] = ((uint32_t)t < B && j < Llen) ? Lc[j] : kInf;
+      }
 
-      // sort; drop nodes already in the worklist; rank in the worklist
-      key = wave_sort(key, lane);
+      // distances of the neighbours (row of u*, loaded earlier)
+      uint64_t key = kInf;
+      if (nb != kNone) key = make_key(adc_regs<M>(T, code), nb);
+
+      // rank in the worklist; a node already in it is dropped (set union)
       uint32_t r = 0;
       bool keep = false;
       if (key != kInf) {
         r = rank_in(Lc, Llen, key);
         keep = !(r < Llen && (Lc[r] >> 1) == (key >> 1));
       }
-      const uint64_t km = __ballot(keep);
-      const uint32_t nv = __popcll(km);
-      const uint32_t idx = __builtin_amdgcn_mbcnt_hi(
-          (uint32_t)(km >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)km, 0u));
-      if (keep) Nb[idx] = key;
-      __syncthreads();
+      const uint64_t kk = keep ? key : kInf;
 
-      // next node: best new key vs first unvisited worklist entry, each at
-      // its position in the merged list; beyond t means it is cut
+      // next node, decided before the merge: the smaller of the first
+      // unvisited worklist entry a and the best new key b.  a is never cut
+      // when it is the smaller; b is cut when its worklist rank reaches L,
+      // and then a is cut too.  Its merged position is a's index or b's rank.
+      uint32_t ja = kNone;
+#pragma unroll
+      for (int t = kMaxBlock - 1; t >= 0; --t) {
+        const uint32_t j = lane * B + t;
+        if (lk[t] != kInf && !(lk[t] & 1ull) && j != cur) ja = j;
+      }
+      const uint64_t am = __ballot(ja != kNone);
+      uint64_t akey = kInf;
+      uint32_t apos = kNone;
+      if (am) {
+        const int f = __ffsll((unsigned long long)am) - 1;
+        apos = __shfl(ja, f);
+        akey = Lc[apos];
+      }
+      const uint64_t bkey = wave_min64(kk);
       uint32_t best = kNone;
       uint64_t bestkey = kInf;
-      for (uint32_t j0 = 0; j0 < Llen; j0 += kWave) {
-        uint32_t j = j0 + lane;
-        uint64_t lk = j < Llen ? Lc[j] : kInf;
-        bool unv = j < Llen && !(lk & 1ull);
-        uint64_t um = __ballot(unv);
-        if (um) {
-          int f = __ffsll((unsigned long long)um) - 1;
-          uint64_t ak = shfl64(lk, f);
-          uint32_t apos = j0 + f + rank_in(Nb, nv, ak);
-          if (apos < a.Lcap) {
-            best = apos;
-            bestkey = ak;
-          }
-          break;
-        }
-      }
-      if (nv > 0) {
-        int f = __ffsll((unsigned long long)km) - 1;
-        uint32_t bpos = __shfl(r, f);
-        if (bpos < a.Lcap && bpos < best) {
+      if (bkey < akey) {
+        const uint64_t bl = __ballot(kk == bkey);
+        const uint32_t bpos = __shfl(r, __ffsll((unsigned long long)bl) - 1);
+        if (bpos < a.Lcap) {
           best = bpos;
-          bestkey = shfl64(key, f);
+          bestkey = bkey;
         }
+      } else if (akey != kInf) {
+        best = apos;
+        bestkey = akey;
       }
-      // request the next adjacency row now; it arrives during the merge
-      nb = (best != kNone && (uint32_t)lane < R)
-               ? a.adj[(size_t)key_id(bestkey) * R + lane]
-               : kNone;
+      // request the next row now; it arrives during the merge
+      if (best != kNone)
+        load_row<M>(a, key_id(bestkey), lane, nb, code);
+      else
+        nb = kNone;
+
+      Nb[lane] = kk;
+      if (keep) atomicAdd(&H[r], 1u);
+      const uint64_t km = __ballot(keep);
+      const uint32_t nv = __popcll(km);
+      __syncthreads();
+
+      // rank among the new keys (their count below mine)
+      uint32_t rn = 0;
+#pragma unroll 8
+      for (int j = 0; j < kWave; j += 2) {
+        const uint64_t x0 = Nb[j], x1 = Nb[j + 1];
+        rn += (x0 < kk) + (x1 < kk);
+      }
+
+      // new keys below worklist entry j = sum of H[0..j] (keys whose
+      // worklist rank is <= j)
+      uint32_t sh[kMaxBlock];
+      uint32_t tot = 0;
+#pragma unroll
+      for (int t = 0; t < kMaxBlock; ++t) {
+        const uint32_t j = lane * B + t;
+        if (lk[t] != kInf) tot += H[j];
+        sh[t] = tot;
+      }
+      const uint32_t excl = wave_exclusive_scan(tot);
 
       // merge: position = own index + rank in the other list
-      if (keep) {
-        uint32_t p = idx + r;
-        if (p < a.Lcap) Ln[p] = key;
+      if (keep && r + rn < a.Lcap) Ln[r + rn] = key;
+#pragma unroll
+      for (int t = 0; t < kMaxBlock; ++t) {
+        const uint32_t j = lane * B + t;
+        if (lk[t] != kInf) {
+          const uint32_t p = j + excl + sh[t];
+          if (p < a.Lcap) Ln[p] = j == cur ? (lk[t] | 1ull) : lk[t];
+        }
+        if ((uint32_t)t < B) H[j] = 0u;
       }
-      for (uint32_t j = lane; j < Llen; j += kWave) {
-        uint64_t lk = Lc[j];
-        uint32_t p = j + rank_in(Nb, nv, lk);
-        if (p < a.Lcap) Ln[p] = lk;
-      }
+      if (lane == 0) H[kWave * B] = 0u;
       Llen = min(a.Lcap, Llen + nv);
-      uint64_t* t = Lc;
+      uint64_t* tmp = Lc;
       Lc = Ln;
-      Ln = t;
+      Ln = tmp;
       cur = best;
       curkey = bestkey;
       __syncthreads();
@@ -464,6 +571,30 @@ __global__ __launch_bounds__(kWave) void search_kernel(SearchArgs a) {
     if (a.out_times && lane == 0) {
       a.out_times[qi * 2] = t_begin;
       a.out_times[qi * 2 + 1] = wall_clock64();
+    }
+  }
+}
+
+// Packed rows: row u = R neighbour ids (padded to row_ids bytes), then the
+// m code bytes of each neighbour slot (zero for an empty slot).
+__global__ __launch_bounds__(256) void pack_rows_kernel(
+    const uint32_t* __restrict__ adj, const uint8_t* __restrict__ codes,
+    uint32_t n, uint32_t R, uint32_t m, uint32_t row_ids, uint32_t stride,
+    unsigned char* __restrict__ out) {
+  const uint64_t total = (uint64_t)n * R;
+  for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+       t += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t u = t / R;
+    const uint32_t r = (uint32_t)(t % R);
+    const uint32_t id = adj[t];
+    unsigned char* row = out + u * stride;
+    reinterpret_cast<uint32_t*>(row)[r] = id;
+    uint4* dst = reinterpret_cast<uint4*>(row + row_ids + (size_t)r * m);
+    if (id != kNone) {
+      const uint4* src = reinterpret_cast<const uint4*>(codes + (size_t)id * m);
+      for (uint32_t i = 0; i < m / 16; ++i) dst[i] = src[i];
+    } else {
+      for (uint32_t i = 0; i < m / 16; ++i) dst[i] = make_uint4(0u, 0u, 0u, 0u);
     }
   }
 }
@@ -587,13 +718,36 @@ bool supported(int dtype, uint32_t m, uint32_t ds) {
   return false;
 }
 
-size_t search_lds_bytes(uint32_t m, uint32_t L, uint32_t iter_cap) {
+static uint32_t lblock_for(uint32_t L) { return (L + kWave - 1) / kWave; }
+
+static size_t region0_bytes(uint32_t m, uint32_t L, uint32_t iter_cap) {
   size_t table = (size_t)m * 256 * 4;
   // re-rank keys: all expanded nodes when they exceed c_max (at most
   // iter_cap), else at most c_max <= 4*L; both padded to a power of two
   size_t sort = (size_t)pow2ceil(iter_cap > 4 * L ? iter_cap : 4 * L) * 8;
-  size_t region0 = table > sort ? table : sort;
-  return region0 + (size_t)2 * L * 8 + (size_t)kWave * 8;
+  return table > sort ? table : sort;
+}
+
+size_t search_lds_bytes(uint32_t m, uint32_t L, uint32_t iter_cap) {
+  const size_t B = lblock_for(L);
+  const size_t hist = ((kWave * B + 1) * 4 + 15) / 16 * 16;
+  return region0_bytes(m, L, iter_cap) + 2 * kWave * B * 8 + kWave * 8 + hist;
+}
+
+uint32_t row_ids_bytes(uint32_t R) { return (4 * R + 15) / 16 * 16; }
+
+uint32_t row_stride_bytes(uint32_t R, uint32_t m) {
+  return (row_ids_bytes(R) + R * m + 15) / 16 * 16;
+}
+
+hipError_t launch_pack(const uint32_t* adj, const uint8_t* codes, uint32_t n,
+                       uint32_t R, uint32_t m, unsigned char* rows,
+                       hipStream_t s) {
+  const uint64_t total = (uint64_t)n * R;
+  const uint32_t grid = (uint32_t)std::min<uint64_t>((total + 255) / 256, 65536);
+  hipLaunchKernelGGL(pack_rows_kernel, dim3(grid), dim3(256), 0, s, adj, codes,
+                     n, R, m, row_ids_bytes(R), row_stride_bytes(R, m), rows);
+  return hipGetLastError();
 }
 
 hipError_t search_occupancy(const DeviceIndex& ix, size_t lds, int* per_cu) {
@@ -608,10 +762,10 @@ hipError_t launch_tables(const DeviceIndex& ix, const void* queries,
 
 hipError_t launch_search(const DeviceIndex& ix, const SearchLaunch& l,
                          hipStream_t s) {
-  size_t lds = search_lds_bytes(ix.m, l.L, l.iter_cap);
+  const size_t lds = search_lds_bytes(ix.m, l.L, l.iter_cap);
   SearchArgs a;
   a.base = ix.base;
-  a.adj = ix.adj;
+  a.rows = ix.rows;
   a.codes = ix.codes;
   a.cb = ix.cb;
   a.queries = (const unsigned char*)l.queries;
@@ -619,11 +773,14 @@ hipError_t launch_search(const DeviceIndex& ix, const SearchLaunch& l,
   a.n = ix.n;
   a.R = ix.R;
   a.medoid = ix.medoid;
+  a.row_stride = row_stride_bytes(ix.R, ix.m);
+  a.row_ids = row_ids_bytes(ix.R);
   a.k = l.k;
   a.Lcap = l.L;
   a.c_max = l.c_max;
   a.iter_cap = l.iter_cap;
-  a.region0 = (uint32_t)(lds - (size_t)2 * l.L * 8 - (size_t)kWave * 8);
+  a.lblock = lblock_for(l.L);
+  a.region0 = (uint32_t)region0_bytes(ix.m, l.L, l.iter_cap);
   a.out_ids = l.out_ids;
   a.out_dists = l.out_dists;
   a.out_cand = l.out_cand;

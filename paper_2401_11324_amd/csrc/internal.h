@@ -12,10 +12,10 @@ enum Dtype : int { kF32 = 0, kU8 = 1, kI8 = 2 };
 
 // Device copies of an index.
 struct DeviceIndex {
-  const void* base;      // [n][d]
-  const uint32_t* adj;   // [n][R]
-  const uint8_t* codes;  // [n][m]
-  const float* cb;       // [m][256][d/m]
+  const void* base;           // [n][d]
+  const unsigned char* rows;  // [n][row_stride_bytes]: ids, neighbour codes
+  const uint8_t* codes;       // [n][m]
+  const float* cb;            // [m][256][d/m]
   uint32_t n, d, R, m, medoid;
   int dtype;
 };
@@ -41,6 +41,13 @@ bool supported(int dtype, uint32_t m, uint32_t dsub);
 
 // LDS bytes the search kernel needs for a worklist of L and an iteration cap.
 size_t search_lds_bytes(uint32_t m, uint32_t L, uint32_t iter_cap);
+
+// Packed adjacency rows: R ids padded to row_ids_bytes, then R x m codes.
+uint32_t row_ids_bytes(uint32_t R);
+uint32_t row_stride_bytes(uint32_t R, uint32_t m);
+hipError_t launch_pack(const uint32_t* adj, const uint8_t* codes, uint32_t n,
+                       uint32_t R, uint32_t m, unsigned char* rows,
+                       hipStream_t s);
 
 // Resident workgroups per CU for the search kernel at this LDS size.
 hipError_t search_occupancy(const DeviceIndex& ix, size_t lds, int* per_cu);
