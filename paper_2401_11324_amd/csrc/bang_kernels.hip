@@ -372,8 +372,8 @@ __global__ __launch_bounds__(kWave) void search_kernel(SearchArgs a) {
   uint64_t* S = reinterpret_cast<uint64_t*>(smem);
   uint64_t* Lb0 = reinterpret_cast<uint64_t*>(smem + a.region0);
   uint64_t* Lb1 = Lb0 + kWave * B;
-  uint64_t* Nb = Lb1 + kWave * B;
-  uint32_t* H = reinterpret_cast<uint32_t*>(Nb + kWave);  // kWave*B + 1
+  uint64_t* Nb = Lb1 + kWave * B;                           // kWave + 4
+  uint32_t* H = reinterpret_cast<uint32_t*>(Nb + kWave + 4);  // kWave*B + 1
   uint64_t* C = a.cscratch + (size_t)blockIdx.x * a.iter_cap;
 
   for (uint32_t t = lane; t <= kWave * B; t += kWave) H[t] = 0u;
@@ -447,6 +447,9 @@ __global__ __launch_bounds__(kWave) void search_kernel(SearchArgs a) {
         r = rank_in(Lc, Llen, key);
         keep = !(r < Llen && (Lc[r] >> 1) == (key >> 1));
       }
+      // a key ranked past a full worklist is cut whatever the other new keys
+      // are: only the remaining ("live") keys take part in the merge
+      keep = keep && r < a.Lcap;
       const uint64_t kk = keep ? key : kInf;
 
       // next node, decided before the merge: the smaller of the first
@@ -487,18 +490,30 @@ __global__ __launch_bounds__(kWave) void search_kernel(SearchArgs a) {
       else
         nb = kNone;
 
-      Nb[lane] = kk;
-      if (keep) atomicAdd(&H[r], 1u);
       const uint64_t km = __ballot(keep);
       const uint32_t nv = __popcll(km);
+      if (nv == 0) {
+        // nothing enters the worklist: it keeps its order, u* is already
+        // marked, and the next node is the first unvisited entry
+        cur = best;
+        curkey = bestkey;
+        __syncthreads();
+        continue;
+      }
+      const uint32_t idx = __builtin_amdgcn_mbcnt_hi(
+          (uint32_t)(km >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)km, 0u));
+      if (keep) {
+        Nb[idx] = kk;  // the live keys, compacted
+        atomicAdd(&H[r], 1u);
+      }
+      if (lane < 4) Nb[nv + lane] = kInf;  // pad to a multiple of 4
       __syncthreads();
 
-      // rank among the new keys (their count below mine)
+      // rank among the live keys (their count below mine)
       uint32_t rn = 0;
-#pragma unroll 8
-      for (int j = 0; j < kWave; j += 2) {
-        const uint64_t x0 = Nb[j], x1 = Nb[j + 1];
-        rn += (x0 < kk) + (x1 < kk);
+      for (uint32_t j = 0; j < nv; j += 4) {
+        const uint64_t x0 = Nb[j], x1 = Nb[j + 1], x2 = Nb[j + 2], x3 = Nb[j + 3];
+        rn += (x0 < kk) + (x1 < kk) + (x2 < kk) + (x3 < kk);
       }
 
       // new keys below worklist entry j = sum of H[0..j] (keys whose
@@ -731,7 +746,8 @@ static size_t region0_bytes(uint32_t m, uint32_t L, uint32_t iter_cap) {
 size_t search_lds_bytes(uint32_t m, uint32_t L, uint32_t iter_cap) {
   const size_t B = lblock_for(L);
   const size_t hist = ((kWave * B + 1) * 4 + 15) / 16 * 16;
-  return region0_bytes(m, L, iter_cap) + 2 * kWave * B * 8 + kWave * 8 + hist;
+  return region0_bytes(m, L, iter_cap) + 2 * kWave * B * 8 + (kWave + 4) * 8 +
+         hist;
 }
 
 uint32_t row_ids_bytes(uint32_t R) { return (4 * R + 15) / 16 * 16; }
