@@ -54,7 +54,14 @@ def lib():
         L.or_adc.argtypes = [P, P, u32, P, u64, P]
         L.or_adc.restype = None
         L.or_search.argtypes = [P, P, u64, u32, u32, u32, u32, ctypes.c_int,
-                                P, P, P, P, P, u32, P, ctypes.c_int]
+                                ctypes.c_int, P, P, P, P, P, u32, P,
+                                ctypes.c_int]
+        L.or_quantize_tables.argtypes = [P, u64, u32, ctypes.c_int, P, P]
+        L.or_quantize_tables.restype = None
+        L.or_f32_to_f16.argtypes = [ctypes.c_float]
+        L.or_f32_to_f16.restype = ctypes.c_uint16
+        L.or_f16_to_f32.argtypes = [ctypes.c_uint16]
+        L.or_f16_to_f32.restype = ctypes.c_float
         L.or_search.restype = ctypes.c_int
         L.or_rerank.argtypes = [P, P, u64, P, u32, u32, P, P, ctypes.c_int]
         L.or_rerank.restype = ctypes.c_int
@@ -156,17 +163,41 @@ def adc(table: np.ndarray, codes: np.ndarray, ids: np.ndarray) -> np.ndarray:
     return out
 
 
+TABLES = {"f32": 0, "f16": 1, "u8": 2}
+
+
 def iter_cap_for(L: int) -> int:
-    """Safety cap on iterations per query, identical on both sides."""
-    return 10 * L + 100
+    """Safety cap on iterations per query, identical on both sides: far
+    above the iteration counts of the paper's worklist-size table (I <= 3.1
+    t) and of the workloads here (I ~ 1.2 L)."""
+    return max(4 * L, L + 64)
+
+
+def quantize_tables(T: np.ndarray, table: str):
+    """Reduced-precision storage of canonical FP32 tables [nq][m][256]:
+    'f16' -> uint16 half bit patterns, 'u8' -> uint8 (see oracle.c)."""
+    T = np.ascontiguousarray(T, dtype=np.float32)
+    nq, m, _ = T.shape
+    nul = ctypes.c_void_p(0)
+    if table == "f16":
+        out = np.empty(T.shape, dtype=np.uint16)
+        lib().or_quantize_tables(_p(T), nq, m, 1, _p(out), nul)
+    elif table == "u8":
+        out = np.empty(T.shape, dtype=np.uint8)
+        lib().or_quantize_tables(_p(T), nq, m, 2, nul, _p(out))
+    else:
+        raise ValueError(table)
+    return out
 
 
 def search(index: Index, queries: np.ndarray, k: int, L: int,
            c_max: int | None = None, iter_cap: int | None = None,
            mode: int = 0, want_pq: bool = False, want_cand: bool = False,
-           nthreads: int = 0):
+           table: str = "f32", nthreads: int = 0):
     """Stages 1-3 for a batch (Algorithms 1 and 2, sections on the PQ
-    table, re-ranking).  Returns a dict with ids, dists and, on request,
+    table, re-ranking).  `table` picks the table storage the search ranks
+    by: "f32" (canonical), "f16" or "u8" (the precision form, oracle.c).
+    Returns a dict with ids, dists and, on request,
     pq_ids/pq_dists (Algorithm 1's own top-k), cand (expanded nodes in
     expansion order, NONE padded) and counters [I, status, added]."""
     q = np.ascontiguousarray(queries, dtype=index.base.dtype)
@@ -181,7 +212,8 @@ def search(index: Index, queries: np.ndarray, k: int, L: int,
     counters = np.empty((nq, 4), dtype=np.uint32)
     nul = ctypes.c_void_p(0)
     rc = lib().or_search(
-        index.cptr, _p(q), nq, k, L, c_max, iter_cap, mode, _p(ids),
+        index.cptr, _p(q), nq, k, L, c_max, iter_cap, mode, TABLES[table],
+        _p(ids),
         _p(dists), _p(pq_ids) if want_pq else nul,
         _p(pq_d) if want_pq else nul, _p(cand) if want_cand else nul,
         iter_cap, _p(counters), nthreads or default_threads())

@@ -112,6 +112,132 @@ static float adc_one(const float* T, const uint8_t* code, uint32_t m) {
   return acc;
 }
 
+/* ------------------------------------------------------------------------
+ * Reduced-precision table storage (the precision form).  Both forms are
+ * derived from the canonical FP32 table of the query, so they are fully
+ * determined by it:
+ *  - F16: every entry times a power-of-two scale 2^-k (the smallest k >= 0
+ *    that brings the largest entry to <= 65504, the largest half value),
+ *    rounded to the nearest half-precision value, ties to even.  ADC sums
+ *    the half values, widened to FP32, left to right in FP32.
+ *  - U8: per subspace j the offset lo_j = min_c T[j][c]; one scale for the
+ *    query, inv = 255 / max_j (max_c T[j][c] - lo_j) in FP32 (0 if every
+ *    range is 0); entry = rint((T[j][c] - lo_j) * inv), ties to even, in
+ *    [0, 255].  ADC is the exact integer sum of the m entries; the constant
+ *    sum of the offsets and the common scale do not change any order, so
+ *    the sum itself (converted to FP32, exact below 2^24) is the distance
+ *    the search ranks by.
+ * ---------------------------------------------------------------------- */
+#define OR_TABLE_F32 0
+#define OR_TABLE_F16 1
+#define OR_TABLE_U8 2
+
+/* FP32 -> IEEE half, round to nearest, ties to even (finite inputs). */
+uint16_t or_f32_to_f16(float f) {
+  uint32_t x;
+  memcpy(&x, &f, 4);
+  uint32_t sign = (x >> 16) & 0x8000u;
+  uint32_t ax = x & 0x7FFFFFFFu;
+  if (ax >= 0x477FF000u) return (uint16_t)(sign | 0x7C00u); /* >= 65520: inf */
+  if (ax >= 0x38800000u) {                                   /* half normal */
+    uint32_t h = ((((ax >> 23) - 127 + 15) << 10) | ((ax >> 13) & 0x3FFu));
+    uint32_t rem = ax & 0x1FFFu;
+    if (rem > 0x1000u || (rem == 0x1000u && (h & 1u))) ++h;
+    return (uint16_t)(sign | h);
+  }
+  /* half subnormal: units of 2^-24, rounded to nearest even (exact in
+   * double: the scaled value has at most 24 significant bits) */
+  double q = (double)fabsf(f) * 16777216.0;
+  double n = rint(q);
+  return (uint16_t)(sign | (uint32_t)n);
+}
+
+float or_f16_to_f32(uint16_t h) {
+  uint32_t sign = (uint32_t)(h & 0x8000u) << 16;
+  uint32_t e = (h >> 10) & 0x1Fu, mant = h & 0x3FFu;
+  float v;
+  if (e == 0)
+    v = (float)mant * 5.9604644775390625e-8f; /* mant * 2^-24, exact */
+  else if (e == 31)
+    v = mant ? NAN : INFINITY;
+  else {
+    uint32_t b = ((e - 15 + 127) << 23) | (mant << 13);
+    memcpy(&v, &b, 4);
+  }
+  uint32_t vb;
+  memcpy(&vb, &v, 4);
+  vb |= sign;
+  memcpy(&v, &vb, 4);
+  return v;
+}
+
+typedef struct {
+  int mode;
+  uint32_t m;
+  const float* T32; /* canonical table (always built) */
+  uint16_t* T16;
+  uint8_t* T8;
+} qtable;
+
+static void quantize_table(qtable* t) {
+  uint64_t ne = (uint64_t)t->m * 256;
+  if (t->mode == OR_TABLE_F16) {
+    float mx = 0.0f;
+    for (uint64_t i = 0; i < ne; ++i)
+      if (t->T32[i] > mx) mx = t->T32[i];
+    float s = 1.0f;
+    while (mx * s > 65504.0f) s = s * 0.5f;
+    for (uint64_t i = 0; i < ne; ++i) t->T16[i] = or_f32_to_f16(t->T32[i] * s);
+  } else if (t->mode == OR_TABLE_U8) {
+    float R = 0.0f;
+    for (uint32_t j = 0; j < t->m; ++j) {
+      float lo = t->T32[(uint64_t)j * 256], hi = lo;
+      for (uint32_t c = 1; c < 256; ++c) {
+        float v = t->T32[(uint64_t)j * 256 + c];
+        if (v < lo) lo = v;
+        if (v > hi) hi = v;
+      }
+      float range = hi - lo;
+      if (range > R) R = range;
+    }
+    float inv = R > 0.0f ? 255.0f / R : 0.0f;
+    for (uint32_t j = 0; j < t->m; ++j) {
+      float lo = t->T32[(uint64_t)j * 256];
+      for (uint32_t c = 1; c < 256; ++c)
+        if (t->T32[(uint64_t)j * 256 + c] < lo) lo = t->T32[(uint64_t)j * 256 + c];
+      for (uint32_t c = 0; c < 256; ++c) {
+        float diff = t->T32[(uint64_t)j * 256 + c] - lo;
+        float v = rintf(diff * inv);
+        t->T8[(uint64_t)j * 256 + c] = (uint8_t)(v > 255.0f ? 255.0f : v);
+      }
+    }
+  }
+}
+
+/* Distance the search ranks by, for the table's storage form. */
+static float adc_q(const qtable* t, const uint8_t* code) {
+  if (t->mode == OR_TABLE_F32) return adc_one(t->T32, code, t->m);
+  if (t->mode == OR_TABLE_F16) {
+    float acc = 0.0f;
+    for (uint32_t j = 0; j < t->m; ++j)
+      acc = acc + or_f16_to_f32(t->T16[(uint64_t)j * 256 + code[j]]);
+    return acc;
+  }
+  uint32_t acc = 0;
+  for (uint32_t j = 0; j < t->m; ++j) acc += t->T8[(uint64_t)j * 256 + code[j]];
+  return (float)acc;
+}
+
+/* Quantised tables of a batch (for tests): out16 [nq][m][256] or out8. */
+void or_quantize_tables(const float* T, uint64_t nq, uint32_t m, int mode,
+                        uint16_t* out16, uint8_t* out8) {
+  for (uint64_t q = 0; q < nq; ++q) {
+    qtable t = {mode, m, T + q * m * 256, out16 ? out16 + q * m * 256 : NULL,
+                out8 ? out8 + q * m * 256 : NULL};
+    quantize_table(&t);
+  }
+}
+
 void or_adc(const float* T, const uint8_t* codes, uint32_t m,
             const uint32_t* ids, uint64_t cnt, float* out) {
   for (uint64_t i = 0; i < cnt; ++i)
@@ -187,14 +313,14 @@ typedef struct {
  * On return C[0..iters) holds the expanded nodes with their PQ distances in
  * expansion order, and Lout[0..*Llen) the final worklist.
  */
-static void greedy_search(const or_index* ix, const float* T, uint32_t Lcap,
+static void greedy_search(const or_index* ix, const qtable* T, uint32_t Lcap,
                           uint32_t iter_cap, int mode, uint32_t* seen,
                           uint32_t stamp, entry* L, uint32_t* Llen, entry* C,
                           entry* scratch, or_counters* cnt) {
   uint32_t R = ix->R, m = ix->m;
   uint32_t s = ix->medoid;
   uint32_t len = 1;
-  L[0].dist = adc_one(T, ix->codes + (uint64_t)s * m, m);
+  L[0].dist = adc_q(T, ix->codes + (uint64_t)s * m);
   L[0].id = s;
   L[0].visited = 0;
   if (mode == 1) seen[s] = stamp;
@@ -230,7 +356,7 @@ static void greedy_search(const or_index* ix, const float* T, uint32_t Lcap,
             break;
           }
         if (present) continue;
-        L[len].dist = adc_one(T, ix->codes + (uint64_t)x * m, m);
+        L[len].dist = adc_q(T, ix->codes + (uint64_t)x * m);
         L[len].id = x;
         L[len].visited = 0;
         ++len;
@@ -246,7 +372,7 @@ static void greedy_search(const or_index* ix, const float* T, uint32_t Lcap,
         uint32_t x = nb[r];
         if (x == OR_NONE || seen[x] == stamp) continue;
         seen[x] = stamp;
-        scratch[np].dist = adc_one(T, ix->codes + (uint64_t)x * m, m);
+        scratch[np].dist = adc_q(T, ix->codes + (uint64_t)x * m);
         scratch[np].id = x;
         scratch[np].visited = 0;
         ++np;
@@ -309,6 +435,7 @@ static size_t dt_size(int dt) {
  */
 int or_search(const or_index* ix, const void* queries, uint64_t nq, uint32_t k,
               uint32_t Lcap, uint32_t c_max, uint32_t iter_cap, int mode,
+              int table_mode,
               uint32_t* ids, float* dists, uint32_t* pq_ids, float* pq_dists,
               uint32_t* cand, uint32_t cand_cap, uint32_t* counters,
               int nthreads) {
@@ -318,12 +445,14 @@ int or_search(const or_index* ix, const void* queries, uint64_t nq, uint32_t k,
 #pragma omp parallel num_threads(nthreads)
   {
     float* T = (float*)malloc((size_t)ix->m * 256 * sizeof(float));
+    uint16_t* T16 = (uint16_t*)malloc((size_t)ix->m * 256 * sizeof(uint16_t));
+    uint8_t* T8 = (uint8_t*)malloc((size_t)ix->m * 256);
     entry* L = (entry*)malloc((size_t)(Lcap + ix->R) * sizeof(entry));
     entry* C = (entry*)malloc((size_t)(iter_cap + 1) * sizeof(entry));
     entry* scr = (entry*)malloc((size_t)(2 * ix->R + Lcap) * sizeof(entry));
     uint32_t* seen = (uint32_t*)calloc(ix->n, sizeof(uint32_t));
     uint32_t stamp = 0;
-    if (!T || !L || !C || !scr || !seen) {
+    if (!T || !T16 || !T8 || !L || !C || !scr || !seen) {
 #pragma omp atomic write
       bad = 1;
     } else {
@@ -331,10 +460,12 @@ int or_search(const or_index* ix, const void* queries, uint64_t nq, uint32_t k,
       for (qi = 0; qi < (int64_t)nq; ++qi) {
         const char* q = (const char*)queries + (size_t)qi * ix->d * dt_size(ix->dtype);
         pq_table_one(q, ix->dtype, ix->d, ix->codebooks, ix->m, T);
+        qtable qt = {table_mode, ix->m, T, T16, T8};
+        quantize_table(&qt);
         or_counters cn;
         uint32_t Llen;
         ++stamp;
-        greedy_search(ix, T, Lcap, iter_cap, mode, seen, stamp, L, &Llen, C,
+        greedy_search(ix, &qt, Lcap, iter_cap, mode, seen, stamp, L, &Llen, C,
                       scr, &cn);
         if (pq_ids)
           for (uint32_t i = 0; i < k; ++i) {
@@ -355,6 +486,8 @@ int or_search(const or_index* ix, const void* queries, uint64_t nq, uint32_t k,
       }
     }
     free(T);
+    free(T16);
+    free(T8);
     free(L);
     free(C);
     free(scr);

@@ -375,3 +375,101 @@ def test_plain_vamana_degree_bound_and_prune_rule():
     # determinism across thread counts
     adj1 = oracle.vamana_build(base, 12, 24, 1.2, perm, s, nthreads=1)
     assert np.array_equal(adj, adj1)
+
+
+# --------------------------------------------------------------------------
+# Precision form: reduced-precision table storage
+# --------------------------------------------------------------------------
+def test_f16_conversion_matches_numpy_round_to_nearest_even():
+    """The oracle's FP32 -> half conversion is IEEE round-to-nearest-even,
+    as numpy's float16 cast is: checked on random values, exact ties, the
+    subnormal range and the top of the finite range."""
+    rng = np.random.default_rng(1)
+    v = np.concatenate([
+        rng.uniform(0, 65504, 20000), rng.uniform(0, 1, 5000),
+        rng.uniform(0, 2 ** -14, 5000),                 # subnormal halves
+        np.float32(1 + np.arange(64) * 2 ** -11 + 2 ** -12),  # exact ties
+        [0.0, 65504.0, 65519.0, 2 ** -24, 2 ** -25, 3 * 2 ** -26]]
+    ).astype(np.float32)
+    L = oracle.lib()
+    got = np.array([L.or_f32_to_f16(float(x)) for x in v], dtype=np.uint16)
+    assert np.array_equal(got, v.astype(np.float16).view(np.uint16))
+    back = np.array([L.or_f16_to_f32(int(h)) for h in got], dtype=np.float32)
+    assert np.array_equal(back, got.view(np.float16).astype(np.float32))
+
+
+def _u8_tables(w):
+    ix, q, _ = w
+    T = oracle.pq_tables(q, ix.codebooks)
+    return ix, q, T
+
+
+def test_f16_table_error_bound(small_u8):
+    """Half storage with a power-of-two scale: each entry is the FP32 entry
+    times 2^-k rounded to half, so its relative error is at most 2^-11
+    (plus the FP32 entry's own rounding), and the largest entry fits."""
+    ix, q, T = _u8_tables(small_u8)
+    H = oracle.quantize_tables(T, "f16").view(np.float16).astype(np.float64)
+    for a in range(len(q)):
+        mx = T[a].max()
+        k = 0
+        while mx * 2.0 ** -k > 65504:
+            k += 1
+        assert np.isfinite(H[a]).all()
+        np.testing.assert_allclose(H[a] * 2.0 ** k, T[a], rtol=2 ** -11,
+                                   atol=2.0 ** (k - 24))
+
+
+def test_u8_table_error_bound_and_range(small_u8):
+    """u8 storage: each subspace's minimum maps to 0, the widest subspace
+    spans 0..255, and lo_j + code / inv is within half a step (plus FP32
+    rounding) of the FP32 entry."""
+    ix, q, T = _u8_tables(small_u8)
+    U = oracle.quantize_tables(T, "u8").astype(np.float64)
+    for a in range(len(q)):
+        t = T[a].astype(np.float64)
+        lo = t.min(1, keepdims=True)
+        R = (T[a].max(1) - T[a].min(1)).max()
+        step = R / 255.0
+        assert (U[a].min(1) == 0).all() and U[a].max() == 255
+        err = np.abs(lo + U[a] * step - t)
+        assert err.max() <= 0.5 * step * (1 + 1e-5) + 1e-6 * t.max()
+
+
+@pytest.mark.parametrize("table", ["f16", "u8"])
+@pytest.mark.parametrize("fx", ["small_f32", "small_u8"])
+def test_precision_form_L_at_least_n_is_brute_force(fx, table, request):
+    """Whatever the table storage, t >= n on a connected graph expands every
+    node, so the exact re-rank returns the brute-force k nearest."""
+    ix, q, _ = request.getfixturevalue(fx)
+    out = oracle.search(ix, q[:4], 10, ix.n, c_max=ix.n, iter_cap=ix.n + 1,
+                        table=table)
+    assert (out["iters"] == ix.n).all()
+    allid = np.arange(ix.n)
+    for a in range(4):
+        ex = exact_sq(ix.base, q[a])
+        assert out["ids"][a].tolist() == np.lexsort((allid, ex))[:10].tolist()
+
+
+@pytest.mark.parametrize("table", ["f16", "u8"])
+def test_precision_form_algorithm1_equals_filtered_form(small_u8, table):
+    ix, q, _ = small_u8
+    a = oracle.search(ix, q, 10, 33, mode=0, table=table, want_cand=True)
+    b = oracle.search(ix, q, 10, 33, mode=1, table=table, want_cand=True)
+    for key in ("ids", "dists", "cand", "iters"):
+        assert np.array_equal(a[key], b[key]), key
+
+
+def test_precision_form_ranks_by_quantised_adc(small_u8):
+    """The PQ answer of Algorithm 1 under u8 storage is ordered by the
+    integer sum of the quantised entries (ties by id)."""
+    ix, q, _ = small_u8
+    T = oracle.pq_tables(q, ix.codebooks)
+    U = oracle.quantize_tables(T, "u8").astype(np.int64)
+    out = oracle.search(ix, q, 10, 32, table="u8", want_pq=True)
+    for a in range(len(q)):
+        ids = out["pq_ids"][a]
+        s = U[a][np.arange(ix.m)[None, :], ix.codes[ids]].sum(1)
+        assert np.array_equal(out["pq_dists"][a], s.astype(np.float32))
+        keys = list(zip(s.tolist(), ids.tolist()))
+        assert keys == sorted(keys)
