@@ -75,7 +75,7 @@ typedef struct {
   uint32_t c_max;           /* re-rank candidates kept (0 = 4*L): when more
                                nodes were expanded, the c_max smallest by
                                (PQ distance, id) are re-ranked */
-  uint32_t iter_cap;        /* iterations per query (0 = 10*L + 100); a
+  uint32_t iter_cap;        /* iterations per query (0 = max(4L, L + 64)); a
                                query that hits it stops and reports status 1 */
   uint32_t* out_cand;       /* device [nq][cand_stride]: expanded node ids in
                                expansion order, BANG_NONE padded */
@@ -85,7 +85,23 @@ typedef struct {
                                the query's work began and when its results
                                were written (hipDeviceAttributeWallClockRate
                                gives the tick rate in kHz) */
+  uint32_t table;           /* storage of the PQ table the search ranks by:
+                               BANG_TABLE_F32 (default), or the precision
+                               form's BANG_TABLE_F16 / BANG_TABLE_U8 */
 } bang_search_opts;
+
+/* Table storage forms.  Both reduced forms are computed from the FP32
+ * entries of the PQ table section, so they are deterministic:
+ *  - F16: entry * 2^-k rounded to half (nearest, ties to even), k >= 0 the
+ *    smallest that keeps the largest entry <= 65504; ADC = FP32 sum of the
+ *    widened halves in subspace order.
+ *  - U8: per subspace j, lo_j = min_c T[j][c]; inv = 255 / max_j range_j
+ *    (FP32); entry = rint((T[j][c] - lo_j) * inv) in [0, 255]; ADC = exact
+ *    integer sum of the m entries, ranked as FP32.
+ * The re-rank stays exact in every form. */
+#define BANG_TABLE_F32 0u
+#define BANG_TABLE_F16 1u
+#define BANG_TABLE_U8 2u
 
 /* Build an index on the current HIP device: validates the description
  * (ids in range, no duplicate ids in a row, m | d, supported (m, d/m,

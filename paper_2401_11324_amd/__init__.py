@@ -21,6 +21,7 @@ BANG_NONE = 0xFFFFFFFF
 MAX_L = 256
 MAX_R = 64
 DTYPES = {"f32": 0, "u8": 1, "i8": 2}
+TABLES = {"f32": 0, "f16": 1, "u8": 2}
 ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EUNSUPPORTED",
           -5: "EABORTED"}
 EXPORTS = ("bang_index_create", "bang_index_destroy", "bang_build_pq_tables",
@@ -46,7 +47,8 @@ class SearchOpts(ctypes.Structure):
     _fields_ = [("c_max", ctypes.c_uint32), ("iter_cap", ctypes.c_uint32),
                 ("out_cand", ctypes.c_void_p), ("cand_stride", ctypes.c_uint32),
                 ("out_counters", ctypes.c_void_p),
-                ("out_times", ctypes.c_void_p)]
+                ("out_times", ctypes.c_void_p),
+                ("table", ctypes.c_uint32)]
 
 
 _lib = None
@@ -164,9 +166,12 @@ class Index:
 
     def search(self, q, k: int, L: int, c_max: int = 0, iter_cap: int = 0,
                want_cand: int = 0, want_counters: bool = False,
-               want_times: bool = False, out=None, stream=None):
+               want_times: bool = False, table: str = "f32", out=None,
+               stream=None):
         """Stages 1-3.  Returns (ids uint32-as-int32 [nq][k], dists
         float32 [nq][k]) and, on request, the expanded nodes [nq][want_cand]
+        `table` is the PQ table storage the search ranks by: "f32", or the
+        precision form's "f16" / "u8".
         and counters [nq][4] (iterations, status) and device wall-clock
         ticks [nq][2] (begin, end)."""
         import torch
@@ -177,7 +182,7 @@ class Index:
             dists = torch.empty((nq, k), dtype=torch.float32, device=q.device)
         else:
             ids, dists = out
-        opts = SearchOpts(c_max, iter_cap, None, 0, None, None)
+        opts = SearchOpts(c_max, iter_cap, None, 0, None, None, TABLES[table])
         cand = cnt = times = None
         if want_cand:
             cand = torch.empty((nq, want_cand), dtype=torch.int32,

@@ -228,12 +228,14 @@ int search_impl(bang_index* ix, const void* queries, uint64_t nq, uint32_t k,
   if (!aligned(out_ids, 4) || !aligned(out_dists, 4))
     return fail(BANG_EINVAL, "outputs not 4-byte aligned");
   uint32_t c_max = (o && o->c_max) ? o->c_max : 4 * L;
-  uint32_t iter_cap = (o && o->iter_cap) ? o->iter_cap : 10 * L + 100;
+  uint32_t iter_cap = (o && o->iter_cap) ? o->iter_cap : std::max(4 * L, L + 64);
+  const uint32_t table = o ? o->table : BANG_TABLE_F32;
+  if (table > BANG_TABLE_U8) return fail(BANG_EINVAL, "unknown table form");
   if (iter_cap > 16384) return fail(BANG_EINVAL, "iter_cap > 16384");
   if (o && o->out_cand && o->cand_stride == 0)
     return fail(BANG_EINVAL, "cand_stride must be > 0 with out_cand");
 
-  size_t lds = bang::search_lds_bytes(ix->dev.m, L, iter_cap);
+  size_t lds = bang::search_lds_bytes(ix->dev.m, L, iter_cap, (int)table);
   if (lds > 64 * 1024)
     return fail(BANG_EUNSUPPORTED,
                 "table + worklist + re-rank keys exceed 64 KB of LDS "
@@ -241,7 +243,7 @@ int search_impl(bang_index* ix, const void* queries, uint64_t nq, uint32_t k,
   int per_cu = 0;
   hipError_t e = hipSetDevice(ix->device);
   if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
-  e = bang::search_occupancy(ix->dev, lds, &per_cu);
+  e = bang::search_occupancy(ix->dev, (int)table, lds, &per_cu);
   if (e != hipSuccess) return hip_fail(e, "occupancy query");
   if (per_cu < 1) return fail(BANG_EUNSUPPORTED, "search kernel cannot be resident");
   uint64_t grid = (uint64_t)per_cu * ix->num_cus;
@@ -269,6 +271,7 @@ int search_impl(bang_index* ix, const void* queries, uint64_t nq, uint32_t k,
   l.L = L;
   l.c_max = c_max;
   l.iter_cap = iter_cap;
+  l.table = (int)table;
   l.out_ids = out_ids;
   l.out_dists = out_dists;
   l.out_cand = o ? o->out_cand : nullptr;

@@ -149,6 +149,137 @@ __device__ __forceinline__ float adc(const float* T,
   return acc;
 }
 
+// Table storage of the search: canonical FP32, or the precision form's
+// half (times a power-of-two scale) or u8 (per-subspace offset, one scale).
+// Both reduced forms are derived from the canonical FP32 entries, so they
+// are as deterministic as the FP32 table itself.
+enum TableKind : int { kTabF32 = 0, kTabF16 = 1, kTabU8 = 2 };
+
+template <int TT>
+struct Tab;
+template <>
+struct Tab<kTabF32> {
+  using E = float;
+};
+template <>
+struct Tab<kTabF16> {
+  using E = uint16_t;
+};
+template <>
+struct Tab<kTabU8> {
+  using E = uint8_t;
+};
+
+__device__ __forceinline__ float f16_bits_to_f32(uint16_t h) {
+  return (float)__builtin_bit_cast(_Float16, h);
+}
+
+// Maximum / minimum of one float per lane across the wave (DPP), returned
+// to every lane.  `ident` is the identity for lanes outside a row.
+template <bool MAX>
+__device__ __forceinline__ float wave_minmax(float v, float ident) {
+  const uint32_t id = __float_as_uint(ident);
+#define BANG_MM(CTRL, RM)                                                    \
+  {                                                                          \
+    float t = __uint_as_float((uint32_t)__builtin_amdgcn_update_dpp(         \
+        (int)id, (int)__float_as_uint(v), CTRL, RM, 0xF, false));            \
+    v = MAX ? (t > v ? t : v) : (t < v ? t : v);                             \
+  }
+  BANG_MM(0x111, 0xF) BANG_MM(0x112, 0xF) BANG_MM(0x114, 0xF)
+  BANG_MM(0x118, 0xF) BANG_MM(0x142, 0xA) BANG_MM(0x143, 0xC)
+#undef BANG_MM
+  return __uint_as_float(
+      __builtin_amdgcn_readlane(__float_as_uint(v), 63));
+}
+
+// The query's table in LDS, in the storage form TT (one wave, 64 lanes).
+// lo (U8 only): m floats of LDS for the per-subspace offsets.
+template <int DT, int M, int DS, int TT>
+__device__ __forceinline__ void build_table_q(const unsigned char* q,
+                                              const float* __restrict__ cb,
+                                              void* Tv, float* lo, int lane) {
+  if constexpr (TT == kTabF32) {
+    build_table<DT, M, DS>(q, cb, reinterpret_cast<float*>(Tv), lane, kWave);
+  } else {
+    // pass 1: the statistics the storage needs
+    float mx = 0.0f;  // F16: largest entry; U8: widest subspace range
+    for (int j = 0; j < M; ++j) {
+      float qv[DS];
+#pragma unroll
+      for (int t = 0; t < DS; ++t) qv[t] = Elem<DT>::f(q, j * DS + t);
+      float vmin = __uint_as_float(0x7F800000u), vmax = 0.0f;
+#pragma unroll
+      for (int r = 0; r < 256 / kWave; ++r) {
+        const int c = lane + kWave * r;
+        const float e = table_entry<DS>(qv, cb + ((size_t)j * 256 + c) * DS);
+        vmin = e < vmin ? e : vmin;
+        vmax = e > vmax ? e : vmax;
+      }
+      if constexpr (TT == kTabF16) {
+        mx = vmax > mx ? vmax : mx;
+      } else {
+        const float l = wave_minmax<false>(vmin, __uint_as_float(0x7F800000u));
+        const float h = wave_minmax<true>(vmax, 0.0f);
+        const float range = h - l;
+        mx = range > mx ? range : mx;
+        if (lane == 0) lo[j] = l;
+      }
+    }
+    float mul;
+    if constexpr (TT == kTabF16) {
+      mx = wave_minmax<true>(mx, 0.0f);
+      mul = 1.0f;
+      while (mx * mul > 65504.0f) mul = mul * 0.5f;
+    } else {
+      mul = mx > 0.0f ? 255.0f / mx : 0.0f;
+      __syncthreads();  // lo[] visible to every lane
+    }
+    // pass 2: the entries again (bit-identical), stored in the reduced form
+    typename Tab<TT>::E* T = reinterpret_cast<typename Tab<TT>::E*>(Tv);
+    for (int j = 0; j < M; ++j) {
+      float qv[DS];
+#pragma unroll
+      for (int t = 0; t < DS; ++t) qv[t] = Elem<DT>::f(q, j * DS + t);
+      const float lj = (TT == kTabU8) ? lo[j] : 0.0f;
+#pragma unroll
+      for (int r = 0; r < 256 / kWave; ++r) {
+        const int c = lane + kWave * r;
+        const float e = table_entry<DS>(qv, cb + ((size_t)j * 256 + c) * DS);
+        if constexpr (TT == kTabF16) {
+          const float sv = e * mul;
+          T[j * 256 + c] = __builtin_bit_cast(uint16_t, (_Float16)sv);
+        } else {
+          const float diff = e - lj;
+          const float v = __builtin_rintf(diff * mul);
+          T[j * 256 + c] = (uint8_t)(v > 255.0f ? 255.0f : v);
+        }
+      }
+    }
+  }
+}
+
+// ADC under storage TT: FP32 sum of the (widened) entries in subspace order;
+// for U8 the exact integer sum, returned as FP32 (exact below 2^24).
+template <int M, int TT>
+__device__ __forceinline__ float adc_codes(const void* Tv, const uint4 (&v)[M / 16]) {
+  const typename Tab<TT>::E* T = reinterpret_cast<const typename Tab<TT>::E*>(Tv);
+  float acc = 0.0f;
+  uint32_t iacc = 0;
+#pragma unroll
+  for (int c = 0; c < M / 16; ++c) {
+    const uint32_t w[4] = {v[c].x, v[c].y, v[c].z, v[c].w};
+#pragma unroll
+    for (int b = 0; b < 16; ++b) {
+      const uint32_t byte = (w[b >> 2] >> (8 * (b & 3))) & 0xFFu;
+      const auto e = T[(16 * c + b) * 256 + byte];
+      if constexpr (TT == kTabF32) acc = acc + e;
+      else if constexpr (TT == kTabF16) acc = acc + f16_bits_to_f32(e);
+      else iacc += e;
+    }
+  }
+  return TT == kTabU8 ? (float)iacc : acc;
+}
+
 // Exact squared distance between base row `id` and the query.
 template <int DT, int D>
 __device__ __forceinline__ float exact_dist(const void* __restrict__ base,
@@ -345,30 +476,15 @@ __device__ __forceinline__ void load_row(const SearchArgs& a, uint32_t u,
   }
 }
 
-// ADC from codes already in registers: m table lookups, subspace order.
-template <int M>
-__device__ __forceinline__ float adc_regs(const float* T,
-                                          const uint4 (&v)[M / 16]) {
-  float acc = 0.0f;
-#pragma unroll
-  for (int c = 0; c < M / 16; ++c) {
-    const uint32_t w[4] = {v[c].x, v[c].y, v[c].z, v[c].w};
-#pragma unroll
-    for (int b = 0; b < 16; ++b) {
-      uint32_t byte = (w[b >> 2] >> (8 * (b & 3))) & 0xFFu;
-      acc = acc + T[(16 * c + b) * 256 + byte];
-    }
-  }
-  return acc;
-}
-
-template <int DT, int M, int DS>
+template <int DT, int M, int DS, int TT>
 __global__ __launch_bounds__(kWave) void search_kernel(SearchArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int D = M * DS;
+  constexpr int kTableBytes = M * 256 * (int)sizeof(typename Tab<TT>::E);
   const int lane = threadIdx.x;
   const uint32_t B = a.lblock;
-  float* T = reinterpret_cast<float*>(smem);
+  void* T = smem;
+  float* lo = reinterpret_cast<float*>(smem + kTableBytes);  // U8 offsets
   uint64_t* S = reinterpret_cast<uint64_t*>(smem);
   uint64_t* Lb0 = reinterpret_cast<uint64_t*>(smem + a.region0);
   uint64_t* Lb1 = Lb0 + kWave * B;
@@ -403,11 +519,15 @@ __global__ __launch_bounds__(kWave) void search_kernel(SearchArgs a) {
     uint32_t nb;
     uint4 code[M / 16];
     load_row<M>(a, s, lane, nb, code);  // in flight during the table build
-    build_table<DT, M, DS>(q, a.cb, T, lane, kWave);
+    build_table_q<DT, M, DS, TT>(q, a.cb, T, lo, lane);
     __syncthreads();
 
     // stage 2: L = [(ADC(s), s)]
-    uint64_t curkey = make_key(adc<M>(T, a.codes + (size_t)s * M), s);
+    uint4 scode[M / 16];
+#pragma unroll
+    for (int i = 0; i < M / 16; ++i)
+      scode[i] = reinterpret_cast<const uint4*>(a.codes + (size_t)s * M)[i];
+    uint64_t curkey = make_key(adc_codes<M, TT>(T, scode), s);
     uint64_t* Lc = Lb0;
     uint64_t* Ln = Lb1;
     if (lane == 0) Lc[0] = curkey;
@@ -438,7 +558,7 @@ __global__ __launch_bounds__(kWave) void search_kernel(SearchArgs a) {
 
       // distances of the neighbours (row of u*, loaded earlier)
       uint64_t key = kInf;
-      if (nb != kNone) key = make_key(adc_regs<M>(T, code), nb);
+      if (nb != kNone) key = make_key(adc_codes<M, TT>(T, code), nb);
 
       // rank in the worklist; a node already in it is dropped (set union)
       uint32_t r = 0;
@@ -675,19 +795,43 @@ hipError_t dispatch(int dt, uint32_t m, uint32_t ds, Args&&... args) {
 
 template <int DT, int M, int DS>
 struct RunSearch {
-  static hipError_t run(const SearchArgs& a, uint32_t grid, size_t lds,
-                        hipStream_t s) {
-    hipLaunchKernelGGL((search_kernel<DT, M, DS>), dim3(grid), dim3(kWave),
-                       lds, s, a);
+  static hipError_t run(const SearchArgs& a, int table, uint32_t grid,
+                        size_t lds, hipStream_t s) {
+    switch (table) {
+      case kTabF32:
+        hipLaunchKernelGGL((search_kernel<DT, M, DS, kTabF32>), dim3(grid),
+                           dim3(kWave), lds, s, a);
+        break;
+      case kTabF16:
+        hipLaunchKernelGGL((search_kernel<DT, M, DS, kTabF16>), dim3(grid),
+                           dim3(kWave), lds, s, a);
+        break;
+      case kTabU8:
+        hipLaunchKernelGGL((search_kernel<DT, M, DS, kTabU8>), dim3(grid),
+                           dim3(kWave), lds, s, a);
+        break;
+      default:
+        return hipErrorInvalidValue;
+    }
     return hipGetLastError();
   }
 };
 
 template <int DT, int M, int DS>
 struct Occupancy {
-  static hipError_t run(size_t lds, int* per_cu) {
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        per_cu, search_kernel<DT, M, DS>, kWave, lds);
+  static hipError_t run(int table, size_t lds, int* per_cu) {
+    switch (table) {
+      case kTabF32:
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            per_cu, search_kernel<DT, M, DS, kTabF32>, kWave, lds);
+      case kTabF16:
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            per_cu, search_kernel<DT, M, DS, kTabF16>, kWave, lds);
+      case kTabU8:
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            per_cu, search_kernel<DT, M, DS, kTabU8>, kWave, lds);
+    }
+    return hipErrorInvalidValue;
   }
 };
 
@@ -735,19 +879,28 @@ bool supported(int dtype, uint32_t m, uint32_t ds) {
 
 static uint32_t lblock_for(uint32_t L) { return (L + kWave - 1) / kWave; }
 
-static size_t region0_bytes(uint32_t m, uint32_t L, uint32_t iter_cap) {
-  size_t table = (size_t)m * 256 * 4;
+static size_t table_entry_bytes(int table) {
+  return table == kTabF32 ? 4 : (table == kTabF16 ? 2 : 1);
+}
+
+static size_t region0_bytes(uint32_t m, uint32_t L, uint32_t iter_cap,
+                            int tab) {
+  // the table (plus the u8 form's m offsets), later the re-rank keys
+  size_t table = (size_t)m * 256 * table_entry_bytes(tab) +
+                 (tab == kTabU8 ? (size_t)m * 4 : 0);
+  table = (table + 15) / 16 * 16;
   // re-rank keys: all expanded nodes when they exceed c_max (at most
   // iter_cap), else at most c_max <= 4*L; both padded to a power of two
   size_t sort = (size_t)pow2ceil(iter_cap > 4 * L ? iter_cap : 4 * L) * 8;
   return table > sort ? table : sort;
 }
 
-size_t search_lds_bytes(uint32_t m, uint32_t L, uint32_t iter_cap) {
+size_t search_lds_bytes(uint32_t m, uint32_t L, uint32_t iter_cap,
+                        int table) {
   const size_t B = lblock_for(L);
   const size_t hist = ((kWave * B + 1) * 4 + 15) / 16 * 16;
-  return region0_bytes(m, L, iter_cap) + 2 * kWave * B * 8 + (kWave + 4) * 8 +
-         hist;
+  return region0_bytes(m, L, iter_cap, table) + 2 * kWave * B * 8 +
+         (kWave + 4) * 8 + hist;
 }
 
 uint32_t row_ids_bytes(uint32_t R) { return (4 * R + 15) / 16 * 16; }
@@ -766,8 +919,9 @@ hipError_t launch_pack(const uint32_t* adj, const uint8_t* codes, uint32_t n,
   return hipGetLastError();
 }
 
-hipError_t search_occupancy(const DeviceIndex& ix, size_t lds, int* per_cu) {
-  return dispatch<Occupancy>(ix.dtype, ix.m, ix.d / ix.m, lds, per_cu);
+hipError_t search_occupancy(const DeviceIndex& ix, int table, size_t lds,
+                            int* per_cu) {
+  return dispatch<Occupancy>(ix.dtype, ix.m, ix.d / ix.m, table, lds, per_cu);
 }
 
 hipError_t launch_tables(const DeviceIndex& ix, const void* queries,
@@ -778,7 +932,7 @@ hipError_t launch_tables(const DeviceIndex& ix, const void* queries,
 
 hipError_t launch_search(const DeviceIndex& ix, const SearchLaunch& l,
                          hipStream_t s) {
-  const size_t lds = search_lds_bytes(ix.m, l.L, l.iter_cap);
+  const size_t lds = search_lds_bytes(ix.m, l.L, l.iter_cap, l.table);
   SearchArgs a;
   a.base = ix.base;
   a.rows = ix.rows;
@@ -796,7 +950,7 @@ hipError_t launch_search(const DeviceIndex& ix, const SearchLaunch& l,
   a.c_max = l.c_max;
   a.iter_cap = l.iter_cap;
   a.lblock = lblock_for(l.L);
-  a.region0 = (uint32_t)region0_bytes(ix.m, l.L, l.iter_cap);
+  a.region0 = (uint32_t)region0_bytes(ix.m, l.L, l.iter_cap, l.table);
   a.out_ids = l.out_ids;
   a.out_dists = l.out_dists;
   a.out_cand = l.out_cand;
@@ -805,7 +959,8 @@ hipError_t launch_search(const DeviceIndex& ix, const SearchLaunch& l,
   a.out_times = l.out_times;
   a.cscratch = l.cscratch;
   a.qcounter = l.qcounter;
-  return dispatch<RunSearch>(ix.dtype, ix.m, ix.d / ix.m, a, l.grid, lds, s);
+  return dispatch<RunSearch>(ix.dtype, ix.m, ix.d / ix.m, a, l.table, l.grid,
+                             lds, s);
 }
 
 hipError_t launch_rerank(const DeviceIndex& ix, const void* queries,

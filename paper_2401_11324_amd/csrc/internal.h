@@ -24,6 +24,7 @@ struct SearchLaunch {
   const void* queries;
   uint64_t nq;
   uint32_t k, L, c_max, iter_cap;
+  int table;             // 0 FP32, 1 FP16, 2 U8 (bang_search_opts.table)
   uint32_t* out_ids;
   float* out_dists;
   uint32_t* out_cand;
@@ -39,8 +40,9 @@ struct SearchLaunch {
 // True if (dtype, m, d/m) has a compiled kernel.
 bool supported(int dtype, uint32_t m, uint32_t dsub);
 
-// LDS bytes the search kernel needs for a worklist of L and an iteration cap.
-size_t search_lds_bytes(uint32_t m, uint32_t L, uint32_t iter_cap);
+// LDS bytes the search kernel needs for a worklist of L, an iteration cap
+// and a table storage form.
+size_t search_lds_bytes(uint32_t m, uint32_t L, uint32_t iter_cap, int table);
 
 // Packed adjacency rows: R ids padded to row_ids_bytes, then R x m codes.
 uint32_t row_ids_bytes(uint32_t R);
@@ -50,7 +52,8 @@ hipError_t launch_pack(const uint32_t* adj, const uint8_t* codes, uint32_t n,
                        hipStream_t s);
 
 // Resident workgroups per CU for the search kernel at this LDS size.
-hipError_t search_occupancy(const DeviceIndex& ix, size_t lds, int* per_cu);
+hipError_t search_occupancy(const DeviceIndex& ix, int table, size_t lds,
+                            int* per_cu);
 
 hipError_t launch_tables(const DeviceIndex& ix, const void* queries,
                          uint64_t nq, float* out, hipStream_t s);

@@ -78,14 +78,17 @@ def f32bits(a):
     return np.ascontiguousarray(a, dtype=np.float32).view(np.uint32)
 
 
-def run_and_compare(ix, gi, q, k, L, c_max=0, iter_cap=0, label=""):
+def run_and_compare(ix, gi, q, k, L, c_max=0, iter_cap=0, label="",
+                    table="f32"):
     cap = iter_cap or oracle.iter_cap_for(L)
     qt = to_dev(q)
     ids, d, cand, cnt = gi.search(qt, k, L, c_max=c_max, iter_cap=iter_cap,
-                                  want_cand=cap, want_counters=True)
+                                  want_cand=cap, want_counters=True,
+                                  table=table)
     torch.cuda.synchronize()
     ref = oracle.search(ix, q, k, L, c_max=c_max or None,
-                        iter_cap=iter_cap or None, want_cand=True)
+                        iter_cap=iter_cap or None, want_cand=True,
+                        table=table)
     ids, d, cand, cnt = u32(ids), d.cpu().numpy(), u32(cand), u32(cnt)
     assert np.array_equal(cnt[:, 0], ref["iters"]), label
     assert np.array_equal(cnt[:, 1], ref["status"]), label
@@ -116,6 +119,18 @@ def test_tables_bit_exact(small_indexes, name):
 def test_search_bit_exact(small_indexes, name, k, L):
     ix, q, gi = small_indexes[name]
     run_and_compare(ix, gi, q, k, L, label=f"{name} k={k} L={L}")
+
+
+@pytest.mark.parametrize("table", ["f16", "u8"])
+@pytest.mark.parametrize("name", list(SMALL))
+@pytest.mark.parametrize("k,L", [(1, 1), (10, 16), (5, 33), (10, 100),
+                                 (32, 256)])
+def test_precision_form_bit_exact(small_indexes, name, k, L, table):
+    """The precision form's half / u8 tables are derived from the canonical
+    FP32 entries on both sides, so the search stays bit-exact."""
+    ix, q, gi = small_indexes[name]
+    run_and_compare(ix, gi, q, k, L, table=table,
+                    label=f"{name} k={k} L={L} {table}")
 
 
 @pytest.mark.parametrize("name", ["u8-d128-m32", "f32-d32-m16"])
@@ -221,7 +236,9 @@ def test_tiny_workload_bit_exact():
     w, ix, d = load_workload("tiny")
     gi = bang_mod().Index(ix.base, ix.adj, ix.medoid, ix.codebooks, ix.codes)
     for L in w.Ls:
-        run_and_compare(ix, gi, d["queries"], w.k, L, label=f"tiny L={L}")
+        for table in ("f32", "f16", "u8"):
+            run_and_compare(ix, gi, d["queries"], w.k, L, table=table,
+                            label=f"tiny L={L} {table}")
 
 
 def test_sift1m_full_batch_sampled_bit_exact():
@@ -234,12 +251,14 @@ def test_sift1m_full_batch_sampled_bit_exact():
     qt = to_dev(q)
     sample = np.sort(np.random.default_rng(2024).choice(len(q), 160,
                                                         replace=False))
-    for L in w.Ls:
+    for L, table in [(L, "f32") for L in w.Ls] + [(64, "f16"), (64, "u8"),
+                                                   (256, "u8")]:
         cap = oracle.iter_cap_for(L)
         ids, dist, cand, cnt = gi.search(qt, w.k, L, want_cand=cap,
-                                         want_counters=True)
+                                         want_counters=True, table=table)
         torch.cuda.synchronize()
-        ref = oracle.search(ix, q[sample], w.k, L, want_cand=True)
+        ref = oracle.search(ix, q[sample], w.k, L, want_cand=True,
+                            table=table)
         assert np.array_equal(u32(cnt)[sample, 0], ref["iters"]), L
         assert np.array_equal(u32(cand)[sample], ref["cand"]), L
         assert np.array_equal(u32(ids)[sample], ref["ids"]), L
