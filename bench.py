@@ -1,15 +1,17 @@
 """Benchmark: QPS of the whole hot path (PQ table + greedy search + re-rank)
-on one MI355X for the 1M uint8 workload, at the smallest worklist size L
-whose mean 10-recall@10 reaches 0.9 (or, if none does, the L with the best
-recall), with p50/p99 per-query completion latency, the search kernel's
-fraction of the HBM roofline, and the CPU oracle timed on the host.
+on one MI355X for the 1M uint8 workload, plain FP32 tables vs the precision
+form (FP16 / u8 tables), each at the smallest worklist size L whose mean
+10-recall@10 reaches 0.9 (or, if none does, the L with the best recall),
+with p50/p99 per-query completion latency, the search kernel's fraction of
+the HBM roofline, and the CPU oracle timed on the host.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--L L]
 
-Prints one JSON line.  A step is one bang_search call over the 10,000
-resident queries; the timed region holds exactly K steps, bracketed by a
-device synchronisation on both sides, each step bracketed by HIP events on
-the stream the kernel runs on.
+Prints one JSON line; `value` is the plain FP32 form's QPS and
+`precision_form` holds the reduced-precision measurements.  A step is one
+bang_search call over the 10,000 resident queries; each form's timed region
+holds exactly K steps, bracketed by a device synchronisation on both sides,
+each step bracketed by HIP events on the stream the kernel runs on.
 """
 from __future__ import annotations
 
@@ -30,6 +32,7 @@ METRIC = ("QPS at recall@10>=0.9 on 1 GPU, plain FP32 vs reduced-precision "
 WORKLOAD = "sift1m"
 HBM_PEAK_GBS = 8000.0
 TARGET_RECALL = 0.9
+TABLES = ("f32", "f16", "u8")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "search_sift1m_traffic.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2401_11324_amd", "csrc", f)
                   for f in ("bang_kernels.hip", "bang_api.cpp", "internal.h")]
@@ -106,7 +109,8 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--L", type=int, default=0,
-                    help="worklist size (default: chosen by the recall sweep)")
+                    help="worklist size for every form (default: chosen by "
+                         "the recall sweep)")
     ap.add_argument("--no-cpu", action="store_true",
                     help="skip the CPU oracle baseline")
     ap.add_argument("--no-sweep", action="store_true",
@@ -145,62 +149,80 @@ def main(argv=None):
     nq, k = q.shape[0], w.k
     stream = torch.cuda.current_stream()
 
-    # recall sweep (untimed apart from one launch each)
+    # recall sweep over L and table forms (one untimed + one timed launch)
     sweep = []
-    for L in ([] if a.no_sweep else w.Ls):
-        ids, dist = gi.search(q, k, L)
-        torch.cuda.synchronize()
-        t0 = torch.cuda.Event(enable_timing=True)
-        t1 = torch.cuda.Event(enable_timing=True)
-        t0.record(stream)
-        gi.search(q, k, L, out=(ids, dist))
-        t1.record(stream)
-        torch.cuda.synchronize()
-        rec = recall_at_k(ids.cpu().numpy().view(np.uint32), gt, k)
-        sweep.append({"L": L, "recall10": round(rec, 4),
-                      "qps": round(nq / (t0.elapsed_time(t1) / 1e3))})
-    if a.L:
-        L = a.L
-    else:
-        ok = [s for s in sweep if s["recall10"] >= TARGET_RECALL]
-        L = ok[0]["L"] if ok else max(sweep, key=lambda s: s["recall10"])["L"]
+    for table in ([] if a.no_sweep else TABLES):
+        for L in w.Ls:
+            ids, dist = gi.search(q, k, L, table=table)
+            torch.cuda.synchronize()
+            t0 = torch.cuda.Event(enable_timing=True)
+            t1 = torch.cuda.Event(enable_timing=True)
+            t0.record(stream)
+            gi.search(q, k, L, out=(ids, dist), table=table)
+            t1.record(stream)
+            torch.cuda.synchronize()
+            rec = recall_at_k(ids.cpu().numpy().view(np.uint32), gt, k)
+            sweep.append({"table": table, "L": L, "recall10": round(rec, 4),
+                          "qps": round(nq / (t0.elapsed_time(t1) / 1e3))})
 
-    ids = torch.empty((nq, k), dtype=torch.int32, device=dev)
-    dist = torch.empty((nq, k), dtype=torch.float32, device=dev)
-    for _ in range(a.warmup):
-        gi.search(q, k, L, out=(ids, dist))
-    torch.cuda.synchronize()
-    ev = [(torch.cuda.Event(enable_timing=True),
-           torch.cuda.Event(enable_timing=True)) for _ in range(a.steps)]
-    wall0 = time.perf_counter()
-    for e0, e1 in ev:
-        e0.record(stream)
-        gi.search(q, k, L, out=(ids, dist))
-        e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - wall0
-    per = np.array([e0.elapsed_time(e1) for e0, e1 in ev])  # ms per launch
-    ms_step = wall * 1e3 / a.steps
-    qps = nq / (ms_step / 1e3)
-    rec = recall_at_k(ids.cpu().numpy().view(np.uint32), gt, k)
+    def pick_L(table):
+        if a.L:
+            return a.L
+        rows = [s for s in sweep if s["table"] == table]
+        ok = [s for s in rows if s["recall10"] >= TARGET_RECALL]
+        return ok[0]["L"] if ok else max(rows, key=lambda s: s["recall10"])["L"]
 
-    # one more (untimed) launch with counters, expanded nodes and timestamps
-    cap = 10 * L + 100
-    _, _, cand, cnt, times = gi.search(q, k, L, want_cand=cap,
-                                       want_counters=True, want_times=True)
-    torch.cuda.synchronize()
-    cand = cand.cpu().numpy().view(np.uint32)
-    iters = cnt.cpu().numpy()[:, 0]
-    t = times.cpu().numpy().astype(np.float64)
-    # completion time of each query after the batch began, scaled so that
-    # the span of the device clock equals the measured kernel time
-    span = max(1.0, t[:, 1].max() - t[:, 0].min())
     adj_deg = (d["adj"] != 0xFFFFFFFF).sum(1)
     elem = 1 if w.dtype in ("u8", "i8") else 4
-    B = algorithmic_bytes(adj_deg, w.R, w.m, w.d, elem, k, iters, cand, 4 * L)
-    kern_ms = float(per.mean())
-    lat_ms = (t[:, 1] - t[:, 0].min()) / span * kern_ms
-    achieved = B / (kern_ms / 1e3) / 1e9
+
+    def measure(table, L):
+        """K timed steps of one form; returns its record."""
+        ids = torch.empty((nq, k), dtype=torch.int32, device=dev)
+        dist = torch.empty((nq, k), dtype=torch.float32, device=dev)
+        for _ in range(a.warmup):
+            gi.search(q, k, L, out=(ids, dist), table=table)
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True),
+               torch.cuda.Event(enable_timing=True)) for _ in range(a.steps)]
+        wall0 = time.perf_counter()
+        for e0, e1 in ev:
+            e0.record(stream)
+            gi.search(q, k, L, out=(ids, dist), table=table)
+            e1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - wall0
+        per = np.array([e0.elapsed_time(e1) for e0, e1 in ev])  # ms/launch
+        rec = recall_at_k(ids.cpu().numpy().view(np.uint32), gt, k)
+        # one more (untimed) launch with counters, expanded nodes, stamps
+        cap = max(4 * L, L + 64)
+        _, _, cand, cnt, times = gi.search(q, k, L, want_cand=cap,
+                                           want_counters=True,
+                                           want_times=True, table=table)
+        torch.cuda.synchronize()
+        cand = cand.cpu().numpy().view(np.uint32)
+        iters = cnt.cpu().numpy()[:, 0]
+        t = times.cpu().numpy().astype(np.float64)
+        # completion time of each query after the batch began, scaled so
+        # that the span of the device clock equals the measured kernel time
+        span = max(1.0, t[:, 1].max() - t[:, 0].min())
+        kern_ms = float(per.mean())
+        lat_ms = (t[:, 1] - t[:, 0].min()) / span * kern_ms
+        B = algorithmic_bytes(adj_deg, w.R, w.m, w.d, elem, k, iters, cand,
+                              4 * L)
+        ms_step = wall * 1e3 / a.steps
+        return {"table": table, "L": L, "recall10": round(rec, 4),
+                "qps": round(nq / (ms_step / 1e3), 1),
+                "ms_per_step": round(ms_step, 4),
+                "p50_ms": round(float(np.percentile(lat_ms, 50)), 4),
+                "p99_ms": round(float(np.percentile(lat_ms, 99)), 4),
+                "mean_iterations": round(float(iters.mean()), 2),
+                "kernel_ms_mean": round(kern_ms, 4),
+                "algorithmic_bytes_per_launch": B,
+                "achieved_gbs": round(B / (kern_ms / 1e3) / 1e9, 2)}
+
+    plain = measure("f32", pick_L("f32"))
+    prec = {t: measure(t, pick_L(t)) for t in ("f16", "u8")}
+    L = plain["L"]
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as f:
@@ -210,12 +232,12 @@ def main(argv=None):
 
     out = {
         "metric": METRIC,
-        "value": round(qps, 1),
+        "value": plain["qps"],
         "unit": "queries/s",
         "n_gpus": 1,
         "steps": a.steps,
         "warmup": a.warmup,
-        "ms_per_step": round(ms_step, 4),
+        "ms_per_step": plain["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -226,25 +248,27 @@ def main(argv=None):
                         "uint8, 1,000 centres U[0,255], sigma 20; 10,000 "
                         "queries; graph R=64 L_build=100 alpha=1.2; PQ m=32",
             "form": "plain FP32",
-            "k": k, "L": L, "recall10": round(rec, 4),
+            "k": k, "L": L, "recall10": plain["recall10"],
             "target_recall10": TARGET_RECALL,
-            "target_met": bool(rec >= TARGET_RECALL),
-            "mean_iterations": round(float(iters.mean()), 2),
+            "target_met": bool(plain["recall10"] >= TARGET_RECALL),
+            "mean_iterations": plain["mean_iterations"],
             "sweep": sweep,
         },
-        "p50_ms": round(float(np.percentile(lat_ms, 50)), 4),
-        "p99_ms": round(float(np.percentile(lat_ms, 99)), 4),
+        "p50_ms": plain["p50_ms"],
+        "p99_ms": plain["p99_ms"],
         "roofline": {
             "bound": "hbm",
-            "kernel": "search_kernel<u8, m=32, d/m=4>",
-            "achieved": round(achieved, 2),
+            "kernel": "search_kernel<u8 data, m=32, d/m=4, FP32 table>",
+            "achieved": plain["achieved_gbs"],
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 5),
+            "frac": round(plain["achieved_gbs"] / HBM_PEAK_GBS, 5),
             "traffic": traffic,
-            "algorithmic_bytes_per_launch": B,
-            "kernel_ms_mean": round(kern_ms, 4),
+            "algorithmic_bytes_per_launch":
+                plain["algorithmic_bytes_per_launch"],
+            "kernel_ms_mean": plain["kernel_ms_mean"],
         },
+        "precision_form": prec,
     }
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(d, d["queries"], k, L)
