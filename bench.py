@@ -53,6 +53,12 @@ def recall_at_k(ids: np.ndarray, gt: np.ndarray, k: int) -> float:
     return float(np.mean(hits)) / k
 
 
+def iteration_overhead(I: float, t: int) -> float:
+    """lambda = (I - t) / t * 100: iterations above the lower bound t (the
+    worklist size), section "Effect of Varying Worklist Size (t)"."""
+    return (I - t) / t * 100.0
+
+
 def algorithmic_bytes(adj_deg, R, m, d, elem, k, iters, cand, c_max):
     """HBM bytes one launch must move, from the per-query counters:
     per expansion the adjacency row (4R) and the m code bytes of every
@@ -216,6 +222,8 @@ def main(argv=None):
                 "p50_ms": round(float(np.percentile(lat_ms, 50)), 4),
                 "p99_ms": round(float(np.percentile(lat_ms, 99)), 4),
                 "mean_iterations": round(float(iters.mean()), 2),
+                "lambda_pct": round(iteration_overhead(float(iters.mean()),
+                                                       L), 2),
                 "kernel_ms_mean": round(kern_ms, 4),
                 "algorithmic_bytes_per_launch": B,
                 "achieved_gbs": round(B / (kern_ms / 1e3) / 1e9, 2)}
@@ -252,6 +260,7 @@ def main(argv=None):
             "target_recall10": TARGET_RECALL,
             "target_met": bool(plain["recall10"] >= TARGET_RECALL),
             "mean_iterations": plain["mean_iterations"],
+            "lambda_pct": plain["lambda_pct"],
             "sweep": sweep,
         },
         "p50_ms": plain["p50_ms"],

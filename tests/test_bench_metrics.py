@@ -1,0 +1,35 @@
+"""The benchmark's measurement formulas, pinned to the paper where it
+prints values (CPU only)."""
+import numpy as np
+
+import bench
+
+
+def test_iteration_overhead_matches_table5(golden):
+    """Table 5 prints t, I and lambda = (I - t) / t * 100 to one decimal."""
+    for row in golden("table5.json")["rows"]:
+        lam = bench.iteration_overhead(row["I"], row["t"])
+        assert round(lam, 1) == row["lambda"]
+
+
+def test_recall_at_k_definition():
+    """k-recall@k = |S ∩ S~| / k ("Algorithm Parameters")."""
+    gt = np.array([[1, 2, 3, 4], [5, 6, 7, 8]])
+    ids = np.array([[4, 3, 9, 9], [5, 6, 7, 8]])
+    assert bench.recall_at_k(ids, gt, 4) == (2 / 4 + 1) / 2
+    assert bench.recall_at_k(ids, gt, 2) == (0 + 1) / 2
+
+
+def test_algorithmic_bytes_counts_rows_codes_and_rerank():
+    deg = np.array([3, 2, 1, 0])
+    cand = np.array([[0, 1, 0xFFFFFFFF], [2, 0xFFFFFFFF, 0xFFFFFFFF]],
+                    dtype=np.uint32)
+    iters = np.array([2, 1])
+    R, m, d, elem, k = 4, 8, 16, 1, 2
+    got = bench.algorithmic_bytes(deg, R, m, d, elem, k, iters, cand, c_max=1)
+    want = (3 * 4 * R                 # three expansions, one row each
+            + (3 + 2 + 1) * m         # codes of every neighbour
+            + 2 * d * elem            # two queries
+            + (1 + 1) * d * elem      # re-ranked rows, capped at c_max=1
+            + 2 * 8 * k)              # results
+    assert got == want
