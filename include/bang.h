@@ -46,7 +46,7 @@ extern "C" {
 #define BANG_EABORTED (-5)     /* reserved */
 
 #define BANG_NONE 0xFFFFFFFFu  /* empty adjacency slot / padded result id */
-#define BANG_MAX_L 256u        /* largest worklist (the paper's t) */
+#define BANG_MAX_L 1024u       /* largest worklist (the paper's t) */
 #define BANG_MAX_R 64u         /* largest graph degree */
 
 typedef enum { BANG_F32 = 0, BANG_U8 = 1, BANG_I8 = 2 } bang_dtype;
@@ -88,7 +88,13 @@ typedef struct {
   uint32_t table;           /* storage of the PQ table the search ranks by:
                                BANG_TABLE_F32 (default), or the precision
                                form's BANG_TABLE_F16 / BANG_TABLE_U8 */
+  uint32_t flags;           /* 0, or BANG_SEARCH_RERANK_GLOBAL */
 } bang_search_opts;
+
+/* The re-rank sorts a query's expanded nodes in on-chip memory when they
+ * fit there and otherwise selects them in device memory; this flag takes
+ * the device-memory path always (same results; for testing it). */
+#define BANG_SEARCH_RERANK_GLOBAL 1u
 
 /* Table storage forms.  Both reduced forms are computed from the FP32
  * entries of the PQ table section, so they are deterministic:

@@ -167,9 +167,9 @@ TABLES = {"f32": 0, "f16": 1, "u8": 2}
 
 
 def iter_cap_for(L: int) -> int:
-    """Safety cap on iterations per query, identical on both sides: far
-    above the iteration counts of the paper's worklist-size table (I <= 3.1
-    t) and of the workloads here (I ~ 1.2 L)."""
+    """Safety cap on iterations per query, identical on both sides: above
+    the iteration counts of the paper's worklist-size table (I <= 3.1 t)
+    and of the workloads here (I ~ 1.2 L on average, 3.3 L at most)."""
     return max(4 * L, L + 64)
 
 

@@ -18,7 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "_bang.so")
 
 BANG_NONE = 0xFFFFFFFF
-MAX_L = 256
+MAX_L = 1024
 MAX_R = 64
 DTYPES = {"f32": 0, "u8": 1, "i8": 2}
 TABLES = {"f32": 0, "f16": 1, "u8": 2}
@@ -48,7 +48,7 @@ class SearchOpts(ctypes.Structure):
                 ("out_cand", ctypes.c_void_p), ("cand_stride", ctypes.c_uint32),
                 ("out_counters", ctypes.c_void_p),
                 ("out_times", ctypes.c_void_p),
-                ("table", ctypes.c_uint32)]
+                ("table", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
 
 
 _lib = None
@@ -88,6 +88,20 @@ def _stream(stream):
     import torch
     s = stream if stream is not None else torch.cuda.current_stream()
     return ctypes.c_void_p(s.cuda_stream)
+
+
+def _check_out(ids, dists, nq, k, device):
+    """Caller-supplied outputs must be exactly [nq][k] on the queries' device
+    (the kernels write every element of both)."""
+    import torch
+    for t, dt, nm in ((ids, torch.int32, "ids"), (dists, torch.float32,
+                                                   "dists")):
+        if tuple(t.shape) != (nq, k):
+            raise ValueError(f"{nm} must have shape ({nq}, {k}), got "
+                             f"{tuple(t.shape)}")
+        if t.device != device:
+            raise ValueError(f"{nm} must be on {device}")
+        _dev_ptr(t, dt, nm)
 
 
 def _dev_ptr(t, dtype=None, name="tensor"):
@@ -159,6 +173,8 @@ class Index:
         if out is None:
             out = torch.empty((q.shape[0], self.m, 256), dtype=torch.float32,
                               device=q.device)
+        elif tuple(out.shape) != (q.shape[0], self.m, 256):
+            raise ValueError(f"out must have shape ({q.shape[0]}, {self.m}, 256)")
         _check(lib().bang_build_pq_tables(
             self._h, qp, q.shape[0], _dev_ptr(out, torch.float32, "out"),
             _stream(stream)))
@@ -166,8 +182,8 @@ class Index:
 
     def search(self, q, k: int, L: int, c_max: int = 0, iter_cap: int = 0,
                want_cand: int = 0, want_counters: bool = False,
-               want_times: bool = False, table: str = "f32", out=None,
-               stream=None):
+               want_times: bool = False, table: str = "f32",
+               rerank_global: bool = False, out=None, stream=None):
         """Stages 1-3.  Returns (ids uint32-as-int32 [nq][k], dists
         float32 [nq][k]) and, on request, the expanded nodes [nq][want_cand]
         `table` is the PQ table storage the search ranks by: "f32", or the
@@ -182,7 +198,9 @@ class Index:
             dists = torch.empty((nq, k), dtype=torch.float32, device=q.device)
         else:
             ids, dists = out
-        opts = SearchOpts(c_max, iter_cap, None, 0, None, None, TABLES[table])
+            _check_out(ids, dists, nq, k, q.device)
+        opts = SearchOpts(c_max, iter_cap, None, 0, None, None, TABLES[table],
+                          1 if rerank_global else 0)
         cand = cnt = times = None
         if want_cand:
             cand = torch.empty((nq, want_cand), dtype=torch.int32,
@@ -221,6 +239,10 @@ class Index:
             dists = torch.empty((nq, k), dtype=torch.float32, device=q.device)
         else:
             ids, dists = out
+            _check_out(ids, dists, nq, k, q.device)
+        _dev_ptr(cand, torch.int32, "cand")
+        if cand.device != q.device:
+            raise ValueError("cand must be on the queries' device")
         _check(lib().bang_rerank(
             self._h, qp, nq, _dev_ptr(cand, torch.int32, "cand"),
             cand.shape[1], k, _dev_ptr(ids, torch.int32, "ids"),

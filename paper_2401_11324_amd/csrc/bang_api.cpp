@@ -27,6 +27,7 @@ struct bang_index {
   size_t cscratch_bytes = 0;
   uint32_t* d_qcounter = nullptr;
   int num_cus = 0;
+  int max_lds = 64 * 1024;  // dynamic LDS bytes one workgroup may use
 };
 
 namespace {
@@ -150,6 +151,10 @@ int create_impl(const bang_index_desc* d, bang_index** out) {
   }
   e = hipDeviceGetAttribute(&ix->num_cus, hipDeviceAttributeMultiprocessorCount,
                             ix->device);
+  if (e == hipSuccess)
+    e = hipDeviceGetAttribute(&ix->max_lds,
+                              hipDeviceAttributeMaxSharedMemoryPerBlock,
+                              ix->device);
   if (e != hipSuccess) {
     delete ix;
     return hip_fail(e, "hipDeviceGetAttribute");
@@ -218,7 +223,7 @@ int search_impl(bang_index* ix, const void* queries, uint64_t nq, uint32_t k,
                 const bang_search_opts* o, hipStream_t s) {
   if (!ix) return fail(BANG_EINVAL, "null index");
   if (k < 1 || k > L || L > BANG_MAX_L)
-    return fail(BANG_EINVAL, "need 1 <= k <= L <= 256");
+    return fail(BANG_EINVAL, "need 1 <= k <= L <= 1024");
   if (k > ix->dev.n) return fail(BANG_EINVAL, "k > n");
   if (nq == 0) return BANG_OK;
   if (nq >= (1ull << 32)) return fail(BANG_EINVAL, "nq too large");
@@ -231,18 +236,19 @@ int search_impl(bang_index* ix, const void* queries, uint64_t nq, uint32_t k,
   uint32_t iter_cap = (o && o->iter_cap) ? o->iter_cap : std::max(4 * L, L + 64);
   const uint32_t table = o ? o->table : BANG_TABLE_F32;
   if (table > BANG_TABLE_U8) return fail(BANG_EINVAL, "unknown table form");
-  if (iter_cap > 16384) return fail(BANG_EINVAL, "iter_cap > 16384");
+  if (iter_cap > 8192) return fail(BANG_EINVAL, "iter_cap > 8192");
   if (o && o->out_cand && o->cand_stride == 0)
     return fail(BANG_EINVAL, "cand_stride must be > 0 with out_cand");
 
   size_t lds = bang::search_lds_bytes(ix->dev.m, L, iter_cap, (int)table);
-  if (lds > 64 * 1024)
-    return fail(BANG_EUNSUPPORTED,
-                "table + worklist + re-rank keys exceed 64 KB of LDS "
-                "(lower iter_cap)");
   int per_cu = 0;
   hipError_t e = hipSetDevice(ix->device);
   if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  if (lds > (size_t)ix->max_lds)
+    return fail(BANG_EUNSUPPORTED,
+                "table + worklist + re-rank keys need " + std::to_string(lds) +
+                    " bytes of LDS, the device allows " +
+                    std::to_string(ix->max_lds) + " (lower L or iter_cap)");
   e = bang::search_occupancy(ix->dev, (int)table, lds, &per_cu);
   if (e != hipSuccess) return hip_fail(e, "occupancy query");
   if (per_cu < 1) return fail(BANG_EUNSUPPORTED, "search kernel cannot be resident");
@@ -272,6 +278,9 @@ int search_impl(bang_index* ix, const void* queries, uint64_t nq, uint32_t k,
   l.c_max = c_max;
   l.iter_cap = iter_cap;
   l.table = (int)table;
+  l.flags = o ? o->flags : 0u;
+  if (l.flags & ~BANG_SEARCH_RERANK_GLOBAL)
+    return fail(BANG_EINVAL, "unknown search flags");
   l.out_ids = out_ids;
   l.out_dists = out_dists;
   l.out_cand = o ? o->out_cand : nullptr;

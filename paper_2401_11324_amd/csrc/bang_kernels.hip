@@ -381,13 +381,12 @@ __device__ __forceinline__ uint64_t wave_min64(uint64_t v) {
 }
 
 // Number of entries of the sorted LDS list A[0..len) whose key, visited bit
-// ignored, is below x's (len <= 256).  Branch-free binary lifting: the
-// step sequence depends only on len, which is uniform across the wave.
+// ignored, is below x's (len <= 1024), by binary lifting.
 __device__ __forceinline__ uint32_t rank_in(const uint64_t* A, uint32_t len,
                                             uint64_t x) {
   const uint64_t xs = x >> 1;
   uint32_t pos = 0;
-  for (uint32_t step = 256; step > 0; step >>= 1) {
+  for (uint32_t step = 1024; step > 0; step >>= 1) {
     if (step > len) continue;
     uint32_t np = pos + step;
     if (np <= len && (A[np - 1] >> 1) < xs) pos = np;
@@ -435,6 +434,34 @@ __device__ void sort_and_emit(uint64_t* S, uint32_t cnt, uint32_t k,
   }
 }
 
+// Partial selection sort in global memory: C[0..kk) become the kk smallest
+// of C[0..n), ascending.  For re-ranks too large for LDS (rare: an
+// expansion count far above L); one wave, with a device fence per round so
+// every lane sees lane 0's swap.
+__device__ void global_select(uint64_t* C, uint32_t n, uint32_t kk, int lane) {
+  for (uint32_t r = 0; r < kk && r < n; ++r) {
+    uint64_t best = kInf;
+    uint32_t at = kNone;
+    for (uint32_t i = r + lane; i < n; i += kWave) {
+      const uint64_t v = C[i];
+      if (v < best) {
+        best = v;
+        at = i;
+      }
+    }
+    const uint64_t m = wave_min64(best);
+    const uint64_t who = __ballot(best == m && at != kNone);
+    const uint32_t src = __shfl(at, __ffsll((unsigned long long)who) - 1);
+    if (lane == 0 && src != kNone && src != r) {
+      const uint64_t t = C[r];
+      C[r] = m;
+      C[src] = t;
+    }
+    __threadfence();
+    __syncthreads();
+  }
+}
+
 struct SearchArgs {
   const void* base;
   const unsigned char* rows;  // packed rows: ids, then the neighbours' codes
@@ -445,8 +472,12 @@ struct SearchArgs {
   uint32_t n, R, medoid;
   uint32_t row_stride, row_ids;  // bytes per row; bytes of the id part
   uint32_t k, Lcap, c_max, iter_cap;
-  uint32_t lblock;   // worklist entries per lane, ceil(Lcap / 64) <= 4
-  uint32_t region0;  // bytes of the table / re-rank region
+  uint32_t lblock;   // worklist entries per lane in a super-row, <= kPer
+  uint32_t lrow;     // worklist buffer entries: Lcap rounded up to 64*lblock
+  uint32_t region0;  // bytes of the table region (re-rank keys reuse it
+                     // together with both worklist buffers)
+  uint32_t s_cap;    // keys that fit there: (region0 + 16 * lrow) / 8, or
+                     // 0 to make the re-rank select in global memory
   uint32_t* out_ids;
   float* out_dists;
   uint32_t* out_cand;
@@ -457,7 +488,10 @@ struct SearchArgs {
   uint32_t* qcounter;
 };
 
-constexpr int kMaxBlock = 4;  // 64 lanes x 4 = the largest worklist, 256
+// The worklist is handled in super-rows of 64*B entries, B = ceil(L/64)
+// capped at kPer; inside one, lane l owns the B entries
+// [base + B*l, base + B*l + B).  L <= 256 is a single super-row.
+constexpr int kPer = 4;
 
 // Adjacency row of node u and, in the same row, the codes of its
 // neighbours: one coalesced load per lane, no dependent gather.
@@ -482,17 +516,17 @@ __global__ __launch_bounds__(kWave) void search_kernel(SearchArgs a) {
   constexpr int D = M * DS;
   constexpr int kTableBytes = M * 256 * (int)sizeof(typename Tab<TT>::E);
   const int lane = threadIdx.x;
-  const uint32_t B = a.lblock;
   void* T = smem;
   float* lo = reinterpret_cast<float*>(smem + kTableBytes);  // U8 offsets
-  uint64_t* S = reinterpret_cast<uint64_t*>(smem);
+  uint64_t* S = reinterpret_cast<uint64_t*>(smem);  // re-rank keys
+  const uint32_t B = a.lblock;
+  const uint32_t sup = kWave * B;  // super-row size
   uint64_t* Lb0 = reinterpret_cast<uint64_t*>(smem + a.region0);
-  uint64_t* Lb1 = Lb0 + kWave * B;
-  uint64_t* Nb = Lb1 + kWave * B;                           // kWave + 4
-  uint32_t* H = reinterpret_cast<uint32_t*>(Nb + kWave + 4);  // kWave*B + 1
+  uint64_t* Lb1 = Lb0 + a.lrow;
+  uint64_t* Nb = Lb1 + a.lrow;                                // kWave + 4
+  uint32_t* H = reinterpret_cast<uint32_t*>(Nb + kWave + 4);  // lrow + 4
   uint64_t* C = a.cscratch + (size_t)blockIdx.x * a.iter_cap;
-
-  for (uint32_t t = lane; t <= kWave * B; t += kWave) H[t] = 0u;
+  for (uint32_t t = lane; t < a.lrow + 4; t += kWave) H[t] = 0u;
 
   for (;;) {
     uint32_t qi = 0;
@@ -545,14 +579,12 @@ __global__ __launch_bounds__(kWave) void search_kernel(SearchArgs a) {
         C[iters] = curkey;
       }
       ++iters;
-
-      // this lane's block of the worklist, lane owns [lane*B, lane*B + B)
-      // (the buffer holds 64*B entries, so the read is in bounds even past
-      // Llen; such entries are masked to +inf)
-      uint64_t lk[kMaxBlock];
+      // this lane's entries of the super-row holding u*
+      const uint32_t sbase = cur / sup * sup;
+      uint64_t lk[kPer];
 #pragma unroll
-      for (int t = 0; t < kMaxBlock; ++t) {
-        const uint32_t j = lane * B + t;
+      for (int t = 0; t < kPer; ++t) {
+        const uint32_t j = sbase + B * lane + t;
         lk[t] = ((uint32_t)t < B && j < Llen) ? Lc[j] : kInf;
       }
 
@@ -560,36 +592,41 @@ __global__ __launch_bounds__(kWave) void search_kernel(SearchArgs a) {
       uint64_t key = kInf;
       if (nb != kNone) key = make_key(adc_codes<M, TT>(T, code), nb);
 
-      // rank in the worklist; a node already in it is dropped (set union)
+      // rank in the worklist; a node already in it is dropped (set union);
+      // a key ranked past a full worklist is cut whatever the other new keys
+      // are, so only the remaining ("live") keys take part in the merge
       uint32_t r = 0;
       bool keep = false;
       if (key != kInf) {
         r = rank_in(Lc, Llen, key);
-        keep = !(r < Llen && (Lc[r] >> 1) == (key >> 1));
+        keep = !(r < Llen && (Lc[r] >> 1) == (key >> 1)) && r < a.Lcap;
       }
-      // a key ranked past a full worklist is cut whatever the other new keys
-      // are: only the remaining ("live") keys take part in the merge
-      keep = keep && r < a.Lcap;
       const uint64_t kk = keep ? key : kInf;
 
       // next node, decided before the merge: the smaller of the first
       // unvisited worklist entry a and the best new key b.  a is never cut
       // when it is the smaller; b is cut when its worklist rank reaches L,
       // and then a is cut too.  Its merged position is a's index or b's rank.
-      uint32_t ja = kNone;
-#pragma unroll
-      for (int t = kMaxBlock - 1; t >= 0; --t) {
-        const uint32_t j = lane * B + t;
-        if (lk[t] != kInf && !(lk[t] & 1ull) && j != cur) ja = j;
-      }
-      const uint64_t am = __ballot(ja != kNone);
-      uint64_t akey = kInf;
       uint32_t apos = kNone;
-      if (am) {
-        const int f = __ffsll((unsigned long long)am) - 1;
-        apos = __shfl(ja, f);
-        akey = Lc[apos];
+      {
+        uint32_t ja = kNone;
+#pragma unroll
+        for (int t = kPer - 1; t >= 0; --t) {
+          const uint32_t j = sbase + B * lane + t;
+          if (lk[t] != kInf && j != cur && !(lk[t] & 1ull)) ja = j;
+        }
+        uint64_t am = __ballot(ja != kNone);
+        for (uint32_t base = sbase + sup; !am && base < Llen; base += sup) {
+#pragma unroll
+          for (int t = kPer - 1; t >= 0; --t) {
+            const uint32_t j = base + B * lane + t;
+            if ((uint32_t)t < B && j < Llen && !(Lc[j] & 1ull)) ja = j;
+          }
+          am = __ballot(ja != kNone);
+        }
+        if (am) apos = __shfl(ja, __ffsll((unsigned long long)am) - 1);
       }
+      const uint64_t akey = apos != kNone ? Lc[apos] : kInf;
       const uint64_t bkey = wave_min64(kk);
       uint32_t best = kNone;
       uint64_t bestkey = kInf;
@@ -636,30 +673,39 @@ __global__ __launch_bounds__(kWave) void search_kernel(SearchArgs a) {
         rn += (x0 < kk) + (x1 < kk) + (x2 < kk) + (x3 < kk);
       }
 
-      // new keys below worklist entry j = sum of H[0..j] (keys whose
-      // worklist rank is <= j)
-      uint32_t sh[kMaxBlock];
-      uint32_t tot = 0;
-#pragma unroll
-      for (int t = 0; t < kMaxBlock; ++t) {
-        const uint32_t j = lane * B + t;
-        if (lk[t] != kInf) tot += H[j];
-        sh[t] = tot;
-      }
-      const uint32_t excl = wave_exclusive_scan(tot);
-
-      // merge: position = own index + rank in the other list
+      // merge: position = own index + rank in the other list.  New keys
+      // below worklist entry j = H[0] + ... + H[j] (live keys whose
+      // worklist rank is <= j): a prefix over super-rows of 64*B entries.
       if (keep && r + rn < a.Lcap) Ln[r + rn] = key;
+      uint32_t carry = 0;
+      for (uint32_t base = 0; base < Llen; base += sup) {
+        uint64_t v[kPer];
+        uint32_t sh[kPer];
+        uint32_t tot = 0;
 #pragma unroll
-      for (int t = 0; t < kMaxBlock; ++t) {
-        const uint32_t j = lane * B + t;
-        if (lk[t] != kInf) {
-          const uint32_t p = j + excl + sh[t];
-          if (p < a.Lcap) Ln[p] = j == cur ? (lk[t] | 1ull) : lk[t];
+        for (int t = 0; t < kPer; ++t) {
+          const uint32_t j = base + B * lane + t;
+          v[t] = base == sbase ? lk[t]
+                               : (((uint32_t)t < B && j < Llen) ? Lc[j] : kInf);
+          if (j == cur) v[t] |= 1ull;  // u*, marked visited
+          if ((uint32_t)t < B) {
+            if (j < Llen) tot += H[j];
+            H[j] = 0u;
+          }
+          sh[t] = tot;
         }
-        if ((uint32_t)t < B) H[j] = 0u;
+        const uint32_t excl = wave_exclusive_scan(tot);
+#pragma unroll
+        for (int t = 0; t < kPer; ++t) {
+          const uint32_t j = base + B * lane + t;
+          if (v[t] != kInf) {
+            const uint32_t p = j + carry + excl + sh[t];
+            if (p < a.Lcap) Ln[p] = v[t];
+          }
+        }
+        carry += __builtin_amdgcn_readlane(excl + tot, kWave - 1);
       }
-      if (lane == 0) H[kWave * B] = 0u;
+      if (lane == 0) H[Llen] = 0u;
       Llen = min(a.Lcap, Llen + nv);
       uint64_t* tmp = Lc;
       Lc = Ln;
@@ -684,25 +730,50 @@ __global__ __launch_bounds__(kWave) void search_kernel(SearchArgs a) {
         a.out_cand[(size_t)qi * a.cand_stride + i] =
             i < iters ? key_id(C[i]) : kNone;
     uint32_t nc = iters;
-    if (nc > a.c_max) {
-      // keep the c_max smallest (PQ distance, id)
-      uint32_t P = pow2ceil_dev(nc);
-      for (uint32_t i = lane; i < P; i += kWave)
-        S[i] = i < nc ? (C[i] & ~1ull) : kInf;
+    uint32_t* oid = a.out_ids + (size_t)qi * a.k;
+    float* od = a.out_dists + (size_t)qi * a.k;
+    if (pow2ceil_dev(nc) <= a.s_cap) {
+      // sort in LDS (table region + both worklist buffers, free now)
+      if (nc > a.c_max) {
+        // keep the c_max smallest (PQ distance, id)
+        const uint32_t P = pow2ceil_dev(nc);
+        for (uint32_t i = lane; i < P; i += kWave)
+          S[i] = i < nc ? (C[i] & ~1ull) : kInf;
+        __syncthreads();
+        lds_sort(S, P, lane);
+        nc = a.c_max;
+      } else {
+        for (uint32_t i = lane; i < nc; i += kWave) S[i] = C[i] & ~1ull;
+      }
       __syncthreads();
-      lds_sort(S, P, lane);
-      nc = a.c_max;
+      for (uint32_t i = lane; i < nc; i += kWave) {
+        const uint32_t id = key_id(S[i]);
+        S[i] = make_key(exact_dist<DT, D>(a.base, id, q), id);
+      }
+      __syncthreads();
+      sort_and_emit(S, nc, a.k, oid, od, lane);
     } else {
-      for (uint32_t i = lane; i < nc; i += kWave) S[i] = C[i] & ~1ull;
+      // too many to sort in LDS: select in the candidate buffer itself
+      for (uint32_t i = lane; i < nc; i += kWave) C[i] &= ~1ull;
+      __threadfence();
+      __syncthreads();
+      if (nc > a.c_max) {
+        global_select(C, nc, a.c_max, lane);
+        nc = a.c_max;
+      }
+      for (uint32_t i = lane; i < nc; i += kWave) {
+        const uint32_t id = key_id(C[i]);
+        C[i] = make_key(exact_dist<DT, D>(a.base, id, q), id);
+      }
+      __threadfence();
+      __syncthreads();
+      global_select(C, nc, a.k, lane);
+      for (uint32_t i = lane; i < a.k; i += kWave) {
+        const uint64_t key = i < nc ? C[i] : kInf;
+        oid[i] = key == kInf ? kNone : key_id(key);
+        od[i] = key == kInf ? __uint_as_float(0x7F800000u) : key_dist(key);
+      }
     }
-    __syncthreads();
-    for (uint32_t i = lane; i < nc; i += kWave) {
-      uint32_t id = key_id(S[i]);
-      S[i] = make_key(exact_dist<DT, D>(a.base, id, q), id);
-    }
-    __syncthreads();
-    sort_and_emit(S, nc, a.k, a.out_ids + (size_t)qi * a.k,
-                  a.out_dists + (size_t)qi * a.k, lane);
     if (a.out_times && lane == 0) {
       a.out_times[qi * 2] = t_begin;
       a.out_times[qi * 2 + 1] = wall_clock64();
@@ -793,6 +864,15 @@ hipError_t dispatch(int dt, uint32_t m, uint32_t ds, Args&&... args) {
   return hipErrorInvalidValue;
 }
 
+// Dynamic LDS above 64 KB per workgroup has to be enabled per kernel.
+template <typename K>
+hipError_t allow_lds(K kernel, size_t lds) {
+  if (lds <= 64 * 1024) return hipSuccess;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)lds);
+}
+
 template <int DT, int M, int DS>
 struct RunSearch {
   static hipError_t run(const SearchArgs& a, int table, uint32_t grid,
@@ -817,19 +897,25 @@ struct RunSearch {
   }
 };
 
+template <typename K>
+hipError_t occupancy_of(K kernel, size_t lds, int* per_cu) {
+  hipError_t e = allow_lds(kernel, lds);
+  if (e != hipSuccess) return e;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, kernel, kWave,
+                                                      lds);
+}
+
+// Also enables the kernel's LDS size, so it precedes every launch.
 template <int DT, int M, int DS>
 struct Occupancy {
   static hipError_t run(int table, size_t lds, int* per_cu) {
     switch (table) {
       case kTabF32:
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            per_cu, search_kernel<DT, M, DS, kTabF32>, kWave, lds);
+        return occupancy_of(search_kernel<DT, M, DS, kTabF32>, lds, per_cu);
       case kTabF16:
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            per_cu, search_kernel<DT, M, DS, kTabF16>, kWave, lds);
+        return occupancy_of(search_kernel<DT, M, DS, kTabF16>, lds, per_cu);
       case kTabU8:
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            per_cu, search_kernel<DT, M, DS, kTabU8>, kWave, lds);
+        return occupancy_of(search_kernel<DT, M, DS, kTabU8>, lds, per_cu);
     }
     return hipErrorInvalidValue;
   }
@@ -877,30 +963,35 @@ bool supported(int dtype, uint32_t m, uint32_t ds) {
   return false;
 }
 
-static uint32_t lblock_for(uint32_t L) { return (L + kWave - 1) / kWave; }
+static uint32_t lblock_for(uint32_t L) {
+  const uint32_t b = (L + kWave - 1) / kWave;
+  return b < (uint32_t)kPer ? b : (uint32_t)kPer;
+}
+
+static uint32_t lrow_for(uint32_t L) {
+  const uint32_t sup = kWave * lblock_for(L);
+  return (L + sup - 1) / sup * sup;
+}
 
 static size_t table_entry_bytes(int table) {
   return table == kTabF32 ? 4 : (table == kTabF16 ? 2 : 1);
 }
 
-static size_t region0_bytes(uint32_t m, uint32_t L, uint32_t iter_cap,
-                            int tab) {
-  // the table (plus the u8 form's m offsets), later the re-rank keys
-  size_t table = (size_t)m * 256 * table_entry_bytes(tab) +
-                 (tab == kTabU8 ? (size_t)m * 4 : 0);
-  table = (table + 15) / 16 * 16;
-  // re-rank keys: all expanded nodes when they exceed c_max (at most
-  // iter_cap), else at most c_max <= 4*L; both padded to a power of two
-  size_t sort = (size_t)pow2ceil(iter_cap > 4 * L ? iter_cap : 4 * L) * 8;
-  return table > sort ? table : sort;
+// Table region: the table (plus the u8 form's m offsets).  After the search
+// the re-rank sorts its keys in this region and the two worklist buffers
+// behind it when they fit (else it selects in global memory).
+static size_t region0_bytes(uint32_t m, int tab) {
+  const size_t table = (size_t)m * 256 * table_entry_bytes(tab) +
+                       (tab == kTabU8 ? (size_t)m * 4 : 0);
+  return (table + 15) / 16 * 16;
 }
 
 size_t search_lds_bytes(uint32_t m, uint32_t L, uint32_t iter_cap,
                         int table) {
-  const size_t B = lblock_for(L);
-  const size_t hist = ((kWave * B + 1) * 4 + 15) / 16 * 16;
-  return region0_bytes(m, L, iter_cap, table) + 2 * kWave * B * 8 +
-         (kWave + 4) * 8 + hist;
+  (void)iter_cap;
+  const size_t lrow = lrow_for(L);
+  const size_t hist = ((lrow + 4) * 4 + 15) / 16 * 16;
+  return region0_bytes(m, table) + 2 * lrow * 8 + (kWave + 4) * 8 + hist;
 }
 
 uint32_t row_ids_bytes(uint32_t R) { return (4 * R + 15) / 16 * 16; }
@@ -950,7 +1041,9 @@ hipError_t launch_search(const DeviceIndex& ix, const SearchLaunch& l,
   a.c_max = l.c_max;
   a.iter_cap = l.iter_cap;
   a.lblock = lblock_for(l.L);
-  a.region0 = (uint32_t)region0_bytes(ix.m, l.L, l.iter_cap, l.table);
+  a.lrow = lrow_for(l.L);
+  a.region0 = (uint32_t)region0_bytes(ix.m, l.table);
+  a.s_cap = (l.flags & 1u) ? 0u : (a.region0 + 16u * a.lrow) / 8u;
   a.out_ids = l.out_ids;
   a.out_dists = l.out_dists;
   a.out_cand = l.out_cand;

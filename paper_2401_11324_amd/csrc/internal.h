@@ -25,6 +25,7 @@ struct SearchLaunch {
   uint64_t nq;
   uint32_t k, L, c_max, iter_cap;
   int table;             // 0 FP32, 1 FP16, 2 U8 (bang_search_opts.table)
+  uint32_t flags;        // bang_search_opts.flags
   uint32_t* out_ids;
   float* out_dists;
   uint32_t* out_cand;

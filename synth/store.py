@@ -31,6 +31,15 @@ DEFAULT_ROOT = os.environ.get(
                  "indexcache"))
 ARRAYS = ("codebooks", "codes", "adj", "gt_ids", "gt_dists")
 FORMAT_VERSION = 1
+# search-time parameters: they do not change the stored index
+SEARCH_ONLY = ("Ls", "k")
+
+
+def _index_params(w) -> dict:
+    d = json.loads(json.dumps(dataclasses.asdict(w)))
+    for key in SEARCH_ONLY:
+        d.pop(key, None)
+    return d
 
 
 def digest(a: np.ndarray) -> str:
@@ -74,8 +83,10 @@ def exists(w: Workload, root: str | None = None) -> bool:
         return False
     with open(os.path.join(p, "manifest.json")) as f:
         man = json.load(f)
-    return (man.get("format") == FORMAT_VERSION
-            and man["workload"] == json.loads(json.dumps(dataclasses.asdict(w))))
+    stored = dict(man["workload"])
+    for key in SEARCH_ONLY:
+        stored.pop(key, None)
+    return man.get("format") == FORMAT_VERSION and stored == _index_params(w)
 
 
 def load(w: Workload, root: str | None = None, verify: bool = True,
@@ -86,7 +97,10 @@ def load(w: Workload, root: str | None = None, verify: bool = True,
         man = json.load(f)
     if man.get("format") != FORMAT_VERSION:
         raise ValueError(f"{p}: index format {man.get('format')} is stale")
-    if man["workload"] != json.loads(json.dumps(dataclasses.asdict(w))):
+    stored = dict(man["workload"])
+    for key in SEARCH_ONLY:
+        stored.pop(key, None)
+    if stored != _index_params(w):
         raise ValueError(f"{p}: built for different workload parameters")
     out = {"medoid": int(man["medoid"]), "manifest": man}
     for name in ARRAYS:

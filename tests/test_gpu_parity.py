@@ -79,12 +79,12 @@ def f32bits(a):
 
 
 def run_and_compare(ix, gi, q, k, L, c_max=0, iter_cap=0, label="",
-                    table="f32"):
+                    table="f32", rerank_global=False):
     cap = iter_cap or oracle.iter_cap_for(L)
     qt = to_dev(q)
     ids, d, cand, cnt = gi.search(qt, k, L, c_max=c_max, iter_cap=iter_cap,
                                   want_cand=cap, want_counters=True,
-                                  table=table)
+                                  table=table, rerank_global=rerank_global)
     torch.cuda.synchronize()
     ref = oracle.search(ix, q, k, L, c_max=c_max or None,
                         iter_cap=iter_cap or None, want_cand=True,
@@ -115,7 +115,8 @@ def test_tables_bit_exact(small_indexes, name):
 # --------------------------------------------------------------------------
 @pytest.mark.parametrize("name", list(SMALL))
 @pytest.mark.parametrize("k,L", [(1, 1), (10, 10), (10, 16), (5, 33),
-                                 (10, 64), (10, 100), (32, 256)])
+                                 (10, 64), (10, 100), (32, 256), (10, 300),
+                                 (100, 1024)])
 def test_search_bit_exact(small_indexes, name, k, L):
     ix, q, gi = small_indexes[name]
     run_and_compare(ix, gi, q, k, L, label=f"{name} k={k} L={L}")
@@ -124,7 +125,7 @@ def test_search_bit_exact(small_indexes, name, k, L):
 @pytest.mark.parametrize("table", ["f16", "u8"])
 @pytest.mark.parametrize("name", list(SMALL))
 @pytest.mark.parametrize("k,L", [(1, 1), (10, 16), (5, 33), (10, 100),
-                                 (32, 256)])
+                                 (32, 256), (10, 600)])
 def test_precision_form_bit_exact(small_indexes, name, k, L, table):
     """The precision form's half / u8 tables are derived from the canonical
     FP32 entries on both sides, so the search stays bit-exact."""
@@ -143,6 +144,17 @@ def test_iteration_cap_and_candidate_cap(small_indexes, name):
     assert (ref["status"] == 1).all()
     ref = run_and_compare(ix, gi, q, 10, 64, c_max=12)
     assert (ref["iters"] > 12).all()
+
+
+@pytest.mark.parametrize("name", ["u8-d64-m16", "f32-d32-m16"])
+@pytest.mark.parametrize("k,L,c_max", [(10, 64, 0), (10, 64, 12),
+                                       (100, 300, 0)])
+def test_rerank_in_device_memory_bit_exact(small_indexes, name, k, L, c_max):
+    """The re-rank's device-memory selection (taken when the expanded set
+    does not fit on chip) returns the same results as the LDS sort."""
+    ix, q, gi = small_indexes[name]
+    run_and_compare(ix, gi, q, k, L, c_max=c_max, rerank_global=True,
+                    label=f"{name} k={k} L={L} c_max={c_max} global")
 
 
 def test_short_results_are_padded():
@@ -170,11 +182,15 @@ def test_invalid_arguments_raise(small_indexes):
     bang = bang_mod()
     ix, q, gi = small_indexes["u8-d64-m16"]
     qt = to_dev(q)
-    for k, L in [(0, 10), (11, 10), (10, 257)]:
+    for k, L in [(0, 10), (11, 10), (10, 1025)]:
         with pytest.raises(bang.BangError):
             gi.search(qt, k, L)
     with pytest.raises(TypeError):
         gi.search(qt.float(), 10, 32)
+    small = torch.empty((len(q), 5), dtype=torch.int32, device=qt.device)
+    d = torch.empty((len(q), 5), dtype=torch.float32, device=qt.device)
+    with pytest.raises(ValueError):
+        gi.search(qt, 10, 32, out=(small, d))
 
 
 def test_deterministic_and_independent_of_batch_order(small_indexes):
@@ -251,8 +267,8 @@ def test_sift1m_full_batch_sampled_bit_exact():
     qt = to_dev(q)
     sample = np.sort(np.random.default_rng(2024).choice(len(q), 160,
                                                         replace=False))
-    for L, table in [(L, "f32") for L in w.Ls] + [(64, "f16"), (64, "u8"),
-                                                   (256, "u8")]:
+    for L, table in [(L, "f32") for L in w.Ls if L <= 256] + [
+            (64, "f16"), (64, "u8"), (256, "u8"), (768, "u8")]:
         cap = oracle.iter_cap_for(L)
         ids, dist, cand, cnt = gi.search(qt, w.k, L, want_cand=cap,
                                          want_counters=True, table=table)
