@@ -475,8 +475,8 @@ struct SearchArgs {
   uint32_t lblock;   // worklist entries per lane in a super-row, <= kPer
   uint32_t lrow;     // worklist buffer entries: Lcap rounded up to 64*lblock
   uint32_t region0;  // bytes of the table region (re-rank keys reuse it
-                     // together with both worklist buffers)
-  uint32_t s_cap;    // keys that fit there: (region0 + 16 * lrow) / 8, or
+                     // together with the worklist buffer)
+  uint32_t s_cap;    // keys that fit there: (region0 + 8 * lrow) / 8, or
                      // 0 to make the re-rank select in global memory
   uint32_t* out_ids;
   float* out_dists;
@@ -521,12 +521,15 @@ __global__ __launch_bounds__(kWave) void search_kernel(SearchArgs a) {
   uint64_t* S = reinterpret_cast<uint64_t*>(smem);  // re-rank keys
   const uint32_t B = a.lblock;
   const uint32_t sup = kWave * B;  // super-row size
-  uint64_t* Lb0 = reinterpret_cast<uint64_t*>(smem + a.region0);
-  uint64_t* Lb1 = Lb0 + a.lrow;
-  uint64_t* Nb = Lb1 + a.lrow;                                // kWave + 4
-  uint32_t* H = reinterpret_cast<uint32_t*>(Nb + kWave + 4);  // lrow + 4
+  // the worklist (merged in place), the live new keys, and a histogram of
+  // the live keys' worklist ranks: one byte per position (a count is at
+  // most 64), added to as 32-bit words
+  uint64_t* Lc = reinterpret_cast<uint64_t*>(smem + a.region0);  // lrow
+  uint64_t* Nb = Lc + a.lrow;                                     // kWave + 4
+  uint8_t* H = reinterpret_cast<uint8_t*>(Nb + kWave + 4);        // lrow + 4
+  uint32_t* Hw = reinterpret_cast<uint32_t*>(H);
   uint64_t* C = a.cscratch + (size_t)blockIdx.x * a.iter_cap;
-  for (uint32_t t = lane; t < a.lrow + 4; t += kWave) H[t] = 0u;
+  for (uint32_t t = lane; t < (a.lrow + 4) / 4; t += kWave) Hw[t] = 0u;
 
   for (;;) {
     uint32_t qi = 0;
@@ -562,8 +565,6 @@ __global__ __launch_bounds__(kWave) void search_kernel(SearchArgs a) {
     for (int i = 0; i < M / 16; ++i)
       scode[i] = reinterpret_cast<const uint4*>(a.codes + (size_t)s * M)[i];
     uint64_t curkey = make_key(adc_codes<M, TT>(T, scode), s);
-    uint64_t* Lc = Lb0;
-    uint64_t* Ln = Lb1;
     if (lane == 0) Lc[0] = curkey;
     uint32_t Llen = 1, cur = 0, iters = 0, status = 0;
     __syncthreads();
@@ -661,7 +662,7 @@ __global__ __launch_bounds__(kWave) void search_kernel(SearchArgs a) {
           (uint32_t)(km >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)km, 0u));
       if (keep) {
         Nb[idx] = kk;  // the live keys, compacted
-        atomicAdd(&H[r], 1u);
+        atomicAdd(&Hw[r >> 2], 1u << (8 * (r & 3)));
       }
       if (lane < 4) Nb[nv + lane] = kInf;  // pad to a multiple of 4
       __syncthreads();
@@ -676,40 +677,66 @@ __global__ __launch_bounds__(kWave) void search_kernel(SearchArgs a) {
       // merge: position = own index + rank in the other list.  New keys
       // below worklist entry j = H[0] + ... + H[j] (live keys whose
       // worklist rank is <= j): a prefix over super-rows of 64*B entries.
-      if (keep && r + rn < a.Lcap) Ln[r + rn] = key;
-      uint32_t carry = 0;
-      for (uint32_t base = 0; base < Llen; base += sup) {
+      // In place: entries only move right, so the super-rows are moved from
+      // the last to the first, each read completely before it is written;
+      // the new keys go last, into the gaps.  Pass 1 gets each super-row's
+      // prefix from the histogram alone.
+      const uint32_t nsup = (Llen + sup - 1) / sup;
+      uint32_t carry_at[kPer];  // prefix before super-row s (s < 4 rows)
+      uint32_t excl_at[kPer];
+      uint32_t hb_at[kPer];     // this lane's B histogram bytes, per row
+      {
+        uint32_t carry = 0;
+#pragma unroll
+        for (int sr = 0; sr < kPer; ++sr) {
+          carry_at[sr] = carry;
+          excl_at[sr] = 0;
+          hb_at[sr] = 0;
+          if ((uint32_t)sr < nsup) {
+            const uint32_t base = sr * sup;
+            uint32_t tot = 0, hb = 0;
+#pragma unroll
+            for (int t = 0; t < kPer; ++t) {
+              const uint32_t j = base + B * lane + t;
+              if ((uint32_t)t < B && j < Llen) {
+                const uint32_t h = H[j];
+                tot += h;
+                hb |= h << (8 * t);
+              }
+            }
+            const uint32_t excl = wave_exclusive_scan(tot);
+            excl_at[sr] = excl;
+            hb_at[sr] = hb;
+            carry += __builtin_amdgcn_readlane(excl + tot, kWave - 1);
+          }
+        }
+      }
+      for (int sr = (int)nsup - 1; sr >= 0; --sr) {
+        const uint32_t base = sr * sup;
         uint64_t v[kPer];
-        uint32_t sh[kPer];
-        uint32_t tot = 0;
 #pragma unroll
         for (int t = 0; t < kPer; ++t) {
           const uint32_t j = base + B * lane + t;
           v[t] = base == sbase ? lk[t]
                                : (((uint32_t)t < B && j < Llen) ? Lc[j] : kInf);
           if (j == cur) v[t] |= 1ull;  // u*, marked visited
-          if ((uint32_t)t < B) {
-            if (j < Llen) tot += H[j];
-            H[j] = 0u;
-          }
-          sh[t] = tot;
         }
-        const uint32_t excl = wave_exclusive_scan(tot);
+        __syncthreads();  // the whole super-row is read before it moves
+        uint32_t sh = 0;
 #pragma unroll
         for (int t = 0; t < kPer; ++t) {
           const uint32_t j = base + B * lane + t;
+          sh += (hb_at[sr] >> (8 * t)) & 0xFFu;
           if (v[t] != kInf) {
-            const uint32_t p = j + carry + excl + sh[t];
-            if (p < a.Lcap) Ln[p] = v[t];
+            const uint32_t p = j + carry_at[sr] + excl_at[sr] + sh;
+            if (p < a.Lcap) Lc[p] = v[t];
           }
         }
-        carry += __builtin_amdgcn_readlane(excl + tot, kWave - 1);
       }
-      if (lane == 0) H[Llen] = 0u;
+      if (keep && r + rn < a.Lcap) Lc[r + rn] = key;
+      // clear the histogram bytes used (positions 0 .. Llen)
+      for (uint32_t t = lane; t <= Llen / 4; t += kWave) Hw[t] = 0u;
       Llen = min(a.Lcap, Llen + nv);
-      uint64_t* tmp = Lc;
-      Lc = Ln;
-      Ln = tmp;
       cur = best;
       curkey = bestkey;
       __syncthreads();
@@ -733,7 +760,7 @@ __global__ __launch_bounds__(kWave) void search_kernel(SearchArgs a) {
     uint32_t* oid = a.out_ids + (size_t)qi * a.k;
     float* od = a.out_dists + (size_t)qi * a.k;
     if (pow2ceil_dev(nc) <= a.s_cap) {
-      // sort in LDS (table region + both worklist buffers, free now)
+      // sort in LDS (table region + worklist buffer, free now)
       if (nc > a.c_max) {
         // keep the c_max smallest (PQ distance, id)
         const uint32_t P = pow2ceil_dev(nc);
@@ -978,8 +1005,8 @@ static size_t table_entry_bytes(int table) {
 }
 
 // Table region: the table (plus the u8 form's m offsets).  After the search
-// the re-rank sorts its keys in this region and the two worklist buffers
-// behind it when they fit (else it selects in global memory).
+// the re-rank sorts its keys in this region and the worklist buffer behind
+// it when they fit (else it selects in global memory).
 static size_t region0_bytes(uint32_t m, int tab) {
   const size_t table = (size_t)m * 256 * table_entry_bytes(tab) +
                        (tab == kTabU8 ? (size_t)m * 4 : 0);
@@ -990,8 +1017,8 @@ size_t search_lds_bytes(uint32_t m, uint32_t L, uint32_t iter_cap,
                         int table) {
   (void)iter_cap;
   const size_t lrow = lrow_for(L);
-  const size_t hist = ((lrow + 4) * 4 + 15) / 16 * 16;
-  return region0_bytes(m, table) + 2 * lrow * 8 + (kWave + 4) * 8 + hist;
+  const size_t hist = (lrow + 4 + 15) / 16 * 16;
+  return region0_bytes(m, table) + lrow * 8 + (kWave + 4) * 8 + hist;
 }
 
 uint32_t row_ids_bytes(uint32_t R) { return (4 * R + 15) / 16 * 16; }
@@ -1043,7 +1070,7 @@ hipError_t launch_search(const DeviceIndex& ix, const SearchLaunch& l,
   a.lblock = lblock_for(l.L);
   a.lrow = lrow_for(l.L);
   a.region0 = (uint32_t)region0_bytes(ix.m, l.table);
-  a.s_cap = (l.flags & 1u) ? 0u : (a.region0 + 16u * a.lrow) / 8u;
+  a.s_cap = (l.flags & 1u) ? 0u : (a.region0 + 8u * a.lrow) / 8u;
   a.out_ids = l.out_ids;
   a.out_dists = l.out_dists;
   a.out_cand = l.out_cand;
