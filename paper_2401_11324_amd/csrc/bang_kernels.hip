@@ -331,11 +331,10 @@ __device__ __forceinline__ uint64_t shfl_xor64(uint64_t v, int m) {
   return ((uint64_t)hi << 32) | lo;
 }
 
-__device__ __forceinline__ uint64_t shfl64(uint64_t v, int src) {
-  uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
-  lo = __shfl(lo, src);
-  hi = __shfl(hi, src);
-  return ((uint64_t)hi << 32) | lo;
+// v of the lowest lane set in the wave-uniform mask (nonzero): a scalar
+// read of one lane, no LDS round trip.
+__device__ __forceinline__ uint32_t first_of(uint32_t v, uint64_t mask) {
+  return __builtin_amdgcn_readlane(v, __builtin_ctzll(mask));
 }
 
 // Cross-lane helpers on DPP (data-parallel primitives; no LDS round trip).
@@ -451,7 +450,7 @@ __device__ void global_select(uint64_t* C, uint32_t n, uint32_t kk, int lane) {
     }
     const uint64_t m = wave_min64(best);
     const uint64_t who = __ballot(best == m && at != kNone);
-    const uint32_t src = __shfl(at, __ffsll((unsigned long long)who) - 1);
+    const uint32_t src = first_of(at, who);
     if (lane == 0 && src != kNone && src != r) {
       const uint64_t t = C[r];
       C[r] = m;
@@ -609,31 +608,43 @@ __global__ __launch_bounds__(kWave) void search_kernel(SearchArgs a) {
       // when it is the smaller; b is cut when its worklist rank reaches L,
       // and then a is cut too.  Its merged position is a's index or b's rank.
       uint32_t apos = kNone;
+      uint64_t akey = kInf;
       {
         uint32_t ja = kNone;
+        uint64_t va = kInf;
 #pragma unroll
         for (int t = kPer - 1; t >= 0; --t) {
           const uint32_t j = sbase + B * lane + t;
-          if (lk[t] != kInf && j != cur && !(lk[t] & 1ull)) ja = j;
+          if (lk[t] != kInf && j != cur && !(lk[t] & 1ull)) {
+            ja = j;
+            va = lk[t];
+          }
         }
         uint64_t am = __ballot(ja != kNone);
         for (uint32_t base = sbase + sup; !am && base < Llen; base += sup) {
 #pragma unroll
           for (int t = kPer - 1; t >= 0; --t) {
             const uint32_t j = base + B * lane + t;
-            if ((uint32_t)t < B && j < Llen && !(Lc[j] & 1ull)) ja = j;
+            const uint64_t v = ((uint32_t)t < B && j < Llen) ? Lc[j] : 1ull;
+            if (!(v & 1ull)) {
+              ja = j;
+              va = v;
+            }
           }
           am = __ballot(ja != kNone);
         }
-        if (am) apos = __shfl(ja, __ffsll((unsigned long long)am) - 1);
+        if (am) {
+          apos = first_of(ja, am);
+          akey = ((uint64_t)first_of((uint32_t)(va >> 32), am) << 32) |
+                 first_of((uint32_t)va, am);
+        }
       }
-      const uint64_t akey = apos != kNone ? Lc[apos] : kInf;
       const uint64_t bkey = wave_min64(kk);
       uint32_t best = kNone;
       uint64_t bestkey = kInf;
       if (bkey < akey) {
         const uint64_t bl = __ballot(kk == bkey);
-        const uint32_t bpos = __shfl(r, __ffsll((unsigned long long)bl) - 1);
+        const uint32_t bpos = first_of(r, bl);
         if (bpos < a.Lcap) {
           best = bpos;
           bestkey = bkey;
@@ -658,6 +669,8 @@ __global__ __launch_bounds__(kWave) void search_kernel(SearchArgs a) {
         __syncthreads();
         continue;
       }
+      // smallest worklist rank of a live key (b's): entries below it stay
+      const uint32_t rmin = first_of(r, __ballot(kk == bkey));
       const uint32_t idx = __builtin_amdgcn_mbcnt_hi(
           (uint32_t)(km >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)km, 0u));
       if (keep) {
@@ -682,6 +695,7 @@ __global__ __launch_bounds__(kWave) void search_kernel(SearchArgs a) {
       // the new keys go last, into the gaps.  Pass 1 gets each super-row's
       // prefix from the histogram alone.
       const uint32_t nsup = (Llen + sup - 1) / sup;
+      const uint32_t s0 = rmin / sup;  // first super-row with a moving entry
       uint32_t carry_at[kPer];  // prefix before super-row s (s < 4 rows)
       uint32_t excl_at[kPer];
       uint32_t hb_at[kPer];     // this lane's B histogram bytes, per row
@@ -692,7 +706,7 @@ __global__ __launch_bounds__(kWave) void search_kernel(SearchArgs a) {
           carry_at[sr] = carry;
           excl_at[sr] = 0;
           hb_at[sr] = 0;
-          if ((uint32_t)sr < nsup) {
+          if ((uint32_t)sr < nsup && (uint32_t)sr >= s0) {
             const uint32_t base = sr * sup;
             uint32_t tot = 0, hb = 0;
 #pragma unroll
@@ -711,7 +725,7 @@ __global__ __launch_bounds__(kWave) void search_kernel(SearchArgs a) {
           }
         }
       }
-      for (int sr = (int)nsup - 1; sr >= 0; --sr) {
+      for (int sr = (int)nsup - 1; sr >= (int)s0; --sr) {
         const uint32_t base = sr * sup;
         uint64_t v[kPer];
 #pragma unroll
@@ -734,8 +748,8 @@ __global__ __launch_bounds__(kWave) void search_kernel(SearchArgs a) {
         }
       }
       if (keep && r + rn < a.Lcap) Lc[r + rn] = key;
-      // clear the histogram bytes used (positions 0 .. Llen)
-      for (uint32_t t = lane; t <= Llen / 4; t += kWave) Hw[t] = 0u;
+      // clear the histogram bytes used (positions rmin .. Llen)
+      for (uint32_t t = rmin / 4 + lane; t <= Llen / 4; t += kWave) Hw[t] = 0u;
       Llen = min(a.Lcap, Llen + nv);
       cur = best;
       curkey = bestkey;
