@@ -379,17 +379,40 @@ __device__ __forceinline__ uint64_t wave_min64(uint64_t v) {
   return ((uint64_t)hi << 32) | lo;
 }
 
-// Number of entries of the sorted LDS list A[0..len) whose key, visited bit
-// ignored, is below x's (len <= 1024), by binary lifting.
+// Number P of entries of the sorted LDS list A[0..len) whose key, visited
+// bit ignored, is below x's (1 <= len <= 1024, last = A[len-1]), and in ge
+// the entry A[P] (kInf when P = len).  (a >> 1) < (x >> 1) is tested as
+// a < (x & ~1).  Radix-4 lifting: three independent probes per level, half
+// the dependent LDS reads of a binary search.  The probe at index P is the
+// first failing one of the last level that fails, so ge comes for free;
+// probes past A[len-2] read as `last`, which is known not to be below x.
 __device__ __forceinline__ uint32_t rank_in(const uint64_t* A, uint32_t len,
-                                            uint64_t x) {
-  const uint64_t xs = x >> 1;
-  uint32_t pos = 0;
-  for (uint32_t step = 1024; step > 0; step >>= 1) {
-    if (step > len) continue;
-    uint32_t np = pos + step;
-    if (np <= len && (A[np - 1] >> 1) < xs) pos = np;
+                                            uint64_t last, uint64_t x,
+                                            uint64_t& ge) {
+  const uint64_t xs = x & ~1ull;
+  if (last < xs) {
+    ge = kInf;
+    return len;
   }
+  const uint32_t lim = len - 1;  // the answer is at most lim
+  uint32_t pos = 0;
+  uint64_t g = last;
+  for (uint32_t s = 256; s > 0; s >>= 2) {
+    if (s > lim) continue;
+    const uint32_t i1 = pos + s - 1, i2 = i1 + s, i3 = i2 + s;
+    const uint64_t v1 = i1 < lim ? A[i1] : last;
+    const uint64_t v2 = i2 < lim ? A[i2] : last;
+    const uint64_t v3 = i3 < lim ? A[i3] : last;
+    const bool p1 = v1 < xs, p2 = v2 < xs, p3 = v3 < xs;
+    if (!p1)
+      g = v1;
+    else if (!p2)
+      g = v2;
+    else if (!p3)
+      g = v3;
+    pos += s * ((uint32_t)p1 + (uint32_t)p2 + (uint32_t)p3);
+  }
+  ge = g;
   return pos;
 }
 
@@ -587,6 +610,7 @@ __global__ __launch_bounds__(kWave) void search_kernel(SearchArgs a) {
         const uint32_t j = sbase + B * lane + t;
         lk[t] = ((uint32_t)t < B && j < Llen) ? Lc[j] : kInf;
       }
+      const uint64_t last = Lc[Llen - 1];
 
       // distances of the neighbours (row of u*, loaded earlier)
       uint64_t key = kInf;
@@ -598,8 +622,9 @@ __global__ __launch_bounds__(kWave) void search_kernel(SearchArgs a) {
       uint32_t r = 0;
       bool keep = false;
       if (key != kInf) {
-        r = rank_in(Lc, Llen, key);
-        keep = !(r < Llen && (Lc[r] >> 1) == (key >> 1)) && r < a.Lcap;
+        uint64_t ge;
+        r = rank_in(Lc, Llen, last, key, ge);
+        keep = (ge >> 1) != (key >> 1) && r < a.Lcap;
       }
       const uint64_t kk = keep ? key : kInf;
 
