@@ -262,20 +262,28 @@ __device__ __forceinline__ void build_table_q(const unsigned char* q,
 // for U8 the exact integer sum, returned as FP32 (exact below 2^24).
 template <int M, int TT>
 __device__ __forceinline__ float adc_codes(const void* Tv, const uint4 (&v)[M / 16]) {
-  const typename Tab<TT>::E* T = reinterpret_cast<const typename Tab<TT>::E*>(Tv);
-  float acc = 0.0f;
-  uint32_t iacc = 0;
+  using E = typename Tab<TT>::E;
+  const E* T = reinterpret_cast<const E*>(Tv);
+  // all M lookups are issued before the first add, so their LDS latencies
+  // overlap; the adds then run in subspace order
+  E e[M];
 #pragma unroll
   for (int c = 0; c < M / 16; ++c) {
     const uint32_t w[4] = {v[c].x, v[c].y, v[c].z, v[c].w};
 #pragma unroll
     for (int b = 0; b < 16; ++b) {
       const uint32_t byte = (w[b >> 2] >> (8 * (b & 3))) & 0xFFu;
-      const auto e = T[(16 * c + b) * 256 + byte];
-      if constexpr (TT == kTabF32) acc = acc + e;
-      else if constexpr (TT == kTabF16) acc = acc + f16_bits_to_f32(e);
-      else iacc += e;
+      e[16 * c + b] = T[(16 * c + b) * 256 + byte];
     }
+  }
+  __builtin_amdgcn_sched_barrier(0);
+  float acc = 0.0f;
+  uint32_t iacc = 0;
+#pragma unroll
+  for (int j = 0; j < M; ++j) {
+    if constexpr (TT == kTabF32) acc = acc + e[j];
+    else if constexpr (TT == kTabF16) acc = acc + f16_bits_to_f32(e[j]);
+    else iacc += e[j];
   }
   return TT == kTabU8 ? (float)iacc : acc;
 }
@@ -385,7 +393,8 @@ __device__ __forceinline__ uint64_t wave_min64(uint64_t v) {
 // a < (x & ~1).  Radix-4 lifting: three independent probes per level, half
 // the dependent LDS reads of a binary search.  The probe at index P is the
 // first failing one of the last level that fails, so ge comes for free;
-// probes past A[len-2] read as `last`, which is known not to be below x.
+// probes past A[len-2] are clamped to A[len-1] = last, which is known not
+// to be below x (a clamp instead of a branch).
 __device__ __forceinline__ uint32_t rank_in(const uint64_t* A, uint32_t len,
                                             uint64_t last, uint64_t x,
                                             uint64_t& ge) {
@@ -400,9 +409,9 @@ __device__ __forceinline__ uint32_t rank_in(const uint64_t* A, uint32_t len,
   for (uint32_t s = 256; s > 0; s >>= 2) {
     if (s > lim) continue;
     const uint32_t i1 = pos + s - 1, i2 = i1 + s, i3 = i2 + s;
-    const uint64_t v1 = i1 < lim ? A[i1] : last;
-    const uint64_t v2 = i2 < lim ? A[i2] : last;
-    const uint64_t v3 = i3 < lim ? A[i3] : last;
+    const uint64_t v1 = A[min(i1, lim)];
+    const uint64_t v2 = A[min(i2, lim)];
+    const uint64_t v3 = A[min(i3, lim)];
     const bool p1 = v1 < xs, p2 = v2 < xs, p3 = v3 < xs;
     if (!p1)
       g = v1;
@@ -532,8 +541,19 @@ __device__ __forceinline__ void load_row(const SearchArgs& a, uint32_t u,
   }
 }
 
+// Waves per SIMD that the table alone still lets share a CU's 160 KB of
+// LDS: the register allocator may spend up to that share, so it keeps more
+// LDS reads in flight where few waves are resident anyway.
+constexpr int max_waves_per_simd(int table_bytes) {
+  const int per_cu = (160 * 1024) / (table_bytes + 1280);
+  const int w = (per_cu + 3) / 4;
+  return w < 1 ? 1 : (w > 8 ? 8 : w);
+}
+
 template <int DT, int M, int DS, int TT>
-__global__ __launch_bounds__(kWave) void search_kernel(SearchArgs a) {
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(
+    1, max_waves_per_simd(M * 256 * (int)sizeof(typename Tab<TT>::E)))))
+void search_kernel(SearchArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int D = M * DS;
   constexpr int kTableBytes = M * 256 * (int)sizeof(typename Tab<TT>::E);
@@ -602,13 +622,18 @@ __global__ __launch_bounds__(kWave) void search_kernel(SearchArgs a) {
         C[iters] = curkey;
       }
       ++iters;
-      // this lane's entries of the super-row holding u*
+      // this lane's entries of the super-row holding u* (reads past Llen
+      // stay inside the buffer, which ends on a super-row boundary)
       const uint32_t sbase = cur / sup * sup;
       uint64_t lk[kPer];
 #pragma unroll
       for (int t = 0; t < kPer; ++t) {
         const uint32_t j = sbase + B * lane + t;
-        lk[t] = ((uint32_t)t < B && j < Llen) ? Lc[j] : kInf;
+        lk[t] = kInf;
+        if ((uint32_t)t < B) {
+          const uint64_t v = Lc[j];
+          lk[t] = j < Llen ? v : kInf;
+        }
       }
       const uint64_t last = Lc[Llen - 1];
 
@@ -650,7 +675,9 @@ __global__ __launch_bounds__(kWave) void search_kernel(SearchArgs a) {
 #pragma unroll
           for (int t = kPer - 1; t >= 0; --t) {
             const uint32_t j = base + B * lane + t;
-            const uint64_t v = ((uint32_t)t < B && j < Llen) ? Lc[j] : 1ull;
+            if ((uint32_t)t >= B) continue;
+            const uint64_t x = Lc[j];
+            const uint64_t v = j < Llen ? x : 1ull;
             if (!(v & 1ull)) {
               ja = j;
               va = v;
@@ -736,9 +763,10 @@ __global__ __launch_bounds__(kWave) void search_kernel(SearchArgs a) {
             uint32_t tot = 0, hb = 0;
 #pragma unroll
             for (int t = 0; t < kPer; ++t) {
-              const uint32_t j = base + B * lane + t;
-              if ((uint32_t)t < B && j < Llen) {
-                const uint32_t h = H[j];
+              // bytes past Llen count keys appended after every entry or
+              // are zero; they move no entry
+              if ((uint32_t)t < B) {
+                const uint32_t h = H[base + B * lane + t];
                 tot += h;
                 hb |= h << (8 * t);
               }
@@ -756,8 +784,11 @@ __global__ __launch_bounds__(kWave) void search_kernel(SearchArgs a) {
 #pragma unroll
         for (int t = 0; t < kPer; ++t) {
           const uint32_t j = base + B * lane + t;
-          v[t] = base == sbase ? lk[t]
-                               : (((uint32_t)t < B && j < Llen) ? Lc[j] : kInf);
+          v[t] = kInf;
+          if ((uint32_t)t < B) {
+            const uint64_t x = base == sbase ? lk[t] : Lc[j];
+            v[t] = j < Llen ? x : kInf;
+          }
           if (j == cur) v[t] |= 1ull;  // u*, marked visited
         }
         __syncthreads();  // the whole super-row is read before it moves
