@@ -31,6 +31,8 @@ METRIC = ("QPS at recall@10>=0.9 on 1 GPU, plain FP32 vs reduced-precision "
           "form; p50/p99 ms")
 WORKLOAD = "sift1m"
 HBM_PEAK_GBS = 8000.0
+# MI355X's host link: PCIe 5.0 x16, 64 GB/s per direction
+HOST_LINK_PEAK_GBS = 64.0
 TARGET_RECALL = 0.9
 TABLES = ("f32", "f16", "u8")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "search_sift1m_traffic.json")
@@ -121,6 +123,8 @@ def main(argv=None):
                     help="skip the CPU oracle baseline")
     ap.add_argument("--no-sweep", action="store_true",
                     help="skip the recall sweep (needs --L)")
+    ap.add_argument("--no-host", action="store_true",
+                    help="skip the host-resident adjacency measurement")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB mebibytes "
                          "(calibrates the HBM byte counters) and exit")
@@ -181,19 +185,20 @@ def main(argv=None):
     adj_deg = (d["adj"] != 0xFFFFFFFF).sum(1)
     elem = 1 if w.dtype in ("u8", "i8") else 4
 
-    def measure(table, L):
+    def measure(table, L, index=None):
         """K timed steps of one form; returns its record."""
+        gi_ = index or gi
         ids = torch.empty((nq, k), dtype=torch.int32, device=dev)
         dist = torch.empty((nq, k), dtype=torch.float32, device=dev)
         for _ in range(a.warmup):
-            gi.search(q, k, L, out=(ids, dist), table=table)
+            gi_.search(q, k, L, out=(ids, dist), table=table)
         torch.cuda.synchronize()
         ev = [(torch.cuda.Event(enable_timing=True),
                torch.cuda.Event(enable_timing=True)) for _ in range(a.steps)]
         wall0 = time.perf_counter()
         for e0, e1 in ev:
             e0.record(stream)
-            gi.search(q, k, L, out=(ids, dist), table=table)
+            gi_.search(q, k, L, out=(ids, dist), table=table)
             e1.record(stream)
         torch.cuda.synchronize()
         wall = time.perf_counter() - wall0
@@ -201,7 +206,7 @@ def main(argv=None):
         rec = recall_at_k(ids.cpu().numpy().view(np.uint32), gt, k)
         # one more (untimed) launch with counters, expanded nodes, stamps
         cap = max(4 * L, L + 64)
-        _, _, cand, cnt, times = gi.search(q, k, L, want_cand=cap,
+        _, _, cand, cnt, times = gi_.search(q, k, L, want_cand=cap,
                                            want_counters=True,
                                            want_times=True, table=table)
         torch.cuda.synchronize()
@@ -217,6 +222,8 @@ def main(argv=None):
                               4 * L)
         ms_step = wall * 1e3 / a.steps
         return {"table": table, "L": L, "recall10": round(rec, 4),
+                "adjacency_bytes_per_launch": int(iters.astype(np.int64).sum()
+                                                  * 4 * w.R),
                 "qps": round(nq / (ms_step / 1e3), 1),
                 "ms_per_step": round(ms_step, 4),
                 "p50_ms": round(float(np.percentile(lat_ms, 50)), 4),
@@ -231,6 +238,21 @@ def main(argv=None):
     plain = measure("f32", pick_L("f32"))
     prec = {t: measure(t, pick_L(t)) for t in ("f16", "u8")}
     L = plain["L"]
+    host = None
+    if not a.no_host:
+        # the same search with the adjacency in pinned host memory, read
+        # across the host link (the paper's CPU-resident graph)
+        hi = bang.Index(d["base"], d["adj"], d["medoid"], d["codebooks"],
+                        d["codes"], host_adj=True)
+        host = measure("f32", L, index=hi)
+        hi.close()
+        link = host["adjacency_bytes_per_launch"] / (
+            host["kernel_ms_mean"] / 1e3) / 1e9
+        host["host_link"] = {
+            "bound": "host link", "achieved": round(link, 2),
+            "peak": HOST_LINK_PEAK_GBS, "unit": "GB/s",
+            "frac": round(link / HOST_LINK_PEAK_GBS, 4),
+            "bytes": "adjacency rows, 4R bytes per expansion"}
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as f:
@@ -279,6 +301,8 @@ def main(argv=None):
         },
         "precision_form": prec,
     }
+    if host is not None:
+        out["host_resident"] = host
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(d, d["queries"], k, L)
     print(json.dumps(out), flush=True)

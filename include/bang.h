@@ -67,8 +67,19 @@ typedef struct {
   uint32_t m;               /* PQ subspaces; m divides d */
   const float* codebooks;   /* [m][256][d/m] FP32 centroids */
   const uint8_t* codes;     /* [n][m] centroid ids */
-  uint32_t flags;           /* must be 0 */
+  uint32_t flags;           /* 0 or BANG_INDEX_HOST_ADJ */
 } bang_index_desc;
+
+/* Index flag: keep the adjacency in pinned host memory instead of device
+ * memory, the paper's CPU-resident graph (section "BANG: Billion-scale ANNS
+ * on a Single GPU": the graph stays in host RAM, the compressed vectors on
+ * the GPU).  bang_index_create copies adj into a page-locked host buffer
+ * (hipHostMalloc, GPU-cacheable, read-only after create); the search
+ * kernel reads one adjacency row (4R bytes) across the host link per
+ * expansion and gathers the neighbours' codes from device memory.  Base
+ * vectors, codes and codebooks stay in device memory.  Results are the
+ * same as with a device-resident graph. */
+#define BANG_INDEX_HOST_ADJ 1u
 
 /* Optional search outputs for inspection; NULL pointers are skipped. */
 typedef struct {

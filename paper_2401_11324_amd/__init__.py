@@ -22,6 +22,7 @@ MAX_L = 1024
 MAX_R = 64
 DTYPES = {"f32": 0, "u8": 1, "i8": 2}
 TABLES = {"f32": 0, "f16": 1, "u8": 2}
+INDEX_HOST_ADJ = 1
 ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EUNSUPPORTED",
           -5: "EABORTED"}
 EXPORTS = ("bang_index_create", "bang_index_destroy", "bang_build_pq_tables",
@@ -116,13 +117,15 @@ def _dev_ptr(t, dtype=None, name="tensor"):
 
 
 class Index:
-    """Device-resident index.  Host numpy arrays in, copies in HBM.
+    """Index.  Host numpy arrays in, copies in HBM.
 
     base [n][d] (float32 / uint8 / int8), adj [n][R] uint32 (BANG_NONE for
     empty slots), medoid, codebooks [m][256][d/m] float32, codes [n][m]
-    uint8."""
+    uint8.  host_adj=True keeps the adjacency in pinned host memory, read
+    by the search across the host link (BANG_INDEX_HOST_ADJ)."""
 
-    def __init__(self, base, adj, medoid, codebooks, codes):
+    def __init__(self, base, adj, medoid, codebooks, codes,
+                 host_adj: bool = False):
         self._h = None
         base = np.ascontiguousarray(base)
         adj = np.ascontiguousarray(adj, dtype=np.uint32)
@@ -137,9 +140,11 @@ class Index:
         self.R = adj.shape[1]
         self.m = codes.shape[1]
         self.torch_dtype = {"f32": "float32", "u8": "uint8", "i8": "int8"}[dt]
+        self.host_adj = bool(host_adj)
         desc = IndexDesc(n, d, DTYPES[dt], base.ctypes.data, adj.shape[1],
                          adj.ctypes.data, int(medoid), codes.shape[1],
-                         cb.ctypes.data, codes.ctypes.data, 0)
+                         cb.ctypes.data, codes.ctypes.data,
+                         INDEX_HOST_ADJ if host_adj else 0)
         if adj.shape[0] != n or codes.shape[0] != n:
             raise ValueError("adj and codes need one row per base vector")
         if cb.shape != (self.m, 256, d // max(1, self.m)):

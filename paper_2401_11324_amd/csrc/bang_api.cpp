@@ -20,6 +20,7 @@ struct bang_index {
   bang::DeviceIndex dev{};
   void* d_base = nullptr;
   unsigned char* d_rows = nullptr;
+  uint32_t* h_adj = nullptr;  // pinned host adjacency (BANG_INDEX_HOST_ADJ)
   uint8_t* d_codes = nullptr;
   float* d_cb = nullptr;
   // search workspace, grown on demand
@@ -108,6 +109,7 @@ void free_index(bang_index* ix) {
   if (!ix) return;
   (void)hipFree(ix->d_base);
   (void)hipFree(ix->d_rows);
+  if (ix->h_adj) (void)hipHostFree(ix->h_adj);
   (void)hipFree(ix->d_codes);
   (void)hipFree(ix->d_cb);
   (void)hipFree(ix->d_cscratch);
@@ -118,7 +120,8 @@ void free_index(bang_index* ix) {
 int create_impl(const bang_index_desc* d, bang_index** out) {
   if (!d || !out) return fail(BANG_EINVAL, "null argument");
   *out = nullptr;
-  if (d->flags != 0) return fail(BANG_EINVAL, "flags must be 0");
+  if (d->flags & ~BANG_INDEX_HOST_ADJ)
+    return fail(BANG_EINVAL, "unknown index flags");
   if (d->n == 0 || d->n >= (1ull << 31))
     return fail(BANG_EINVAL, "n must be in [1, 2^31)");
   if (d->dtype < BANG_F32 || d->dtype > BANG_I8)
@@ -161,9 +164,12 @@ int create_impl(const bang_index_desc* d, bang_index** out) {
   }
   int rc;
   size_t nd = (size_t)d->n * d->d;
+  const bool host_adj = (d->flags & BANG_INDEX_HOST_ADJ) != 0;
+  const size_t adj_bytes = (size_t)d->n * d->R * 4;
   uint32_t* d_adj = nullptr;
   if ((rc = upload(&ix->d_base, d->base, nd * elem_size(d->dtype), "base")) ||
-      (rc = upload(&d_adj, d->adj, (size_t)d->n * d->R * 4, "adjacency")) ||
+      (!host_adj &&
+       (rc = upload(&d_adj, d->adj, adj_bytes, "adjacency"))) ||
       (rc = upload(&ix->d_codes, d->codes, (size_t)d->n * d->m, "codes")) ||
       (rc = upload(&ix->d_cb, d->codebooks, (size_t)d->m * 256 * (d->d / d->m) * 4,
                    "codebooks")) ||
@@ -174,10 +180,35 @@ int create_impl(const bang_index_desc* d, bang_index** out) {
   }
   // the two search counters start at zero; each launch leaves them at zero
   e = hipMemset(ix->d_qcounter, 0, 2 * sizeof(uint32_t));
+  if (e != hipSuccess) {
+    free_index(ix);
+    return hip_fail(e, "clearing the search counters");
+  }
+  if (host_adj) {
+    // page-locked, GPU-cacheable (the kernels only read it), mapped into
+    // the device address space
+    e = hipHostMalloc(reinterpret_cast<void**>(&ix->h_adj), adj_bytes,
+                      hipHostMallocNonCoherent);
+    if (e != hipSuccess) {
+      ix->h_adj = nullptr;
+      free_index(ix);
+      return fail(BANG_ENOMEM, std::string("pinned host adjacency: ") +
+                                   hipGetErrorString(e));
+    }
+    std::memcpy(ix->h_adj, d->adj, adj_bytes);
+    void* dptr = nullptr;
+    e = hipHostGetDevicePointer(&dptr, ix->h_adj, 0);
+    if (e != hipSuccess) {
+      free_index(ix);
+      return hip_fail(e, "hipHostGetDevicePointer");
+    }
+    ix->dev.hadj = static_cast<const uint32_t*>(dptr);
+    ix->dev.rows = nullptr;
+  }
   // rows: each node's adjacency followed by its neighbours' codes, so one
   // coalesced load per expansion brings both (layout in internal.h)
   const size_t row_bytes = (size_t)d->n * bang::row_stride_bytes(d->R, d->m);
-  if (e == hipSuccess) {
+  if (!host_adj) {
     e = hipMalloc(reinterpret_cast<void**>(&ix->d_rows), row_bytes);
     if (e != hipSuccess) {
       (void)hipFree(d_adj);
@@ -187,7 +218,7 @@ int create_impl(const bang_index_desc* d, bang_index** out) {
     }
     e = hipMemset(ix->d_rows, 0, row_bytes);
   }
-  if (e == hipSuccess)
+  if (e == hipSuccess && !host_adj)
     e = bang::launch_pack(d_adj, ix->d_codes, (uint32_t)d->n, d->R, d->m,
                           ix->d_rows, nullptr);
   if (e == hipSuccess) e = hipDeviceSynchronize();
@@ -197,7 +228,7 @@ int create_impl(const bang_index_desc* d, bang_index** out) {
     return hip_fail(e, "packing adjacency rows");
   }
   ix->dev.base = ix->d_base;
-  ix->dev.rows = ix->d_rows;
+  if (!host_adj) ix->dev.rows = ix->d_rows;
   ix->dev.codes = ix->d_codes;
   ix->dev.cb = ix->d_cb;
   ix->dev.n = (uint32_t)d->n;

@@ -498,6 +498,7 @@ struct SearchArgs {
   const unsigned char* rows;  // packed rows: ids, then the neighbours' codes
   const uint8_t* codes;
   const float* cb;
+  const uint32_t* hadj;  // host-resident adjacency [n][R], or null
   const unsigned char* queries;
   uint64_t nq;
   uint32_t n, R, medoid;
@@ -525,11 +526,17 @@ struct SearchArgs {
 constexpr int kPer = 4;
 
 // Adjacency row of node u and, in the same row, the codes of its
-// neighbours: one coalesced load per lane, no dependent gather.
+// neighbours: one coalesced load per lane, no dependent gather.  With a
+// host-resident adjacency only the ids are requested here (4R bytes across
+// the host link); gather_codes fetches the codes once they have arrived.
 template <int M>
 __device__ __forceinline__ void load_row(const SearchArgs& a, uint32_t u,
                                          int lane, uint32_t& nb,
                                          uint4 (&code)[M / 16]) {
+  if (a.hadj) {
+    nb = (uint32_t)lane < a.R ? a.hadj[(size_t)u * a.R + lane] : kNone;
+    return;
+  }
   const unsigned char* row = a.rows + (size_t)u * a.row_stride;
   if ((uint32_t)lane < a.R) {
     nb = reinterpret_cast<const uint32_t*>(row)[lane];
@@ -548,6 +555,18 @@ constexpr int max_waves_per_simd(int table_bytes) {
   const int per_cu = (160 * 1024) / (table_bytes + 1280);
   const int w = (per_cu + 3) / 4;
   return w < 1 ? 1 : (w > 8 ? 8 : w);
+}
+
+// Codes of neighbour nb from the [n][m] code array in device memory (host-
+// resident adjacency only; the packed rows carry them otherwise).
+template <int M>
+__device__ __forceinline__ void gather_codes(const SearchArgs& a, uint32_t nb,
+                                             uint4 (&code)[M / 16]) {
+  if (a.hadj && nb != kNone) {
+    const uint4* c = reinterpret_cast<const uint4*>(a.codes + (size_t)nb * M);
+#pragma unroll
+    for (int i = 0; i < M / 16; ++i) code[i] = c[i];
+  }
 }
 
 template <int DT, int M, int DS, int TT>
@@ -638,6 +657,7 @@ void search_kernel(SearchArgs a) {
       const uint64_t last = Lc[Llen - 1];
 
       // distances of the neighbours (row of u*, loaded earlier)
+      gather_codes<M>(a, nb, code);
       uint64_t key = kInf;
       if (nb != kNone) key = make_key(adc_codes<M, TT>(T, code), nb);
 
@@ -1124,6 +1144,7 @@ hipError_t launch_search(const DeviceIndex& ix, const SearchLaunch& l,
   SearchArgs a;
   a.base = ix.base;
   a.rows = ix.rows;
+  a.hadj = ix.hadj;
   a.codes = ix.codes;
   a.cb = ix.cb;
   a.queries = (const unsigned char*)l.queries;

@@ -14,6 +14,8 @@ enum Dtype : int { kF32 = 0, kU8 = 1, kI8 = 2 };
 struct DeviceIndex {
   const void* base;           // [n][d]
   const unsigned char* rows;  // [n][row_stride_bytes]: ids, neighbour codes
+                              // (null when the adjacency is host-resident)
+  const uint32_t* hadj;       // [n][R] in pinned host memory, or null
   const uint8_t* codes;       // [n][m]
   const float* cb;            // [m][256][d/m]
   uint32_t n, d, R, m, medoid;

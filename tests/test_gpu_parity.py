@@ -286,3 +286,56 @@ def test_sift1m_full_batch_sampled_bit_exact():
         dd = dist.cpu().numpy()
         assert (np.diff(dd, axis=1) >= 0).all()
         assert all(len(set(r)) == len(r) for r in allids[:500])
+
+
+# --------------------------------------------------------------------------
+# host-resident adjacency (BANG_INDEX_HOST_ADJ): the same search, adjacency
+# rows read across the host link, codes gathered from device memory
+# --------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def small_host_indexes(small_indexes):
+    return {name: bang_mod().Index(ix.base, ix.adj, ix.medoid, ix.codebooks,
+                                   ix.codes, host_adj=True)
+            for name, (ix, q, _) in small_indexes.items()}
+
+
+@pytest.mark.parametrize("name", list(SMALL))
+@pytest.mark.parametrize("k,L,table", [(1, 1, "f32"), (10, 16, "f32"),
+                                       (5, 33, "u8"), (10, 100, "f32"),
+                                       (10, 300, "f16"), (100, 1024, "f32")])
+def test_host_adjacency_bit_exact(small_indexes, small_host_indexes, name, k,
+                                  L, table):
+    ix, q, _ = small_indexes[name]
+    run_and_compare(ix, small_host_indexes[name], q, k, L, table=table,
+                    label=f"host {name} k={k} L={L} {table}")
+
+
+def test_sift1m_host_adjacency_bit_exact():
+    """1M uint8 points with the adjacency in pinned host memory: the full
+    batch equals the device-resident run bit for bit, and a seeded sample
+    equals the oracle."""
+    w, ix, d = load_workload("sift1m")
+    bang = bang_mod()
+    dev = bang.Index(ix.base, ix.adj, ix.medoid, ix.codebooks, ix.codes)
+    host = bang.Index(ix.base, ix.adj, ix.medoid, ix.codebooks, ix.codes,
+                      host_adj=True)
+    q = d["queries"]
+    qt = to_dev(q)
+    sample = np.sort(np.random.default_rng(2025).choice(len(q), 96,
+                                                        replace=False))
+    for L, table in [(64, "f32"), (768, "f32"), (768, "u8")]:
+        a_ids, a_d, a_cnt = host.search(qt, w.k, L, want_counters=True,
+                                        table=table)
+        b_ids, b_d, b_cnt = dev.search(qt, w.k, L, want_counters=True,
+                                       table=table)
+        torch.cuda.synchronize()
+        assert np.array_equal(u32(a_ids), u32(b_ids)), (L, table)
+        assert np.array_equal(f32bits(a_d.cpu().numpy()),
+                              f32bits(b_d.cpu().numpy())), (L, table)
+        assert np.array_equal(u32(a_cnt), u32(b_cnt)), (L, table)
+        ref = oracle.search(ix, q[sample], w.k, L, table=table)
+        assert np.array_equal(u32(a_ids)[sample], ref["ids"]), (L, table)
+        assert np.array_equal(f32bits(a_d.cpu().numpy()[sample]),
+                              f32bits(ref["dists"])), (L, table)
+    host.close()
+    dev.close()
