@@ -163,7 +163,9 @@ def adc(table: np.ndarray, codes: np.ndarray, ids: np.ndarray) -> np.ndarray:
     return out
 
 
-TABLES = {"f32": 0, "f16": 1, "u8": 2}
+# "exact": no table; the search ranks by exact distances and returns the
+# k first worklist entries with no re-rank (the Exact-distance Version)
+TABLES = {"f32": 0, "f16": 1, "u8": 2, "exact": 3}
 
 
 def iter_cap_for(L: int) -> int:
@@ -196,7 +198,9 @@ def search(index: Index, queries: np.ndarray, k: int, L: int,
            table: str = "f32", nthreads: int = 0):
     """Stages 1-3 for a batch (Algorithms 1 and 2, sections on the PQ
     table, re-ranking).  `table` picks the table storage the search ranks
-    by: "f32" (canonical), "f16" or "u8" (the precision form, oracle.c).
+    by: "f32" (canonical), "f16" or "u8" (the precision form, oracle.c),
+    or "exact": exact distances in the search and no re-rank (section
+    "Implementation Variants", Exact-distance Version).
     Returns a dict with ids, dists and, on request,
     pq_ids/pq_dists (Algorithm 1's own top-k), cand (expanded nodes in
     expansion order, NONE padded) and counters [I, status, added]."""

@@ -131,6 +131,11 @@ static float adc_one(const float* T, const uint8_t* code, uint32_t m) {
 #define OR_TABLE_F32 0
 #define OR_TABLE_F16 1
 #define OR_TABLE_U8 2
+/* No table at all: the paper's Exact-distance Version (section
+ * "Implementation Variants").  The search ranks every node by its exact
+ * distance to the query (the re-rank's distance), and there is no re-rank:
+ * the answer is the k first entries of the final worklist. */
+#define OR_TABLE_EXACT 3
 
 /* FP32 -> IEEE half, round to nearest, ties to even (finite inputs). */
 uint16_t or_f32_to_f16(float f) {
@@ -174,9 +179,10 @@ float or_f16_to_f32(uint16_t h) {
 typedef struct {
   int mode;
   uint32_t m;
-  const float* T32; /* canonical table (always built) */
+  const float* T32; /* canonical table (built for every mode but EXACT) */
   uint16_t* T16;
   uint8_t* T8;
+  const void* q;    /* the query (EXACT) */
 } qtable;
 
 static void quantize_table(qtable* t) {
@@ -233,7 +239,7 @@ void or_quantize_tables(const float* T, uint64_t nq, uint32_t m, int mode,
                         uint16_t* out16, uint8_t* out8) {
   for (uint64_t q = 0; q < nq; ++q) {
     qtable t = {mode, m, T + q * m * 256, out16 ? out16 + q * m * 256 : NULL,
-                out8 ? out8 + q * m * 256 : NULL};
+                out8 ? out8 + q * m * 256 : NULL, NULL};
     quantize_table(&t);
   }
 }
@@ -270,6 +276,13 @@ static float exact_dist(const or_index* ix, const void* q, uint32_t id) {
     acc += (a - b) * (a - b);
   }
   return (float)acc;
+}
+
+/* The distance the search ranks node x by: its PQ distance from the table,
+ * or, without a table, its exact distance. */
+static float node_dist(const or_index* ix, const qtable* T, uint32_t x) {
+  if (T->mode == OR_TABLE_EXACT) return exact_dist(ix, T->q, x);
+  return adc_q(T, ix->codes + (uint64_t)x * ix->m);
 }
 
 /* ------------------------------------------------------------------------
@@ -317,10 +330,10 @@ static void greedy_search(const or_index* ix, const qtable* T, uint32_t Lcap,
                           uint32_t iter_cap, int mode, uint32_t* seen,
                           uint32_t stamp, entry* L, uint32_t* Llen, entry* C,
                           entry* scratch, or_counters* cnt) {
-  uint32_t R = ix->R, m = ix->m;
+  uint32_t R = ix->R;
   uint32_t s = ix->medoid;
   uint32_t len = 1;
-  L[0].dist = adc_q(T, ix->codes + (uint64_t)s * m);
+  L[0].dist = node_dist(ix, T, s);
   L[0].id = s;
   L[0].visited = 0;
   if (mode == 1) seen[s] = stamp;
@@ -356,7 +369,7 @@ static void greedy_search(const or_index* ix, const qtable* T, uint32_t Lcap,
             break;
           }
         if (present) continue;
-        L[len].dist = adc_q(T, ix->codes + (uint64_t)x * m);
+        L[len].dist = node_dist(ix, T, x);
         L[len].id = x;
         L[len].visited = 0;
         ++len;
@@ -372,7 +385,7 @@ static void greedy_search(const or_index* ix, const qtable* T, uint32_t Lcap,
         uint32_t x = nb[r];
         if (x == OR_NONE || seen[x] == stamp) continue;
         seen[x] = stamp;
-        scratch[np].dist = adc_q(T, ix->codes + (uint64_t)x * m);
+        scratch[np].dist = node_dist(ix, T, x);
         scratch[np].id = x;
         scratch[np].visited = 0;
         ++np;
@@ -459,8 +472,9 @@ int or_search(const or_index* ix, const void* queries, uint64_t nq, uint32_t k,
 #pragma omp for schedule(dynamic, 1)
       for (qi = 0; qi < (int64_t)nq; ++qi) {
         const char* q = (const char*)queries + (size_t)qi * ix->d * dt_size(ix->dtype);
-        pq_table_one(q, ix->dtype, ix->d, ix->codebooks, ix->m, T);
-        qtable qt = {table_mode, ix->m, T, T16, T8};
+        if (table_mode != OR_TABLE_EXACT)
+          pq_table_one(q, ix->dtype, ix->d, ix->codebooks, ix->m, T);
+        qtable qt = {table_mode, ix->m, T, T16, T8, q};
         quantize_table(&qt);
         or_counters cn;
         uint32_t Llen;
@@ -481,8 +495,16 @@ int or_search(const or_index* ix, const void* queries, uint64_t nq, uint32_t k,
           counters[qi * 4 + 2] = (uint32_t)(cn.added & 0xFFFFFFFFu);
           counters[qi * 4 + 3] = (uint32_t)(cn.added >> 32);
         }
-        rerank_entries(ix, q, C, cn.iters, c_max, k, ids + qi * k,
-                       dists + qi * k);
+        if (table_mode == OR_TABLE_EXACT) {
+          /* no re-rank: the worklist already holds exact distances */
+          for (uint32_t i = 0; i < k; ++i) {
+            ids[qi * k + i] = i < Llen ? L[i].id : OR_NONE;
+            dists[qi * k + i] = i < Llen ? L[i].dist : INFINITY;
+          }
+        } else {
+          rerank_entries(ix, q, C, cn.iters, c_max, k, ids + qi * k,
+                         dists + qi * k);
+        }
       }
     }
     free(T);

@@ -473,3 +473,74 @@ def test_precision_form_ranks_by_quantised_adc(small_u8):
         assert np.array_equal(out["pq_dists"][a], s.astype(np.float32))
         keys = list(zip(s.tolist(), ids.tolist()))
         assert keys == sorted(keys)
+
+
+# --------------------------------------------------------------------------
+# Exact-distance Version (section "Implementation Variants"): no table, the
+# search ranks by exact distances, no re-rank
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("fx", ["small_f32", "small_u8", "small_i8"])
+def test_exact_distance_L_at_least_n_is_brute_force(fx, request):
+    """t >= n on a connected graph expands every node and evicts none, so
+    the worklist ends holding every node in exact-distance order: its k
+    first entries are the brute-force k nearest."""
+    ix, q, _ = request.getfixturevalue(fx)
+    out = oracle.search(ix, q[:6], 10, ix.n, iter_cap=ix.n + 1,
+                        table="exact")
+    assert (out["iters"] == ix.n).all() and (out["status"] == 0).all()
+    allid = np.arange(ix.n)
+    for a in range(6):
+        ex = exact_sq(ix.base, q[a])
+        order = np.lexsort((allid, ex))[:10]
+        assert out["ids"][a].tolist() == order.tolist()
+        if ix.base.dtype == np.float32:
+            np.testing.assert_allclose(out["dists"][a], ex[order], rtol=2e-6)
+        else:
+            assert np.array_equal(out["dists"][a],
+                                  ex[order].astype(np.float32))
+
+
+@pytest.mark.parametrize("fx", ["small_f32", "small_u8", "small_i8"])
+@pytest.mark.parametrize("L", [10, 33, 64])
+def test_exact_distance_answer_needs_no_rerank(fx, L, request):
+    """Without a re-rank the answer is the worklist's k first entries; a
+    node expanded but no longer in the worklist was evicted at or above its
+    last key, so these are also the k nearest expanded nodes by exact
+    distance, which is what a re-rank of the expanded nodes would return.
+    The distances are the exact squared distances of the ids."""
+    ix, q, _ = request.getfixturevalue(fx)
+    out = oracle.search(ix, q, 10, L, table="exact", want_cand=True)
+    rr_ids, rr_d = oracle.rerank(ix, q, out["cand"], 10)
+    assert np.array_equal(out["ids"], rr_ids)
+    assert np.array_equal(out["dists"], rr_d)
+    for a in range(len(q)):
+        ex = exact_sq(ix.base, q[a])[out["ids"][a].astype(np.int64)]
+        if ix.base.dtype == np.float32:
+            np.testing.assert_allclose(out["dists"][a], ex, rtol=2e-6)
+        else:
+            assert np.array_equal(out["dists"][a], ex.astype(np.float32))
+        keys = list(zip(out["dists"][a].tolist(), out["ids"][a].tolist()))
+        assert keys == sorted(keys)
+
+
+@pytest.mark.parametrize("L", [10, 33])
+def test_exact_distance_algorithm1_equals_filtered_form(small_u8, L):
+    ix, q, _ = small_u8
+    a = oracle.search(ix, q, 10, L, mode=0, table="exact", want_cand=True)
+    b = oracle.search(ix, q, 10, L, mode=1, table="exact", want_cand=True)
+    for key in ("ids", "dists", "cand", "iters"):
+        assert np.array_equal(a[key], b[key]), key
+
+
+def test_exact_distance_beats_pq_recall(small_u8):
+    """Exact distances remove the PQ error the re-rank compensates for: at
+    the same t the exact-distance search finds at least as many true
+    neighbours on average."""
+    ix, q, _ = small_u8
+    gt = np.stack([np.lexsort((np.arange(ix.n), exact_sq(ix.base, x)))[:10]
+                   for x in q])
+    def recall(ids):
+        return np.mean([len(set(a) & set(b)) for a, b in zip(ids, gt)]) / 10
+    ex = oracle.search(ix, q, 10, 16, table="exact")
+    pq = oracle.search(ix, q, 10, 16)
+    assert recall(ex["ids"]) >= recall(pq["ids"])
