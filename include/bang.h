@@ -97,8 +97,9 @@ typedef struct {
                                were written (hipDeviceAttributeWallClockRate
                                gives the tick rate in kHz) */
   uint32_t table;           /* storage of the PQ table the search ranks by:
-                               BANG_TABLE_F32 (default), or the precision
-                               form's BANG_TABLE_F16 / BANG_TABLE_U8 */
+                               BANG_TABLE_F32 (default), the precision
+                               form's BANG_TABLE_F16 / BANG_TABLE_U8, or
+                               BANG_TABLE_EXACT (no table) */
   uint32_t flags;           /* 0, or BANG_SEARCH_RERANK_GLOBAL */
 } bang_search_opts;
 
@@ -119,6 +120,12 @@ typedef struct {
 #define BANG_TABLE_F32 0u
 #define BANG_TABLE_F16 1u
 #define BANG_TABLE_U8 2u
+/* No PQ table: the paper's Exact-distance Version (section
+ * "Implementation Variants").  The search ranks every node by its exact
+ * squared distance to the query (the re-rank's distance, computed from the
+ * base vectors in device memory) and there is no re-rank: the result is
+ * the k first entries of the final worklist.  c_max is ignored. */
+#define BANG_TABLE_EXACT 3u
 
 /* Build an index on the current HIP device: validates the description
  * (ids in range, no duplicate ids in a row, m | d, supported (m, d/m,

@@ -21,7 +21,7 @@ BANG_NONE = 0xFFFFFFFF
 MAX_L = 1024
 MAX_R = 64
 DTYPES = {"f32": 0, "u8": 1, "i8": 2}
-TABLES = {"f32": 0, "f16": 1, "u8": 2}
+TABLES = {"f32": 0, "f16": 1, "u8": 2, "exact": 3}
 INDEX_HOST_ADJ = 1
 ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EUNSUPPORTED",
           -5: "EABORTED"}
@@ -191,8 +191,9 @@ class Index:
                rerank_global: bool = False, out=None, stream=None):
         """Stages 1-3.  Returns (ids uint32-as-int32 [nq][k], dists
         float32 [nq][k]) and, on request, the expanded nodes [nq][want_cand]
-        `table` is the PQ table storage the search ranks by: "f32", or the
-        precision form's "f16" / "u8".
+        `table` is the PQ table storage the search ranks by: "f32", the
+        precision form's "f16" / "u8", or "exact" (no table: exact
+        distances, no re-rank).
         and counters [nq][4] (iterations, status) and device wall-clock
         ticks [nq][2] (begin, end)."""
         import torch

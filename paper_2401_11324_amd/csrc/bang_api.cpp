@@ -266,7 +266,7 @@ int search_impl(bang_index* ix, const void* queries, uint64_t nq, uint32_t k,
   uint32_t c_max = (o && o->c_max) ? o->c_max : 4 * L;
   uint32_t iter_cap = (o && o->iter_cap) ? o->iter_cap : std::max(4 * L, L + 64);
   const uint32_t table = o ? o->table : BANG_TABLE_F32;
-  if (table > BANG_TABLE_U8) return fail(BANG_EINVAL, "unknown table form");
+  if (table > BANG_TABLE_EXACT) return fail(BANG_EINVAL, "unknown table form");
   if (iter_cap > 8192) return fail(BANG_EINVAL, "iter_cap > 8192");
   if (o && o->out_cand && o->cand_stride == 0)
     return fail(BANG_EINVAL, "cand_stride must be > 0 with out_cand");

@@ -152,8 +152,10 @@ __device__ __forceinline__ float adc(const float* T,
 // Table storage of the search: canonical FP32, or the precision form's
 // half (times a power-of-two scale) or u8 (per-subspace offset, one scale).
 // Both reduced forms are derived from the canonical FP32 entries, so they
-// are as deterministic as the FP32 table itself.
-enum TableKind : int { kTabF32 = 0, kTabF16 = 1, kTabU8 = 2 };
+// are as deterministic as the FP32 table itself.  kTabExact: no table; the
+// search ranks by exact distances and skips the re-rank (the paper's
+// Exact-distance Version, section "Implementation Variants").
+enum TableKind : int { kTabF32 = 0, kTabF16 = 1, kTabU8 = 2, kTabExact = 3 };
 
 template <int TT>
 struct Tab;
@@ -169,6 +171,14 @@ template <>
 struct Tab<kTabU8> {
   using E = uint8_t;
 };
+template <>
+struct Tab<kTabExact> {
+  using E = uint8_t;  // no table
+};
+template <int TT>
+constexpr int table_bytes(int M) {
+  return TT == kTabExact ? 0 : M * 256 * (int)sizeof(typename Tab<TT>::E);
+}
 
 __device__ __forceinline__ float f16_bits_to_f32(uint16_t h) {
   return (float)__builtin_bit_cast(_Float16, h);
@@ -288,11 +298,37 @@ __device__ __forceinline__ float adc_codes(const void* Tv, const uint4 (&v)[M / 
   return TT == kTabU8 ? (float)iacc : acc;
 }
 
-// Exact squared distance between base row `id` and the query.
+// Sum of the squares of the query's coordinates, integer data only (0 for
+// FP32): the constant term of exact_dist.
+template <int DT, int D>
+__device__ __forceinline__ int32_t query_sq(const unsigned char* q) {
+  if constexpr (DT == kF32) {
+    return 0;
+  } else {
+    const uint32_t* qw = reinterpret_cast<const uint32_t*>(q);
+    uint32_t s = 0;
+#pragma unroll
+    for (int i = 0; i < D / 4; ++i) {
+      if constexpr (DT == kU8)
+        s = __builtin_amdgcn_udot4(qw[i], qw[i], s, false);
+      else
+        s = (uint32_t)__builtin_amdgcn_sdot4((int)qw[i], (int)qw[i], (int)s,
+                                             false);
+    }
+    return (int32_t)s;
+  }
+}
+
+// Exact squared distance between base row `id` and the query.  FP32 data:
+// the differences squared and added left to right over the d coordinates.
+// Integer data: sum (x - q)^2 = sum x^2 - 2 sum x q + qq (qq = query_sq),
+// each sum exact from four-byte dot products, so the value is the plain
+// integer sum (below 2^24, exact in FP32).
 template <int DT, int D>
 __device__ __forceinline__ float exact_dist(const void* __restrict__ base,
                                             uint32_t id,
-                                            const unsigned char* q) {
+                                            const unsigned char* q,
+                                            int32_t qq) {
   if constexpr (DT == kF32) {
     const float4* x =
         reinterpret_cast<const float4*>((const float*)base + (size_t)id * D);
@@ -314,21 +350,26 @@ __device__ __forceinline__ float exact_dist(const void* __restrict__ base,
     static_assert(D % 16 == 0, "rows are read 16 bytes at a time");
     const uint4* x = reinterpret_cast<const uint4*>(
         (const uint8_t*)base + (size_t)id * D);
-    int acc = 0;
+    const uint32_t* qw = reinterpret_cast<const uint32_t*>(q);
+    uint32_t xx = 0, xq = 0;
 #pragma unroll 2
     for (int c = 0; c < D / 16; ++c) {
-      uint4 v = x[c];
+      const uint4 v = x[c];
       const uint32_t w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
-      for (int b = 0; b < 16; ++b) {
-        uint32_t byte = (w[b >> 2] >> (8 * (b & 3))) & 0xFFu;
-        int xv = (DT == kU8) ? (int)byte : (int)(int8_t)byte;
-        int qv = (DT == kU8) ? (int)q[16 * c + b] : (int)(int8_t)q[16 * c + b];
-        int df = xv - qv;
-        acc += df * df;
+      for (int t = 0; t < 4; ++t) {
+        if constexpr (DT == kU8) {
+          xx = __builtin_amdgcn_udot4(w[t], w[t], xx, false);
+          xq = __builtin_amdgcn_udot4(w[t], qw[4 * c + t], xq, false);
+        } else {
+          xx = (uint32_t)__builtin_amdgcn_sdot4((int)w[t], (int)w[t], (int)xx,
+                                                false);
+          xq = (uint32_t)__builtin_amdgcn_sdot4((int)w[t], (int)qw[4 * c + t],
+                                                (int)xq, false);
+        }
       }
     }
-    return (float)acc;
+    return (float)(int32_t)(xx - 2u * xq + (uint32_t)qq);
   }
 }
 
@@ -529,7 +570,8 @@ constexpr int kPer = 4;
 // neighbours: one coalesced load per lane, no dependent gather.  With a
 // host-resident adjacency only the ids are requested here (4R bytes across
 // the host link); gather_codes fetches the codes once they have arrived.
-template <int M>
+// CODES = false (exact distances) requests the ids alone.
+template <int M, bool CODES = true>
 __device__ __forceinline__ void load_row(const SearchArgs& a, uint32_t u,
                                          int lane, uint32_t& nb,
                                          uint4 (&code)[M / 16]) {
@@ -540,6 +582,7 @@ __device__ __forceinline__ void load_row(const SearchArgs& a, uint32_t u,
   const unsigned char* row = a.rows + (size_t)u * a.row_stride;
   if ((uint32_t)lane < a.R) {
     nb = reinterpret_cast<const uint32_t*>(row)[lane];
+    if (!CODES) return;
     const uint4* c = reinterpret_cast<const uint4*>(row + a.row_ids + lane * M);
 #pragma unroll
     for (int i = 0; i < M / 16; ++i) code[i] = c[i];
@@ -571,11 +614,12 @@ __device__ __forceinline__ void gather_codes(const SearchArgs& a, uint32_t nb,
 
 template <int DT, int M, int DS, int TT>
 __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(
-    1, max_waves_per_simd(M * 256 * (int)sizeof(typename Tab<TT>::E)))))
+    1, max_waves_per_simd(table_bytes<TT>(M)))))
 void search_kernel(SearchArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int D = M * DS;
-  constexpr int kTableBytes = M * 256 * (int)sizeof(typename Tab<TT>::E);
+  constexpr int kTableBytes = table_bytes<TT>(M);
+  constexpr bool kExact = TT == kTabExact;
   const int lane = threadIdx.x;
   void* T = smem;
   float* lo = reinterpret_cast<float*>(smem + kTableBytes);  // U8 offsets
@@ -614,18 +658,28 @@ void search_kernel(SearchArgs a) {
     // stage 1: the table (the previous query's re-rank is done with S)
     __syncthreads();
     const uint32_t s = a.medoid;
+    // constant term of integer exact distances (the PQ forms compute it
+    // after the search, so the query is not held through the loop)
+    int32_t qq = 0;
+    if constexpr (kExact) qq = query_sq<DT, D>(q);
     uint32_t nb;
     uint4 code[M / 16];
-    load_row<M>(a, s, lane, nb, code);  // in flight during the table build
-    build_table_q<DT, M, DS, TT>(q, a.cb, T, lo, lane);
+    load_row<M, !kExact>(a, s, lane, nb, code);  // in flight meanwhile
+    if constexpr (!kExact) build_table_q<DT, M, DS, TT>(q, a.cb, T, lo, lane);
     __syncthreads();
 
-    // stage 2: L = [(ADC(s), s)]
-    uint4 scode[M / 16];
+    // stage 2: L = [(dist(s), s)]
+    float d0;
+    if constexpr (kExact) {
+      d0 = exact_dist<DT, D>(a.base, s, q, qq);
+    } else {
+      uint4 scode[M / 16];
 #pragma unroll
-    for (int i = 0; i < M / 16; ++i)
-      scode[i] = reinterpret_cast<const uint4*>(a.codes + (size_t)s * M)[i];
-    uint64_t curkey = make_key(adc_codes<M, TT>(T, scode), s);
+      for (int i = 0; i < M / 16; ++i)
+        scode[i] = reinterpret_cast<const uint4*>(a.codes + (size_t)s * M)[i];
+      d0 = adc_codes<M, TT>(T, scode);
+    }
+    uint64_t curkey = make_key(d0, s);
     if (lane == 0) Lc[0] = curkey;
     uint32_t Llen = 1, cur = 0, iters = 0, status = 0;
     __syncthreads();
@@ -657,9 +711,13 @@ void search_kernel(SearchArgs a) {
       const uint64_t last = Lc[Llen - 1];
 
       // distances of the neighbours (row of u*, loaded earlier)
-      gather_codes<M>(a, nb, code);
       uint64_t key = kInf;
-      if (nb != kNone) key = make_key(adc_codes<M, TT>(T, code), nb);
+      if constexpr (kExact) {
+        if (nb != kNone) key = make_key(exact_dist<DT, D>(a.base, nb, q, qq), nb);
+      } else {
+        gather_codes<M>(a, nb, code);
+        if (nb != kNone) key = make_key(adc_codes<M, TT>(T, code), nb);
+      }
 
       // rank in the worklist; a node already in it is dropped (set union);
       // a key ranked past a full worklist is cut whatever the other new keys
@@ -727,7 +785,7 @@ void search_kernel(SearchArgs a) {
       }
       // request the next row now; it arrives during the merge
       if (best != kNone)
-        load_row<M>(a, key_id(bestkey), lane, nb, code);
+        load_row<M, !kExact>(a, key_id(bestkey), lane, nb, code);
       else
         nb = kNone;
 
@@ -849,7 +907,14 @@ void search_kernel(SearchArgs a) {
     uint32_t nc = iters;
     uint32_t* oid = a.out_ids + (size_t)qi * a.k;
     float* od = a.out_dists + (size_t)qi * a.k;
-    if (pow2ceil_dev(nc) <= a.s_cap) {
+    if constexpr (kExact) {
+      // no re-rank: the worklist already ranks by exact distance
+      for (uint32_t i = lane; i < a.k; i += kWave) {
+        const uint64_t key = i < Llen ? Lc[i] : kInf;
+        oid[i] = key == kInf ? kNone : key_id(key);
+        od[i] = key == kInf ? __uint_as_float(0x7F800000u) : key_dist(key);
+      }
+    } else if (qq = query_sq<DT, D>(q); pow2ceil_dev(nc) <= a.s_cap) {
       // sort in LDS (table region + worklist buffer, free now)
       if (nc > a.c_max) {
         // keep the c_max smallest (PQ distance, id)
@@ -863,9 +928,10 @@ void search_kernel(SearchArgs a) {
         for (uint32_t i = lane; i < nc; i += kWave) S[i] = C[i] & ~1ull;
       }
       __syncthreads();
+#pragma unroll 1
       for (uint32_t i = lane; i < nc; i += kWave) {
         const uint32_t id = key_id(S[i]);
-        S[i] = make_key(exact_dist<DT, D>(a.base, id, q), id);
+        S[i] = make_key(exact_dist<DT, D>(a.base, id, q, qq), id);
       }
       __syncthreads();
       sort_and_emit(S, nc, a.k, oid, od, lane);
@@ -878,9 +944,10 @@ void search_kernel(SearchArgs a) {
         global_select(C, nc, a.c_max, lane);
         nc = a.c_max;
       }
+#pragma unroll 1
       for (uint32_t i = lane; i < nc; i += kWave) {
         const uint32_t id = key_id(C[i]);
-        C[i] = make_key(exact_dist<DT, D>(a.base, id, q), id);
+        C[i] = make_key(exact_dist<DT, D>(a.base, id, q, qq), id);
       }
       __threadfence();
       __syncthreads();
@@ -943,6 +1010,7 @@ __global__ __launch_bounds__(kWave) void rerank_kernel(
   const int lane = threadIdx.x;
   for (uint64_t qi = blockIdx.x; qi < nq; qi += gridDim.x) {
     const unsigned char* q = queries + qi * D * Elem<DT>::size;
+    const int32_t qq = query_sq<DT, D>(q);
     uint32_t cnt = 0;
     for (uint32_t i0 = 0; i0 < c_max; i0 += kWave) {
       uint32_t i = i0 + lane;
@@ -951,7 +1019,7 @@ __global__ __launch_bounds__(kWave) void rerank_kernel(
       uint64_t m = __ballot(ok);
       uint32_t idx = __builtin_amdgcn_mbcnt_hi(
           (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-      if (ok) S[cnt + idx] = make_key(exact_dist<DT, D>(base, id, q), id);
+      if (ok) S[cnt + idx] = make_key(exact_dist<DT, D>(base, id, q, qq), id);
       cnt += __popcll(m);
     }
     __syncthreads();
@@ -1007,6 +1075,10 @@ struct RunSearch {
         hipLaunchKernelGGL((search_kernel<DT, M, DS, kTabU8>), dim3(grid),
                            dim3(kWave), lds, s, a);
         break;
+      case kTabExact:
+        hipLaunchKernelGGL((search_kernel<DT, M, DS, kTabExact>), dim3(grid),
+                           dim3(kWave), lds, s, a);
+        break;
       default:
         return hipErrorInvalidValue;
     }
@@ -1033,6 +1105,8 @@ struct Occupancy {
         return occupancy_of(search_kernel<DT, M, DS, kTabF16>, lds, per_cu);
       case kTabU8:
         return occupancy_of(search_kernel<DT, M, DS, kTabU8>, lds, per_cu);
+      case kTabExact:
+        return occupancy_of(search_kernel<DT, M, DS, kTabExact>, lds, per_cu);
     }
     return hipErrorInvalidValue;
   }
@@ -1098,6 +1172,7 @@ static size_t table_entry_bytes(int table) {
 // the re-rank sorts its keys in this region and the worklist buffer behind
 // it when they fit (else it selects in global memory).
 static size_t region0_bytes(uint32_t m, int tab) {
+  if (tab == kTabExact) return 0;  // no table, no re-rank keys
   const size_t table = (size_t)m * 256 * table_entry_bytes(tab) +
                        (tab == kTabU8 ? (size_t)m * 4 : 0);
   return (table + 15) / 16 * 16;

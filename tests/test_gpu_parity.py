@@ -339,3 +339,47 @@ def test_sift1m_host_adjacency_bit_exact():
                               f32bits(ref["dists"])), (L, table)
     host.close()
     dev.close()
+
+
+# --------------------------------------------------------------------------
+# exact-distance search (BANG_TABLE_EXACT): no table, no re-rank
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("name", list(SMALL))
+@pytest.mark.parametrize("k,L", [(1, 1), (10, 10), (5, 33), (10, 100),
+                                 (32, 256), (100, 1024)])
+def test_exact_distance_bit_exact(small_indexes, name, k, L):
+    ix, q, gi = small_indexes[name]
+    run_and_compare(ix, gi, q, k, L, table="exact",
+                    label=f"exact {name} k={k} L={L}")
+
+
+@pytest.mark.parametrize("name", ["u8-d128-m32", "i8-d96-m48"])
+def test_exact_distance_host_adjacency_bit_exact(small_indexes,
+                                                 small_host_indexes, name):
+    ix, q, _ = small_indexes[name]
+    run_and_compare(ix, small_host_indexes[name], q, 10, 64, table="exact",
+                    label=f"exact host {name}")
+
+
+def test_sift1m_exact_distance_sampled_bit_exact():
+    """1M uint8 points, exact distances in the search: full batch on the
+    GPU, a seeded sample recomputed by the oracle."""
+    w, ix, d = load_workload("sift1m")
+    gi = bang_mod().Index(ix.base, ix.adj, ix.medoid, ix.codebooks, ix.codes)
+    q = d["queries"]
+    qt = to_dev(q)
+    sample = np.sort(np.random.default_rng(2026).choice(len(q), 128,
+                                                        replace=False))
+    for L in (16, 64, 256):
+        cap = oracle.iter_cap_for(L)
+        ids, dist, cand, cnt = gi.search(qt, w.k, L, want_cand=cap,
+                                         want_counters=True, table="exact")
+        torch.cuda.synchronize()
+        ref = oracle.search(ix, q[sample], w.k, L, want_cand=True,
+                            table="exact")
+        assert np.array_equal(u32(cnt)[sample, 0], ref["iters"]), L
+        assert np.array_equal(u32(cand)[sample], ref["cand"]), L
+        assert np.array_equal(u32(ids)[sample], ref["ids"]), L
+        assert np.array_equal(f32bits(dist.cpu().numpy()[sample]),
+                              f32bits(ref["dists"])), L
+    gi.close()
