@@ -61,14 +61,20 @@ def iteration_overhead(I: float, t: int) -> float:
     return (I - t) / t * 100.0
 
 
-def algorithmic_bytes(adj_deg, R, m, d, elem, k, iters, cand, c_max):
+def algorithmic_bytes(adj_deg, R, m, d, elem, k, iters, cand, c_max,
+                      exact=False):
     """HBM bytes one launch must move, from the per-query counters:
     per expansion the adjacency row (4R) and the m code bytes of every
     neighbour in it; per query the query vector, the base rows of the
-    re-ranked candidates and the k (id, distance) results."""
+    re-ranked candidates and the k (id, distance) results.  Exact-distance
+    search: the base row (d elements) of every neighbour instead of its
+    codes, and no re-rank."""
     I = iters.astype(np.int64)
     valid = cand != 0xFFFFFFFF
     deg_sum = np.where(valid, adj_deg[np.where(valid, cand, 0)], 0).sum()
+    if exact:
+        return int(I.sum() * 4 * R + deg_sum * d * elem + len(I) * d * elem
+                   + len(I) * 8 * k)
     rr = np.minimum(I, c_max).sum()
     return int(I.sum() * 4 * R + deg_sum * m + len(I) * d * elem
                + rr * d * elem + len(I) * 8 * k)
@@ -161,7 +167,7 @@ def main(argv=None):
 
     # recall sweep over L and table forms (one untimed + one timed launch)
     sweep = []
-    for table in ([] if a.no_sweep else TABLES):
+    for table in ([] if a.no_sweep else TABLES + ("exact",)):
         for L in w.Ls:
             ids, dist = gi.search(q, k, L, table=table)
             torch.cuda.synchronize()
@@ -219,7 +225,7 @@ def main(argv=None):
         kern_ms = float(per.mean())
         lat_ms = (t[:, 1] - t[:, 0].min()) / span * kern_ms
         B = algorithmic_bytes(adj_deg, w.R, w.m, w.d, elem, k, iters, cand,
-                              4 * L)
+                              4 * L, exact=table == "exact")
         ms_step = wall * 1e3 / a.steps
         return {"table": table, "L": L, "recall10": round(rec, 4),
                 "adjacency_bytes_per_launch": int(iters.astype(np.int64).sum()
@@ -237,6 +243,9 @@ def main(argv=None):
 
     plain = measure("f32", pick_L("f32"))
     prec = {t: measure(t, pick_L(t)) for t in ("f16", "u8")}
+    # the paper's Exact-distance Version: no table, no re-rank
+    exact = None if a.no_sweep and not a.L else measure("exact",
+                                                         pick_L("exact"))
     L = plain["L"]
     host = None
     if not a.no_host:
@@ -303,6 +312,8 @@ def main(argv=None):
     }
     if host is not None:
         out["host_resident"] = host
+    if exact is not None:
+        out["exact_distance"] = exact
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(d, d["queries"], k, L)
     print(json.dumps(out), flush=True)

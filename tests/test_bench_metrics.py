@@ -33,3 +33,18 @@ def test_algorithmic_bytes_counts_rows_codes_and_rerank():
             + (1 + 1) * d * elem      # re-ranked rows, capped at c_max=1
             + 2 * 8 * k)              # results
     assert got == want
+
+
+def test_algorithmic_bytes_exact_distance_reads_base_rows_and_no_rerank():
+    deg = np.array([3, 2, 1, 0])
+    cand = np.array([[0, 1, 0xFFFFFFFF], [2, 0xFFFFFFFF, 0xFFFFFFFF]],
+                    dtype=np.uint32)
+    iters = np.array([2, 1])
+    R, m, d, elem, k = 4, 8, 16, 1, 2
+    got = bench.algorithmic_bytes(deg, R, m, d, elem, k, iters, cand, c_max=1,
+                                  exact=True)
+    want = (3 * 4 * R                 # three expansions, one row each
+            + (3 + 2 + 1) * d * elem  # base row of every neighbour
+            + 2 * d * elem            # two queries
+            + 2 * 8 * k)              # results; no re-rank
+    assert got == want
