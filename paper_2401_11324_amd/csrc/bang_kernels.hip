@@ -506,6 +506,38 @@ __device__ void sort_and_emit(uint64_t* S, uint32_t cnt, uint32_t k,
   }
 }
 
+// The k <= 64 smallest of the distinct keys S[i], i < cnt, ascending, to
+// the outputs (padded with (NONE, +inf)).  Lane l holds in best/at the
+// smallest of its own keys (i = l mod 64).  Each round the wave minimum is
+// the next result; only the lane that owned it rescans its keys.  k rounds
+// of a wave minimum instead of a sort of all cnt keys.
+__device__ void select_and_emit(uint64_t* S, uint32_t cnt, uint32_t k,
+                                uint64_t best, uint32_t at, uint32_t* out_ids,
+                                float* out_d, int lane) {
+  uint64_t mine = kInf;  // lane r: the r-th result
+  for (uint32_t r = 0; r < k; ++r) {
+    const uint64_t m = wave_min64(best);
+    if ((uint32_t)lane == r) mine = m;
+    if (m == kInf) break;
+    if (best == m) {  // one lane: the keys are distinct
+      S[at] = kInf;
+      best = kInf;
+      at = kNone;
+      for (uint32_t i = lane; i < cnt; i += kWave) {
+        const uint64_t v = S[i];
+        if (v < best) {
+          best = v;
+          at = i;
+        }
+      }
+    }
+  }
+  if ((uint32_t)lane < k) {
+    out_ids[lane] = mine == kInf ? kNone : key_id(mine);
+    out_d[lane] = mine == kInf ? __uint_as_float(0x7F800000u) : key_dist(mine);
+  }
+}
+
 // Partial selection sort in global memory: C[0..kk) become the kk smallest
 // of C[0..n), ascending.  For re-ranks too large for LDS (rare: an
 // expansion count far above L); one wave, with a device fence per round so
@@ -928,13 +960,24 @@ void search_kernel(SearchArgs a) {
         for (uint32_t i = lane; i < nc; i += kWave) S[i] = C[i] & ~1ull;
       }
       __syncthreads();
+      // exact keys; each lane also keeps the smallest of its own
+      uint64_t best = kInf;
+      uint32_t at = kNone;
 #pragma unroll 1
       for (uint32_t i = lane; i < nc; i += kWave) {
         const uint32_t id = key_id(S[i]);
-        S[i] = make_key(exact_dist<DT, D>(a.base, id, q, qq), id);
+        const uint64_t key = make_key(exact_dist<DT, D>(a.base, id, q, qq), id);
+        S[i] = key;
+        if (key < best) {
+          best = key;
+          at = i;
+        }
       }
       __syncthreads();
-      sort_and_emit(S, nc, a.k, oid, od, lane);
+      if (a.k <= kWave)
+        select_and_emit(S, nc, a.k, best, at, oid, od, lane);
+      else
+        sort_and_emit(S, nc, a.k, oid, od, lane);
     } else {
       // too many to sort in LDS: select in the candidate buffer itself
       for (uint32_t i = lane; i < nc; i += kWave) C[i] &= ~1ull;
