@@ -101,6 +101,17 @@ typedef struct {
                                form's BANG_TABLE_F16 / BANG_TABLE_U8, or
                                BANG_TABLE_EXACT (no table) */
   uint32_t flags;           /* 0, or BANG_SEARCH_RERANK_GLOBAL */
+  const uint32_t* query_L;  /* device [nq] or NULL: a mixed batch, query i
+                               searched with worklist size L_i in [1, L]
+                               and, with query_k, k_i results in
+                               [1, min(k, L_i)] (values out of range are
+                               clamped); its iteration cap and c_max are
+                               the defaults for L_i, so c_max and iter_cap
+                               above must be 0.  Row i of the outputs holds
+                               k_i results, then (BANG_NONE, +inf) up to k.
+                               Each query's result equals a search of that
+                               query alone with (k_i, L_i). */
+  const uint32_t* query_k;  /* device [nq] or NULL (every k_i = k) */
 } bang_search_opts;
 
 /* The re-rank sorts a query's expanded nodes in on-chip memory when they
@@ -169,6 +180,76 @@ int bang_rerank(bang_index* index, const void* queries, uint64_t nq,
 
 /* Message of the last failed call on this thread ("" if none). */
 const char* bang_last_error(void);
+
+/* ------------------------------------------------------------------------
+ * Serving: a continuous-batching request loop over one index.  The paper
+ * only batches (its experiments search a fixed batch); this is the form a
+ * search service takes.  Requests of nq queries, each with its own k and
+ * L, queue on the host.  A scheduler thread packs the oldest queued
+ * requests, up to max_batch queries, into one mixed-batch search launch
+ * (bang_search_opts.query_L / query_k) as soon as one of `slots` launch
+ * slots is free; each slot owns a HIP stream, a search workspace and
+ * pinned staging buffers, so batches on different slots overlap on the
+ * device, and requests that arrive while others are being searched start
+ * as soon as a slot frees up.  Every query's result is the one a search of
+ * that query alone with the same (k, L) returns.  Results are copied back
+ * to host memory.
+ * ---------------------------------------------------------------------- */
+typedef struct bang_server bang_server; /* opaque */
+
+typedef struct {
+  uint32_t max_batch;       /* queries per launch, 1..2^20; a request may
+                               hold at most this many */
+  uint32_t slots;           /* launches in flight at once, 1..8 */
+  uint32_t max_k;           /* largest k of a request, <= max_L */
+  uint32_t max_L;           /* largest L of a request, <= BANG_MAX_L */
+  uint32_t table;           /* BANG_TABLE_* every request is searched with */
+  uint64_t hbm_budget_bytes;/* 0, or a device-memory budget for the slots:
+                               admission by footprint, fewer slots when
+                               `slots` of them do not fit (ENOMEM if one
+                               does not) */
+} bang_server_opts;
+
+/* Allocate the slots (device workspace and buffers, pinned host buffers)
+ * and start the scheduler thread.  The index must outlive the server.
+ * Errors: EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED. */
+int bang_server_create(bang_index* index, const bang_server_opts* opts,
+                       bang_server** out);
+
+/* Finish every queued and running request, stop the scheduler and free
+ * the slots (NULL is a no-op).  Results not yet collected are dropped. */
+int bang_server_destroy(bang_server* server);
+
+/* Queue a request: nq (1..max_batch) queries in HOST memory, copied before
+ * the call returns, searched with 1 <= k <= L, k <= max_k, L <= max_L.
+ * Never waits for the device.  *ticket names the request for
+ * bang_server_wait.  Thread-safe. */
+int bang_server_submit(bang_server* server, const void* queries, uint32_t nq,
+                       uint32_t k, uint32_t L, uint64_t* ticket);
+
+/* Wait for a request (timeout_ms < 0: without limit) and copy its results
+ * to host ids[nq][k] / dists[nq][k] (either may be NULL), then forget the
+ * ticket.  EABORTED on timeout (the request stays queued and the ticket
+ * valid); a failed search returns its error.  Thread-safe. */
+int bang_server_wait(bang_server* server, uint64_t ticket, uint32_t* ids,
+                     float* dists, int timeout_ms);
+
+/* Open-loop replay, for measurement: request j arrives arrival_s[j]
+ * seconds after the call (non-decreasing) with nq[j] queries (the next
+ * rows of `queries`, host memory), k[j] and L[j].  The call submits each
+ * at its time, waits for all, and writes the results in request order to
+ * host ids / dists with row stride kstride >= max k[j] (padded with
+ * (BANG_NONE, +inf)) and latency_s[j] = completion time - arrival time
+ * (-1 for a failed request; the first failure is returned). */
+int bang_server_replay(bang_server* server, const void* queries,
+                       uint32_t nreq, const uint32_t* nq, const uint32_t* k,
+                       const uint32_t* L, const double* arrival_s,
+                       uint32_t kstride, uint32_t* ids, float* dists,
+                       double* latency_s);
+
+/* Counters: {requests submitted, launches, queries launched, most slots
+ * busy at once, slots}; the first n (<= 5) are written to out. */
+int bang_server_stats(bang_server* server, uint64_t* out, uint32_t n);
 
 #ifdef __cplusplus
 }

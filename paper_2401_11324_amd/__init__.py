@@ -26,7 +26,9 @@ INDEX_HOST_ADJ = 1
 ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EUNSUPPORTED",
           -5: "EABORTED"}
 EXPORTS = ("bang_index_create", "bang_index_destroy", "bang_build_pq_tables",
-           "bang_search", "bang_rerank", "bang_last_error")
+           "bang_search", "bang_rerank", "bang_server_create",
+           "bang_server_destroy", "bang_server_submit", "bang_server_wait",
+           "bang_server_replay", "bang_server_stats", "bang_last_error")
 
 
 class BangError(RuntimeError):
@@ -49,7 +51,15 @@ class SearchOpts(ctypes.Structure):
                 ("out_cand", ctypes.c_void_p), ("cand_stride", ctypes.c_uint32),
                 ("out_counters", ctypes.c_void_p),
                 ("out_times", ctypes.c_void_p),
-                ("table", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
+                ("table", ctypes.c_uint32), ("flags", ctypes.c_uint32),
+                ("query_L", ctypes.c_void_p), ("query_k", ctypes.c_void_p)]
+
+
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("max_batch", ctypes.c_uint32), ("slots", ctypes.c_uint32),
+                ("max_k", ctypes.c_uint32), ("max_L", ctypes.c_uint32),
+                ("table", ctypes.c_uint32),
+                ("hbm_budget_bytes", ctypes.c_uint64)]
 
 
 _lib = None
@@ -72,6 +82,14 @@ def lib():
         L.bang_search.argtypes = [P, P, u64, u32, u32, P, P,
                                   ctypes.POINTER(SearchOpts), P]
         L.bang_rerank.argtypes = [P, P, u64, P, u32, u32, P, P, P]
+        L.bang_server_create.argtypes = [P, ctypes.POINTER(ServerOpts),
+                                         ctypes.POINTER(P)]
+        L.bang_server_destroy.argtypes = [P]
+        L.bang_server_submit.argtypes = [P, P, u32, u32, u32,
+                                         ctypes.POINTER(u64)]
+        L.bang_server_wait.argtypes = [P, u64, P, P, ctypes.c_int]
+        L.bang_server_replay.argtypes = [P, P, u32, P, P, P, P, u32, P, P, P]
+        L.bang_server_stats.argtypes = [P, P, u32]
         for f in EXPORTS[:-1]:
             getattr(L, f).restype = ctypes.c_int
         L.bang_last_error.argtypes = []
@@ -188,12 +206,15 @@ class Index:
     def search(self, q, k: int, L: int, c_max: int = 0, iter_cap: int = 0,
                want_cand: int = 0, want_counters: bool = False,
                want_times: bool = False, table: str = "f32",
-               rerank_global: bool = False, out=None, stream=None):
+               rerank_global: bool = False, query_L=None, query_k=None,
+               out=None, stream=None):
         """Stages 1-3.  Returns (ids uint32-as-int32 [nq][k], dists
         float32 [nq][k]) and, on request, the expanded nodes [nq][want_cand]
         `table` is the PQ table storage the search ranks by: "f32", the
         precision form's "f16" / "u8", or "exact" (no table: exact
-        distances, no re-rank).
+        distances, no re-rank).  query_L / query_k (int32 CUDA tensors
+        [nq]) make a mixed batch: query i with its own L_i <= L and
+        k_i <= min(k, L_i), row i holding k_i results then padding.
         and counters [nq][4] (iterations, status) and device wall-clock
         ticks [nq][2] (begin, end)."""
         import torch
@@ -207,6 +228,11 @@ class Index:
             _check_out(ids, dists, nq, k, q.device)
         opts = SearchOpts(c_max, iter_cap, None, 0, None, None, TABLES[table],
                           1 if rerank_global else 0)
+        for t, nm in ((query_L, "query_L"), (query_k, "query_k")):
+            if t is not None:
+                if tuple(t.shape) != (nq,):
+                    raise ValueError(f"{nm} must have shape ({nq},)")
+                setattr(opts, nm, _dev_ptr(t, torch.int32, nm).value)
         cand = cnt = times = None
         if want_cand:
             cand = torch.empty((nq, want_cand), dtype=torch.int32,
@@ -254,3 +280,88 @@ class Index:
             cand.shape[1], k, _dev_ptr(ids, torch.int32, "ids"),
             _dev_ptr(dists, torch.float32, "dists"), _stream(stream)))
         return ids, dists
+
+
+class Server:
+    """Continuous-batching request loop over an Index (bang_server_*).
+
+    submit(q, k, L) queues a request of host queries (numpy [nq][d]) and
+    returns a ticket; wait(ticket) returns (ids uint32 [nq][k], dists
+    float32 [nq][k]).  replay() drives an open-loop arrival schedule from
+    native code and returns results and per-request latencies."""
+
+    def __init__(self, index: Index, max_batch: int = 4096, slots: int = 2,
+                 max_k: int = 100, max_L: int = 256, table: str = "f32",
+                 hbm_budget_bytes: int = 0):
+        self._h = None
+        self.index = index  # the index must outlive the server
+        o = ServerOpts(max_batch, slots, max_k, max_L, TABLES[table],
+                       hbm_budget_bytes)
+        h = ctypes.c_void_p()
+        _check(lib().bang_server_create(index._h, ctypes.byref(o),
+                                        ctypes.byref(h)))
+        self._h = h
+        self.dtype = np.dtype(index.torch_dtype)
+
+    def _q(self, q):
+        q = np.ascontiguousarray(q, dtype=self.dtype)
+        if q.ndim != 2 or q.shape[1] != self.index.d:
+            raise ValueError(f"queries must be [nq][{self.index.d}]")
+        return q
+
+    def submit(self, q, k: int, L: int) -> int:
+        q = self._q(q)
+        t = ctypes.c_uint64()
+        _check(lib().bang_server_submit(self._h, q.ctypes.data, q.shape[0], k,
+                                        L, ctypes.byref(t)))
+        self._shapes = getattr(self, "_shapes", {})
+        self._shapes[t.value] = (q.shape[0], k)
+        return t.value
+
+    def wait(self, ticket: int, timeout_ms: int = -1):
+        nq, k = self._shapes[ticket]
+        ids = np.empty((nq, k), dtype=np.uint32)
+        d = np.empty((nq, k), dtype=np.float32)
+        _check(lib().bang_server_wait(self._h, ticket, ids.ctypes.data,
+                                      d.ctypes.data, timeout_ms))
+        del self._shapes[ticket]
+        return ids, d
+
+    def replay(self, queries, nq, k, L, arrival_s, kstride: int | None = None):
+        """Open loop: request j arrives at arrival_s[j] (seconds from the
+        call) with nq[j] consecutive query rows, k[j], L[j].  Returns
+        (ids [sum nq][kstride], dists, latency_s [nreq])."""
+        q = self._q(queries)
+        nq = np.ascontiguousarray(nq, dtype=np.uint32)
+        k = np.ascontiguousarray(k, dtype=np.uint32)
+        L = np.ascontiguousarray(L, dtype=np.uint32)
+        arr = np.ascontiguousarray(arrival_s, dtype=np.float64)
+        if int(nq.sum()) > q.shape[0]:
+            raise ValueError("fewer query rows than the requests hold")
+        ks = int(kstride or k.max())
+        tot = int(nq.sum())
+        ids = np.empty((tot, ks), dtype=np.uint32)
+        d = np.empty((tot, ks), dtype=np.float32)
+        lat = np.empty(len(nq), dtype=np.float64)
+        _check(lib().bang_server_replay(
+            self._h, q.ctypes.data, len(nq), nq.ctypes.data, k.ctypes.data,
+            L.ctypes.data, arr.ctypes.data, ks, ids.ctypes.data,
+            d.ctypes.data, lat.ctypes.data))
+        return ids, d, lat
+
+    def stats(self) -> dict:
+        out = np.zeros(5, dtype=np.uint64)
+        _check(lib().bang_server_stats(self._h, out.ctypes.data, 5))
+        return dict(zip(("requests", "launches", "queries", "max_in_flight",
+                         "slots"), (int(x) for x in out)))
+
+    def close(self):
+        if self._h is not None and _lib is not None:
+            lib().bang_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

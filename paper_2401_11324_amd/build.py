@@ -8,7 +8,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "_bang.so")
-SOURCES = [os.path.join(CSRC, f) for f in ("bang_kernels.hip", "bang_api.cpp")]
+SOURCES = [os.path.join(CSRC, f)
+           for f in ("bang_kernels.hip", "bang_api.cpp", "bang_server.cpp")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # -ffp-contract=off: no fused multiply-add (fixed FP32 rounding sequence).

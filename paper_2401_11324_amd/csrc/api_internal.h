@@ -1,0 +1,64 @@
+// Host-side state shared by the C ABI (bang_api.cpp) and the serving loop
+// (bang_server.cpp): the index object, search workspaces, error reporting
+// and the validated search entry.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "bang.h"
+#include "internal.h"
+
+namespace bang {
+
+// Device memory one search launch needs besides its inputs and outputs:
+// the expanded-node keys of every resident wave and the two counters of
+// the persistent launch (zero between launches).  Launches that overlap in
+// time need workspaces of their own.
+struct Workspace {
+  uint64_t* cscratch = nullptr;
+  size_t cscratch_bytes = 0;
+  uint32_t* qcounter = nullptr;
+};
+
+int workspace_init(Workspace* ws, size_t cscratch_bytes);
+void workspace_free(Workspace* ws);
+
+// Sets the thread-local error message and returns code.
+int fail(int code, const std::string& msg);
+int hip_fail(hipError_t e, const char* what);
+const char* last_error();
+
+}  // namespace bang
+
+struct bang_index {
+  int device = 0;
+  bang::DeviceIndex dev{};
+  void* d_base = nullptr;
+  unsigned char* d_rows = nullptr;
+  uint32_t* h_adj = nullptr;  // pinned host adjacency (BANG_INDEX_HOST_ADJ)
+  uint8_t* d_codes = nullptr;
+  float* d_cb = nullptr;
+  bang::Workspace ws;         // used by bang_search; grown on demand
+  int num_cus = 0;
+  int max_lds = 64 * 1024;    // dynamic LDS bytes one workgroup may use
+};
+
+namespace bang {
+
+// Workspace bytes a launch with these parameters needs (grid x iter_cap
+// keys); 0 with an error set if the launch cannot run at all.
+size_t search_workspace_bytes(bang_index* ix, uint64_t nq, uint32_t L,
+                              uint32_t iter_cap, uint32_t table);
+
+// bang_search on an explicit workspace.  grow = false: a workspace that is
+// too small is an error instead of being reallocated (reallocation
+// synchronises the device).
+int search_with(bang_index* ix, Workspace* ws, bool grow, const void* queries,
+                uint64_t nq, uint32_t k, uint32_t L, uint32_t* out_ids,
+                float* out_dists, const bang_search_opts* o, hipStream_t s);
+
+}  // namespace bang

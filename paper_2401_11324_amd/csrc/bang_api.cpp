@@ -12,28 +12,13 @@
 #include <thread>
 #include <vector>
 
-#include "bang.h"
-#include "internal.h"
+#include "api_internal.h"
 
-struct bang_index {
-  int device = 0;
-  bang::DeviceIndex dev{};
-  void* d_base = nullptr;
-  unsigned char* d_rows = nullptr;
-  uint32_t* h_adj = nullptr;  // pinned host adjacency (BANG_INDEX_HOST_ADJ)
-  uint8_t* d_codes = nullptr;
-  float* d_cb = nullptr;
-  // search workspace, grown on demand
-  uint64_t* d_cscratch = nullptr;
-  size_t cscratch_bytes = 0;
-  uint32_t* d_qcounter = nullptr;
-  int num_cus = 0;
-  int max_lds = 64 * 1024;  // dynamic LDS bytes one workgroup may use
-};
+namespace bang {
 
 namespace {
-
 thread_local std::string g_err;
+}
 
 int fail(int code, const std::string& msg) {
   g_err = msg;
@@ -44,6 +29,44 @@ int hip_fail(hipError_t e, const char* what) {
   return fail(BANG_EDEVICE,
               std::string(what) + ": " + hipGetErrorString(e));
 }
+
+const char* last_error() { return g_err.c_str(); }
+
+int workspace_init(Workspace* ws, size_t cscratch_bytes) {
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(&ws->qcounter),
+                           2 * sizeof(uint32_t));
+  if (e != hipSuccess) {
+    ws->qcounter = nullptr;
+    return fail(BANG_ENOMEM, std::string("search counters: ") +
+                                 hipGetErrorString(e));
+  }
+  // the counters start at zero; every launch leaves them at zero
+  e = hipMemset(ws->qcounter, 0, 2 * sizeof(uint32_t));
+  if (e != hipSuccess) return hip_fail(e, "clearing the search counters");
+  if (cscratch_bytes) {
+    e = hipMalloc(reinterpret_cast<void**>(&ws->cscratch), cscratch_bytes);
+    if (e != hipSuccess) {
+      ws->cscratch = nullptr;
+      return fail(BANG_ENOMEM, std::string("search workspace: ") +
+                                   hipGetErrorString(e));
+    }
+    ws->cscratch_bytes = cscratch_bytes;
+  }
+  return BANG_OK;
+}
+
+void workspace_free(Workspace* ws) {
+  (void)hipFree(ws->cscratch);
+  (void)hipFree(ws->qcounter);
+  *ws = Workspace{};
+}
+
+}  // namespace bang
+
+using bang::fail;
+using bang::hip_fail;
+
+namespace {
 
 size_t elem_size(int dt) { return dt == BANG_F32 ? 4 : 1; }
 
@@ -112,8 +135,7 @@ void free_index(bang_index* ix) {
   if (ix->h_adj) (void)hipHostFree(ix->h_adj);
   (void)hipFree(ix->d_codes);
   (void)hipFree(ix->d_cb);
-  (void)hipFree(ix->d_cscratch);
-  (void)hipFree(ix->d_qcounter);
+  bang::workspace_free(&ix->ws);
   delete ix;
 }
 
@@ -173,16 +195,10 @@ int create_impl(const bang_index_desc* d, bang_index** out) {
       (rc = upload(&ix->d_codes, d->codes, (size_t)d->n * d->m, "codes")) ||
       (rc = upload(&ix->d_cb, d->codebooks, (size_t)d->m * 256 * (d->d / d->m) * 4,
                    "codebooks")) ||
-      (rc = upload(&ix->d_qcounter, nullptr, 0, "counters"))) {
+      (rc = bang::workspace_init(&ix->ws, 0))) {
     (void)hipFree(d_adj);
     free_index(ix);
     return rc;
-  }
-  // the two search counters start at zero; each launch leaves them at zero
-  e = hipMemset(ix->d_qcounter, 0, 2 * sizeof(uint32_t));
-  if (e != hipSuccess) {
-    free_index(ix);
-    return hip_fail(e, "clearing the search counters");
   }
   if (host_adj) {
     // page-locked, GPU-cacheable (the kernels only read it), mapped into
@@ -249,9 +265,40 @@ int check_queries(const bang_index* ix, const void* queries) {
   return BANG_OK;
 }
 
-int search_impl(bang_index* ix, const void* queries, uint64_t nq, uint32_t k,
-                uint32_t L, uint32_t* out_ids, float* out_dists,
-                const bang_search_opts* o, hipStream_t s) {
+// Launch geometry of a search: LDS bytes and resident workgroups.
+int search_geometry(bang_index* ix, uint64_t nq, uint32_t L, uint32_t iter_cap,
+                    uint32_t table, size_t* lds, uint64_t* grid) {
+  *lds = bang::search_lds_bytes(ix->dev.m, L, iter_cap, (int)table);
+  hipError_t e = hipSetDevice(ix->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  if (*lds > (size_t)ix->max_lds)
+    return fail(BANG_EUNSUPPORTED,
+                "table + worklist + re-rank keys need " + std::to_string(*lds) +
+                    " bytes of LDS, the device allows " +
+                    std::to_string(ix->max_lds) + " (lower L or iter_cap)");
+  int per_cu = 0;
+  e = bang::search_occupancy(ix->dev, (int)table, *lds, &per_cu);
+  if (e != hipSuccess) return hip_fail(e, "occupancy query");
+  if (per_cu < 1) return fail(BANG_EUNSUPPORTED, "search kernel cannot be resident");
+  *grid = std::min<uint64_t>((uint64_t)per_cu * ix->num_cus, nq);
+  return BANG_OK;
+}
+
+}  // namespace
+
+namespace bang {
+
+size_t search_workspace_bytes(bang_index* ix, uint64_t nq, uint32_t L,
+                              uint32_t iter_cap, uint32_t table) {
+  size_t lds;
+  uint64_t grid;
+  if (search_geometry(ix, nq, L, iter_cap, table, &lds, &grid)) return 0;
+  return (size_t)grid * iter_cap * sizeof(uint64_t);
+}
+
+int search_with(bang_index* ix, Workspace* ws, bool grow, const void* queries,
+                uint64_t nq, uint32_t k, uint32_t L, uint32_t* out_ids,
+                float* out_dists, const bang_search_opts* o, hipStream_t s) {
   if (!ix) return fail(BANG_EINVAL, "null index");
   if (k < 1 || k > L || L > BANG_MAX_L)
     return fail(BANG_EINVAL, "need 1 <= k <= L <= 1024");
@@ -263,6 +310,14 @@ int search_impl(bang_index* ix, const void* queries, uint64_t nq, uint32_t k,
   if (!out_ids || !out_dists) return fail(BANG_EINVAL, "null output");
   if (!aligned(out_ids, 4) || !aligned(out_dists, 4))
     return fail(BANG_EINVAL, "outputs not 4-byte aligned");
+  const bool mixed = o && (o->query_L || o->query_k);
+  if (mixed && (o->c_max || o->iter_cap))
+    return fail(BANG_EINVAL,
+                "a mixed batch (query_L / query_k) takes the default c_max "
+                "and iter_cap of each query's L");
+  if (o && ((o->query_L && !aligned(o->query_L, 4)) ||
+            (o->query_k && !aligned(o->query_k, 4))))
+    return fail(BANG_EINVAL, "query_L / query_k not 4-byte aligned");
   uint32_t c_max = (o && o->c_max) ? o->c_max : 4 * L;
   uint32_t iter_cap = (o && o->iter_cap) ? o->iter_cap : std::max(4 * L, L + 64);
   const uint32_t table = o ? o->table : BANG_TABLE_F32;
@@ -270,35 +325,32 @@ int search_impl(bang_index* ix, const void* queries, uint64_t nq, uint32_t k,
   if (iter_cap > 8192) return fail(BANG_EINVAL, "iter_cap > 8192");
   if (o && o->out_cand && o->cand_stride == 0)
     return fail(BANG_EINVAL, "cand_stride must be > 0 with out_cand");
+  const uint32_t flags = o ? o->flags : 0u;
+  if (flags & ~BANG_SEARCH_RERANK_GLOBAL)
+    return fail(BANG_EINVAL, "unknown search flags");
 
-  size_t lds = bang::search_lds_bytes(ix->dev.m, L, iter_cap, (int)table);
-  int per_cu = 0;
-  hipError_t e = hipSetDevice(ix->device);
-  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
-  if (lds > (size_t)ix->max_lds)
-    return fail(BANG_EUNSUPPORTED,
-                "table + worklist + re-rank keys need " + std::to_string(lds) +
-                    " bytes of LDS, the device allows " +
-                    std::to_string(ix->max_lds) + " (lower L or iter_cap)");
-  e = bang::search_occupancy(ix->dev, (int)table, lds, &per_cu);
-  if (e != hipSuccess) return hip_fail(e, "occupancy query");
-  if (per_cu < 1) return fail(BANG_EUNSUPPORTED, "search kernel cannot be resident");
-  uint64_t grid = (uint64_t)per_cu * ix->num_cus;
-  if (grid > nq) grid = nq;
-
+  size_t lds;
+  uint64_t grid;
+  rc = search_geometry(ix, nq, L, iter_cap, table, &lds, &grid);
+  if (rc) return rc;
   size_t need = (size_t)grid * iter_cap * sizeof(uint64_t);
-  if (need > ix->cscratch_bytes) {
+  if (need > ws->cscratch_bytes) {
+    if (!grow)
+      return fail(BANG_ENOMEM, "search workspace of " +
+                                   std::to_string(ws->cscratch_bytes) +
+                                   " bytes, the launch needs " +
+                                   std::to_string(need));
     // the previous workspace may still be in use by queued work
-    e = hipDeviceSynchronize();
+    hipError_t e = hipDeviceSynchronize();
     if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
-    (void)hipFree(ix->d_cscratch);
-    ix->d_cscratch = nullptr;
-    ix->cscratch_bytes = 0;
-    e = hipMalloc(reinterpret_cast<void**>(&ix->d_cscratch), need);
+    (void)hipFree(ws->cscratch);
+    ws->cscratch = nullptr;
+    ws->cscratch_bytes = 0;
+    e = hipMalloc(reinterpret_cast<void**>(&ws->cscratch), need);
     if (e != hipSuccess)
       return fail(BANG_ENOMEM, std::string("search workspace: ") +
                                    hipGetErrorString(e));
-    ix->cscratch_bytes = need;
+    ws->cscratch_bytes = need;
   }
 
   bang::SearchLaunch l{};
@@ -309,23 +361,26 @@ int search_impl(bang_index* ix, const void* queries, uint64_t nq, uint32_t k,
   l.c_max = c_max;
   l.iter_cap = iter_cap;
   l.table = (int)table;
-  l.flags = o ? o->flags : 0u;
-  if (l.flags & ~BANG_SEARCH_RERANK_GLOBAL)
-    return fail(BANG_EINVAL, "unknown search flags");
+  l.flags = flags;
   l.out_ids = out_ids;
   l.out_dists = out_dists;
+  l.qL = o ? o->query_L : nullptr;
+  l.qk = o ? o->query_k : nullptr;
   l.out_cand = o ? o->out_cand : nullptr;
   l.cand_stride = o ? o->cand_stride : 0;
   l.out_counters = o ? o->out_counters : nullptr;
   l.out_times = o ? o->out_times : nullptr;
-  l.cscratch = ix->d_cscratch;
-  l.qcounter = ix->d_qcounter;
+  l.cscratch = ws->cscratch;
+  l.qcounter = ws->qcounter;
   l.grid = (uint32_t)grid;
-  e = bang::launch_search(ix->dev, l, s);
+  hipError_t e = bang::launch_search(ix->dev, l, s);
   if (e != hipSuccess) return hip_fail(e, "search launch");
   return BANG_OK;
 }
 
+}  // namespace bang
+
+namespace {
 }  // namespace
 
 extern "C" {
@@ -372,8 +427,9 @@ int bang_search(bang_index* ix, const void* queries, uint64_t nq, uint32_t k,
                 uint32_t L, uint32_t* out_ids, float* out_dists,
                 const bang_search_opts* opts, void* stream) {
   try {
-    return search_impl(ix, queries, nq, k, L, out_ids, out_dists, opts,
-                       static_cast<hipStream_t>(stream));
+    if (!ix) return fail(BANG_EINVAL, "null index");
+    return bang::search_with(ix, &ix->ws, true, queries, nq, k, L, out_ids,
+                             out_dists, opts, static_cast<hipStream_t>(stream));
   } catch (...) {
     return fail(BANG_ENOMEM, "exception");
   }
@@ -403,6 +459,6 @@ int bang_rerank(bang_index* ix, const void* queries, uint64_t nq,
   }
 }
 
-const char* bang_last_error(void) { return g_err.c_str(); }
+const char* bang_last_error(void) { return bang::last_error(); }
 
 }  // extern "C"

@@ -583,8 +583,13 @@ struct SearchArgs {
                      // together with the worklist buffer)
   uint32_t s_cap;    // keys that fit there: (region0 + 8 * lrow) / 8, or
                      // 0 to make the re-rank select in global memory
-  uint32_t* out_ids;
+  uint32_t* out_ids;   // [nq][k]: k is the row stride
   float* out_dists;
+  // optional per-query worklist size and k (mixed batches): L_q in [1,
+  // Lcap] and k_q in [1, min(k, L_q)] (clamped into range); the iteration
+  // cap and c_max then follow L_q as their defaults do
+  const uint32_t* qL;
+  const uint32_t* qk;
   uint32_t* out_cand;
   uint32_t cand_stride;
   uint32_t* out_counters;
@@ -686,6 +691,14 @@ void search_kernel(SearchArgs a) {
     }
     const unsigned char* q = a.queries + (size_t)qi * D * Elem<DT>::size;
     const uint64_t t_begin = a.out_times ? wall_clock64() : 0;
+    // this query's worklist size, result count, iteration cap and c_max
+    uint32_t Lq = a.Lcap, kq = a.k, capq = a.iter_cap, cmq = a.c_max;
+    if (a.qL) {
+      Lq = min(max(a.qL[qi], 1u), a.Lcap);
+      capq = min(max(4u * Lq, Lq + 64u), a.iter_cap);
+      cmq = 4u * Lq;
+    }
+    if (a.qk) kq = min(max(a.qk[qi], 1u), min(a.k, Lq));
 
     // stage 1: the table (the previous query's re-rank is done with S)
     __syncthreads();
@@ -717,7 +730,7 @@ void search_kernel(SearchArgs a) {
     __syncthreads();
 
     while (cur != kNone) {
-      if (iters == a.iter_cap) {
+      if (iters == capq) {
         status = 1;
         break;
       }
@@ -759,7 +772,7 @@ void search_kernel(SearchArgs a) {
       if (key != kInf) {
         uint64_t ge;
         r = rank_in(Lc, Llen, last, key, ge);
-        keep = (ge >> 1) != (key >> 1) && r < a.Lcap;
+        keep = (ge >> 1) != (key >> 1) && r < Lq;
       }
       const uint64_t kk = keep ? key : kInf;
 
@@ -807,7 +820,7 @@ void search_kernel(SearchArgs a) {
       if (bkey < akey) {
         const uint64_t bl = __ballot(kk == bkey);
         const uint32_t bpos = first_of(r, bl);
-        if (bpos < a.Lcap) {
+        if (bpos < Lq) {
           best = bpos;
           bestkey = bkey;
         }
@@ -909,14 +922,14 @@ void search_kernel(SearchArgs a) {
           sh += (hb_at[sr] >> (8 * t)) & 0xFFu;
           if (v[t] != kInf) {
             const uint32_t p = j + carry_at[sr] + excl_at[sr] + sh;
-            if (p < a.Lcap) Lc[p] = v[t];
+            if (p < Lq) Lc[p] = v[t];
           }
         }
       }
-      if (keep && r + rn < a.Lcap) Lc[r + rn] = key;
+      if (keep && r + rn < Lq) Lc[r + rn] = key;
       // clear the histogram bytes used (positions rmin .. Llen)
       for (uint32_t t = rmin / 4 + lane; t <= Llen / 4; t += kWave) Hw[t] = 0u;
-      Llen = min(a.Lcap, Llen + nv);
+      Llen = min(Lq, Llen + nv);
       cur = best;
       curkey = bestkey;
       __syncthreads();
@@ -941,21 +954,21 @@ void search_kernel(SearchArgs a) {
     float* od = a.out_dists + (size_t)qi * a.k;
     if constexpr (kExact) {
       // no re-rank: the worklist already ranks by exact distance
-      for (uint32_t i = lane; i < a.k; i += kWave) {
+      for (uint32_t i = lane; i < kq; i += kWave) {
         const uint64_t key = i < Llen ? Lc[i] : kInf;
         oid[i] = key == kInf ? kNone : key_id(key);
         od[i] = key == kInf ? __uint_as_float(0x7F800000u) : key_dist(key);
       }
     } else if (qq = query_sq<DT, D>(q); pow2ceil_dev(nc) <= a.s_cap) {
       // sort in LDS (table region + worklist buffer, free now)
-      if (nc > a.c_max) {
+      if (nc > cmq) {
         // keep the c_max smallest (PQ distance, id)
         const uint32_t P = pow2ceil_dev(nc);
         for (uint32_t i = lane; i < P; i += kWave)
           S[i] = i < nc ? (C[i] & ~1ull) : kInf;
         __syncthreads();
         lds_sort(S, P, lane);
-        nc = a.c_max;
+        nc = cmq;
       } else {
         for (uint32_t i = lane; i < nc; i += kWave) S[i] = C[i] & ~1ull;
       }
@@ -974,18 +987,18 @@ void search_kernel(SearchArgs a) {
         }
       }
       __syncthreads();
-      if (a.k <= kWave)
-        select_and_emit(S, nc, a.k, best, at, oid, od, lane);
+      if (kq <= kWave)
+        select_and_emit(S, nc, kq, best, at, oid, od, lane);
       else
-        sort_and_emit(S, nc, a.k, oid, od, lane);
+        sort_and_emit(S, nc, kq, oid, od, lane);
     } else {
       // too many to sort in LDS: select in the candidate buffer itself
       for (uint32_t i = lane; i < nc; i += kWave) C[i] &= ~1ull;
       __threadfence();
       __syncthreads();
-      if (nc > a.c_max) {
-        global_select(C, nc, a.c_max, lane);
-        nc = a.c_max;
+      if (nc > cmq) {
+        global_select(C, nc, cmq, lane);
+        nc = cmq;
       }
 #pragma unroll 1
       for (uint32_t i = lane; i < nc; i += kWave) {
@@ -994,12 +1007,17 @@ void search_kernel(SearchArgs a) {
       }
       __threadfence();
       __syncthreads();
-      global_select(C, nc, a.k, lane);
-      for (uint32_t i = lane; i < a.k; i += kWave) {
+      global_select(C, nc, kq, lane);
+      for (uint32_t i = lane; i < kq; i += kWave) {
         const uint64_t key = i < nc ? C[i] : kInf;
         oid[i] = key == kInf ? kNone : key_id(key);
         od[i] = key == kInf ? __uint_as_float(0x7F800000u) : key_dist(key);
       }
+    }
+    // a row of a mixed batch holds k_q results, then padding
+    for (uint32_t i = kq + lane; i < a.k; i += kWave) {
+      oid[i] = kNone;
+      od[i] = __uint_as_float(0x7F800000u);
     }
     if (a.out_times && lane == 0) {
       a.out_times[qi * 2] = t_begin;
@@ -1282,6 +1300,8 @@ hipError_t launch_search(const DeviceIndex& ix, const SearchLaunch& l,
   a.s_cap = (l.flags & 1u) ? 0u : (a.region0 + 8u * a.lrow) / 8u;
   a.out_ids = l.out_ids;
   a.out_dists = l.out_dists;
+  a.qL = l.qL;
+  a.qk = l.qk;
   a.out_cand = l.out_cand;
   a.cand_stride = l.cand_stride;
   a.out_counters = l.out_counters;

@@ -30,6 +30,8 @@ struct SearchLaunch {
   uint32_t flags;        // bang_search_opts.flags
   uint32_t* out_ids;
   float* out_dists;
+  const uint32_t* qL;    // per-query L / k (device, [nq]) or null
+  const uint32_t* qk;
   uint32_t* out_cand;
   uint32_t cand_stride;
   uint32_t* out_counters;

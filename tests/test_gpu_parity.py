@@ -383,3 +383,101 @@ def test_sift1m_exact_distance_sampled_bit_exact():
         assert np.array_equal(f32bits(dist.cpu().numpy()[sample]),
                               f32bits(ref["dists"])), L
     gi.close()
+
+
+# --------------------------------------------------------------------------
+# mixed batches (per-query k and L) and the serving loop: every result is
+# the one the query gets alone
+# --------------------------------------------------------------------------
+def _alone(gi, q, k, L, table):
+    ids, d = gi.search(to_dev(q), k, L, table=table)
+    torch.cuda.synchronize()
+    return u32(ids), d.cpu().numpy()
+
+
+@pytest.mark.parametrize("name", ["u8-d128-m32", "f32-d32-m16", "i8-d96-m48"])
+@pytest.mark.parametrize("table", ["f32", "u8", "exact"])
+def test_mixed_batch_equals_each_query_alone(small_indexes, name, table):
+    ix, q, gi = small_indexes[name]
+    rng = np.random.default_rng(7)
+    nq = len(q)
+    Ls = rng.choice([1, 10, 33, 100, 256], nq).astype(np.int32)
+    ks = np.array([rng.integers(1, min(32, L) + 1) for L in Ls], np.int32)
+    kmax, Lmax = int(ks.max()), int(Ls.max())
+    ids, d = gi.search(to_dev(q), kmax, Lmax, table=table,
+                       query_L=to_dev(Ls), query_k=to_dev(ks))
+    torch.cuda.synchronize()
+    ids, d = u32(ids), d.cpu().numpy()
+    for (k, L) in sorted(set(zip(ks.tolist(), Ls.tolist()))):
+        sel = np.where((ks == k) & (Ls == L))[0]
+        a_ids, a_d = _alone(gi, q[sel], k, L, table)
+        assert np.array_equal(ids[sel, :k], a_ids), (k, L)
+        assert np.array_equal(f32bits(d[sel, :k]), f32bits(a_d)), (k, L)
+        assert (ids[sel, k:] == NONE).all() and np.isinf(d[sel, k:]).all()
+        ref = oracle.search(ix, q[sel], k, L, table=table)
+        assert np.array_equal(a_ids, ref["ids"]), (k, L)
+
+
+def test_server_replay_results_equal_alone(small_indexes):
+    """Requests with mixed sizes, k and L arrive open-loop (Poisson) and
+    overlap on the device in two slots; each result equals a search of its
+    queries alone."""
+    ix, q, gi = small_indexes["u8-d128-m32"]
+    bang = bang_mod()
+    rng = np.random.default_rng(11)
+    nreq = 60
+    nq = rng.integers(1, 9, nreq).astype(np.uint32)
+    k = rng.choice([1, 5, 10, 32], nreq).astype(np.uint32)
+    L = np.maximum(k, rng.choice([16, 33, 64, 128], nreq)).astype(np.uint32)
+    rows = rng.integers(0, len(q), int(nq.sum()))
+    Q = q[rows]
+    arr = np.cumsum(rng.exponential(2e-4, nreq))
+    sv = bang.Server(gi, max_batch=24, slots=2, max_k=32, max_L=128)
+    ids, d, lat = sv.replay(Q, nq, k, L, arr, kstride=32)
+    st = sv.stats()
+    sv.close()
+    assert st["requests"] == nreq and st["queries"] == int(nq.sum())
+    assert (lat >= 0).all()
+    off = 0
+    for j in range(nreq):
+        sl = slice(off, off + int(nq[j]))
+        a_ids, a_d = _alone(gi, Q[sl], int(k[j]), int(L[j]), "f32")
+        assert np.array_equal(ids[sl, :k[j]], a_ids), j
+        assert np.array_equal(f32bits(d[sl, :k[j]]), f32bits(a_d)), j
+        assert (ids[sl, k[j]:] == NONE).all()
+        off += int(nq[j])
+
+
+def test_server_threads_submit_and_wait(small_indexes):
+    """Several host threads submit and wait at once; every ticket returns
+    its own request's results."""
+    import threading
+    ix, q, gi = small_indexes["f32-d32-m16"]
+    bang = bang_mod()
+    sv = bang.Server(gi, max_batch=16, slots=3, max_k=10, max_L=64,
+                     table="exact")
+    errors = []
+
+    def worker(seed):
+        r = np.random.default_rng(seed)
+        try:
+            for _ in range(15):
+                n = int(r.integers(1, 6))
+                sel = r.integers(0, len(q), n)
+                kk, LL = int(r.choice([1, 10])), int(r.choice([10, 33, 64]))
+                t = sv.submit(q[sel], kk, LL)
+                got_ids, got_d = sv.wait(t)
+                a_ids, a_d = _alone(gi, q[sel], kk, LL, "exact")
+                if not (np.array_equal(got_ids, a_ids)
+                        and np.array_equal(f32bits(got_d), f32bits(a_d))):
+                    errors.append((seed, n, kk, LL))
+        except Exception as ex:  # surfaced below
+            errors.append(repr(ex))
+
+    th = [threading.Thread(target=worker, args=(s,)) for s in range(4)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    sv.close()
+    assert not errors, errors
