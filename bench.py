@@ -101,6 +101,41 @@ def cpu_baseline(idx_np, queries, k, L, budget_s=15.0):
                       f"{threads} threads"}
 
 
+SERVE_RATES = (1e4, 1e5, 1e6)      # offered queries/s
+SERVE_P99_TARGET_MS = 50.0
+SERVE_CANDIDATES = ((1024, 2), (4096, 2), (4096, 4), (16384, 2))
+
+
+def serving_section(gi, d, w, gt):
+    """The serving loop on the resident index: the autotuner picks batch
+    size and slot count on a calibration stream, then open-loop Poisson
+    streams at each offered rate (requests of 1-256 queries, k in {10,
+    100}, L in {32, 64, 128}) report sustained rate, p50/p99 request
+    latency and recall@10 of every served query."""
+    import synth
+    from paper_2401_11324_amd import serving
+    qnp = d["queries"]
+    max_k, max_L = 100, 128
+    # calibrate near the highest offered rate, where the candidates differ
+    calib = synth.serving_requests(w, SERVE_RATES[-1], 0.2, salt=1)
+    (mb, sl), trials = serving.autotune(gi, qnp, calib, SERVE_CANDIDATES,
+                                        max_k, max_L, SERVE_P99_TARGET_MS)
+    rates = []
+    for i, rate in enumerate(SERVE_RATES):
+        req = synth.serving_requests(w, rate, min(1.0, 2e5 / rate),
+                                     salt=10 + i)
+        s, ids, _ = serving.run_load(gi, qnp, req, mb, sl, max_k, max_L)
+        s["recall10"] = round(recall_at_k(ids[:, :10], gt[req["rows"]], 10), 4)
+        rates.append(s)
+    return {"table": "f32",
+            "requests": "sizes log-uniform 1-256 queries, k in {10,100}, "
+                        "L in {32,64,128} raised to k, Poisson arrivals",
+            "autotune": {"chosen": {"max_batch": mb, "slots": sl},
+                         "p99_target_ms": SERVE_P99_TARGET_MS,
+                         "trials": trials},
+            "rates": rates}
+
+
 def copy_probe(mib: int) -> int:
     """A plain copy of `mib` MiB between two device buffers (reads and
     writes exactly that many bytes); its FETCH_SIZE / WRITE_SIZE readings
@@ -131,6 +166,8 @@ def main(argv=None):
                     help="skip the recall sweep (needs --L)")
     ap.add_argument("--no-host", action="store_true",
                     help="skip the host-resident adjacency measurement")
+    ap.add_argument("--no-serve", action="store_true",
+                    help="skip the serving-loop measurement")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB mebibytes "
                          "(calibrates the HBM byte counters) and exit")
@@ -312,6 +349,8 @@ def main(argv=None):
     }
     if host is not None:
         out["host_resident"] = host
+    if not a.no_serve:
+        out["serving"] = serving_section(gi, d, w, gt)
     if exact is not None:
         out["exact_distance"] = exact
     if not a.no_cpu:

@@ -124,3 +124,33 @@ def small(dtype: str = "f32", n: int = 2000, d: int = 32, nq: int = 20,
                 Ls=(32,))
     base.update(kw)
     return Workload(**base)
+
+
+def serving_requests(w: Workload, rate_qps: float, duration_s: float,
+                     salt: int = 0, nq_max: int = 256, ks=(10, 100),
+                     Ls=(32, 64, 128)):
+    """An open-loop request stream over the workload's queries: request
+    sizes log-uniform in [1, nq_max] queries, k and L drawn uniformly from
+    `ks` and `Ls` (L raised to k where k > L: the worklist holds at least
+    the k results), arrivals a Poisson process whose mean query rate is
+    rate_qps, for duration_s seconds.  Query rows are drawn uniformly from
+    the workload's queries.  Seeded by (workload, salt).
+
+    Returns dict(nq, k, L, arrival_s, rows): per-request arrays and the
+    concatenated query row indices."""
+    rng = np.random.default_rng(
+        np.random.SeedSequence([SEED_BASE + w.index, 99, int(salt)]))
+    mean_nq = (nq_max - 1) / np.log(nq_max) if nq_max > 1 else 1.0
+    rate_req = rate_qps / mean_nq
+    n_exp = int(rate_req * duration_s * 1.2) + 16
+    gaps = rng.exponential(1.0 / rate_req, n_exp)
+    arrival = np.cumsum(gaps)
+    arrival = arrival[arrival < duration_s]
+    nreq = max(1, len(arrival))
+    arrival = arrival[:nreq] if len(arrival) else np.zeros(1)
+    nq = np.floor(np.exp(rng.uniform(0.0, np.log(nq_max + 1), nreq)))
+    nq = np.clip(nq, 1, nq_max).astype(np.uint32)
+    k = rng.choice(np.asarray(ks), nreq).astype(np.uint32)
+    L = np.maximum(rng.choice(np.asarray(Ls), nreq), k).astype(np.uint32)
+    rows = rng.integers(0, w.nq, int(nq.sum()))
+    return {"nq": nq, "k": k, "L": L, "arrival_s": arrival, "rows": rows}

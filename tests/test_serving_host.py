@@ -1,0 +1,41 @@
+"""Host-side pieces of the serving measurement (no GPU): the seeded
+request stream and the autotuner's choice rule."""
+import numpy as np
+
+import synth
+from paper_2401_11324_amd import serving
+
+
+def test_request_stream_is_seeded_and_well_formed():
+    w = synth.WORKLOADS["sift1m"]
+    a = synth.serving_requests(w, 1e5, 0.5, salt=3)
+    b = synth.serving_requests(w, 1e5, 0.5, salt=3)
+    for key in a:
+        assert np.array_equal(a[key], b[key])
+    c = synth.serving_requests(w, 1e5, 0.5, salt=4)
+    assert not np.array_equal(a["arrival_s"], c["arrival_s"])
+    assert (np.diff(a["arrival_s"]) >= 0).all()
+    assert a["arrival_s"].max() < 0.5
+    assert ((a["nq"] >= 1) & (a["nq"] <= 256)).all()
+    assert set(a["k"].tolist()) <= {10, 100}
+    assert (a["L"] >= a["k"]).all()
+    assert set(a["L"].tolist()) <= {32, 64, 100, 128}
+    assert len(a["rows"]) == a["nq"].sum() and a["rows"].max() < w.nq
+    # the mean query rate is the offered one, within sampling noise
+    rate = a["nq"].sum() / 0.5
+    assert 0.7e5 < rate < 1.3e5
+
+
+def test_autotune_choice_rule():
+    t = [{"max_batch": 1, "slots": 1, "sustained_qps": 5.0, "p99_ms": 10.0},
+         {"max_batch": 2, "slots": 1, "sustained_qps": 9.0, "p99_ms": 60.0},
+         {"max_batch": 3, "slots": 2, "sustained_qps": 7.0, "p99_ms": 40.0}]
+    assert serving.choose(t, 50.0)["max_batch"] == 3   # fastest within target
+    assert serving.choose(t, 5.0)["max_batch"] == 1    # none: lowest p99
+
+
+def test_autotune_prefers_lower_p99_when_rates_tie():
+    t = [{"max_batch": 1, "slots": 1, "sustained_qps": 100.0, "p99_ms": 9.0},
+         {"max_batch": 2, "slots": 2, "sustained_qps": 99.5, "p99_ms": 3.0},
+         {"max_batch": 3, "slots": 2, "sustained_qps": 90.0, "p99_ms": 1.0}]
+    assert serving.choose(t, 50.0)["max_batch"] == 2
