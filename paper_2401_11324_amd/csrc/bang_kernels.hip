@@ -324,7 +324,9 @@ __device__ __forceinline__ int32_t query_sq(const unsigned char* q) {
 // Integer data: sum (x - q)^2 = sum x^2 - 2 sum x q + qq (qq = query_sq),
 // each sum exact from four-byte dot products, so the value is the plain
 // integer sum (below 2^24, exact in FP32).
-template <int DT, int D>
+// EAGER: every load of the row is issued before the first product (one
+// memory round trip, D/4 more registers); otherwise two chunks at a time.
+template <int DT, int D, bool EAGER = false>
 __device__ __forceinline__ float exact_dist(const void* __restrict__ base,
                                             uint32_t id,
                                             const unsigned char* q,
@@ -352,9 +354,14 @@ __device__ __forceinline__ float exact_dist(const void* __restrict__ base,
         (const uint8_t*)base + (size_t)id * D);
     const uint32_t* qw = reinterpret_cast<const uint32_t*>(q);
     uint32_t xx = 0, xq = 0;
-#pragma unroll 2
+    uint4 row[EAGER ? D / 16 : 1];
+    if constexpr (EAGER) {
+#pragma unroll
+      for (int c = 0; c < D / 16; ++c) row[c] = x[c];
+    }
+#pragma unroll(EAGER ? D / 16 : 2)
     for (int c = 0; c < D / 16; ++c) {
-      const uint4 v = x[c];
+      const uint4 v = EAGER ? row[EAGER ? c : 0] : x[c];
       const uint32_t w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
@@ -758,7 +765,8 @@ void search_kernel(SearchArgs a) {
       // distances of the neighbours (row of u*, loaded earlier)
       uint64_t key = kInf;
       if constexpr (kExact) {
-        if (nb != kNone) key = make_key(exact_dist<DT, D>(a.base, nb, q, qq), nb);
+        if (nb != kNone)
+          key = make_key(exact_dist<DT, D, true>(a.base, nb, q, qq), nb);
       } else {
         gather_codes<M>(a, nb, code);
         if (nb != kNone) key = make_key(adc_codes<M, TT>(T, code), nb);
