@@ -270,10 +270,38 @@ __device__ __forceinline__ void build_table_q(const unsigned char* q,
 
 // ADC under storage TT: FP32 sum of the (widened) entries in subspace order;
 // for U8 the exact integer sum, returned as FP32 (exact below 2^24).
+// (byte B of w) << S in one instruction (SDWA byte select): the byte
+// offset of entry `code` in a table row of 2^S-byte entries.
+#define BANG_SDWA_SHL(S, B)                                               \
+  asm("v_lshlrev_b32_sdwa %0, " #S ", %1 dst_sel:DWORD "                   \
+      "dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_" #B             \
+      : "=v"(r) : "v"(w))
+template <int S, int B>
+__device__ __forceinline__ uint32_t byte_shl(uint32_t w) {
+  static_assert(S >= 0 && S <= 2 && B >= 0 && B <= 3, "byte_shl");
+  if constexpr (S == 0) {
+    return (w >> (8 * B)) & 0xFFu;
+  } else {
+    uint32_t r;
+    if constexpr (S == 1 && B == 0) BANG_SDWA_SHL(1, 0);
+    else if constexpr (S == 1 && B == 1) BANG_SDWA_SHL(1, 1);
+    else if constexpr (S == 1 && B == 2) BANG_SDWA_SHL(1, 2);
+    else if constexpr (S == 1 && B == 3) BANG_SDWA_SHL(1, 3);
+    else if constexpr (B == 0) BANG_SDWA_SHL(2, 0);
+    else if constexpr (B == 1) BANG_SDWA_SHL(2, 1);
+    else if constexpr (B == 2) BANG_SDWA_SHL(2, 2);
+    else BANG_SDWA_SHL(2, 3);
+    return r;
+  }
+}
+#undef BANG_SDWA_SHL
+
+// ADC of one neighbour from its m codes (16 per uint4) against the query's
+// table, which must start at LDS address 0: the search kernel puts it first
+// in its dynamic LDS block and declares no static LDS.
 template <int M, int TT>
-__device__ __forceinline__ float adc_codes(const void* Tv, const uint4 (&v)[M / 16]) {
+__device__ __forceinline__ float adc_codes(const uint4 (&v)[M / 16]) {
   using E = typename Tab<TT>::E;
-  const E* T = reinterpret_cast<const E*>(Tv);
   // all M lookups are issued before the first add, so their LDS latencies
   // overlap; the adds then run in subspace order
   E e[M];
@@ -282,8 +310,22 @@ __device__ __forceinline__ float adc_codes(const void* Tv, const uint4 (&v)[M / 
     const uint32_t w[4] = {v[c].x, v[c].y, v[c].z, v[c].w};
 #pragma unroll
     for (int b = 0; b < 16; ++b) {
-      const uint32_t byte = (w[b >> 2] >> (8 * (b & 3))) & 0xFFu;
-      e[16 * c + b] = T[(16 * c + b) * 256 + byte];
+      // entry (j, code) at byte offset (j*256 + code) * sizeof(E); the
+      // byte offset of the code comes from one SDWA instruction, and the
+      // table, the first thing in the dynamic LDS block, starts at LDS
+      // address 0 (search_kernel declares no static LDS), so no base is
+      // added
+      constexpr int S = sizeof(E) == 4 ? 2 : (sizeof(E) == 2 ? 1 : 0);
+      uint32_t off;
+      switch (b & 3) {
+        case 0: off = byte_shl<S, 0>(w[b >> 2]); break;
+        case 1: off = byte_shl<S, 1>(w[b >> 2]); break;
+        case 2: off = byte_shl<S, 2>(w[b >> 2]); break;
+        default: off = byte_shl<S, 3>(w[b >> 2]); break;
+      }
+      using lds_E = __attribute__((address_space(3))) const E;
+      e[16 * c + b] = *(reinterpret_cast<lds_E*>(static_cast<uintptr_t>(off)) +
+                        (16 * c + b) * 256);
     }
   }
   __builtin_amdgcn_sched_barrier(0);
@@ -359,7 +401,8 @@ __device__ __forceinline__ float exact_dist(const void* __restrict__ base,
 #pragma unroll
       for (int c = 0; c < D / 16; ++c) row[c] = x[c];
     }
-#pragma unroll(EAGER ? D / 16 : 2)
+    constexpr int kUnroll = EAGER ? D / 16 : 2;
+#pragma unroll kUnroll
     for (int c = 0; c < D / 16; ++c) {
       const uint4 v = EAGER ? row[EAGER ? c : 0] : x[c];
       const uint32_t w[4] = {v.x, v.y, v.z, v.w};
@@ -729,7 +772,7 @@ void search_kernel(SearchArgs a) {
 #pragma unroll
       for (int i = 0; i < M / 16; ++i)
         scode[i] = reinterpret_cast<const uint4*>(a.codes + (size_t)s * M)[i];
-      d0 = adc_codes<M, TT>(T, scode);
+      d0 = adc_codes<M, TT>(scode);
     }
     uint64_t curkey = make_key(d0, s);
     if (lane == 0) Lc[0] = curkey;
@@ -769,7 +812,7 @@ void search_kernel(SearchArgs a) {
           key = make_key(exact_dist<DT, D, true>(a.base, nb, q, qq), nb);
       } else {
         gather_codes<M>(a, nb, code);
-        if (nb != kNone) key = make_key(adc_codes<M, TT>(T, code), nb);
+        if (nb != kNone) key = make_key(adc_codes<M, TT>(code), nb);
       }
 
       // rank in the worklist; a node already in it is dropped (set union);
