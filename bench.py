@@ -136,6 +136,44 @@ def serving_section(gi, d, w, gt):
             "rates": rates}
 
 
+DEEP_WORKLOAD = "deep1m"
+
+
+def deep_section(a, bang, torch):
+    """Plain FP32 vs the precision form (FP16 / u8 tables) and the exact-
+    distance search on the unit-normalised float index shaped like the
+    paper's Deep data (d=96, m=48: a 48 KB FP32 table), each at its
+    smallest swept L with recall@10 >= 0.9; recall lost against FP32 at
+    the same L and the distance error against FP64 ground truth."""
+    import synth
+    from synth import store
+    w = synth.WORKLOADS[DEEP_WORKLOAD]
+    if not store.exists(w):
+        return {"skipped": f"index files for {w.name} are missing; write "
+                           f"them with `python -m oracle.build_index "
+                           f"{w.name}`"}
+    run = Runner(w, a, bang, torch)
+    forms = TABLES + ("exact",)
+    rows = run.sweep(forms)
+    by = {(r["table"], r["L"]): r["recall10"] for r in rows}
+    out = {"workload": "unit-normalised Gaussian mixture: n=1,000,000 d=96 "
+                       "float32, 4,096 unit centres, noise norm 0.3; 10,000 "
+                       "queries; graph R=64 L_build=100 alpha=1.2; PQ m=48",
+           "sweep": rows, "forms": {}}
+    for t in forms:
+        rec = run.measure(t, run.pick_L(t))
+        if t in ("f16", "u8"):
+            rec["recall_lost_vs_f32_same_L"] = round(
+                by[("f32", rec["L"])] - by[(t, rec["L"])], 4)
+        out["forms"][t] = rec
+    base = out["forms"]["f32"]["qps"]
+    for t in forms:
+        out["forms"][t]["speedup_vs_f32"] = round(
+            out["forms"][t]["qps"] / base, 3)
+    run.gi.close()
+    return out
+
+
 def copy_probe(mib: int) -> int:
     """A plain copy of `mib` MiB between two device buffers (reads and
     writes exactly that many bytes); its FETCH_SIZE / WRITE_SIZE readings
@@ -150,6 +188,121 @@ def copy_probe(mib: int) -> int:
     print(json.dumps({"copy_probe_mib": mib, "bytes_each_way": n * 4,
                       "dispatches": 3}), flush=True)
     return 0
+
+
+class Runner:
+    """One workload's index on the GPU, its recall sweep over L and the
+    timed measurement of one table form at one L."""
+
+    def __init__(self, w, a, bang, torch):
+        from synth import store
+        self.w, self.a, self.torch = w, a, torch
+        self.d = store.load(w)
+        d = self.d
+        self.gi = bang.Index(d["base"], d["adj"], d["medoid"],
+                             d["codebooks"], d["codes"])
+        self.dev = torch.device("cuda:0")
+        self.q = torch.from_numpy(d["queries"]).to(self.dev)
+        self.gt = d["gt_ids"]
+        self.adj_deg = (d["adj"] != 0xFFFFFFFF).sum(1)
+        self.elem = 1 if w.dtype in ("u8", "i8") else 4
+        self.rows = []
+
+    def sweep(self, tables):
+        """Recall and QPS of every (table, L): one untimed and one timed
+        launch each."""
+        torch, w, gi, q = self.torch, self.w, self.gi, self.q
+        stream = torch.cuda.current_stream()
+        nq, k = q.shape[0], w.k
+        for table in tables:
+            for L in w.Ls:
+                ids, dist = gi.search(q, k, L, table=table)
+                torch.cuda.synchronize()
+                t0 = torch.cuda.Event(enable_timing=True)
+                t1 = torch.cuda.Event(enable_timing=True)
+                t0.record(stream)
+                gi.search(q, k, L, out=(ids, dist), table=table)
+                t1.record(stream)
+                torch.cuda.synchronize()
+                rec = recall_at_k(ids.cpu().numpy().view(np.uint32), self.gt,
+                                  k)
+                self.rows.append({"table": table, "L": L,
+                                  "recall10": round(rec, 4),
+                                  "qps": round(nq / (t0.elapsed_time(t1)
+                                                     / 1e3))})
+        return self.rows
+
+    def pick_L(self, table):
+        """The smallest swept L whose recall@10 reaches the target, else
+        the L with the best recall (or --L when given)."""
+        if self.a.L:
+            return self.a.L
+        rows = [s for s in self.rows if s["table"] == table]
+        ok = [s for s in rows if s["recall10"] >= TARGET_RECALL]
+        return ok[0]["L"] if ok else max(rows, key=lambda s: s["recall10"])["L"]
+
+    def measure(self, table, L, index=None):
+        """K timed steps of one form; returns its record."""
+        torch, w, a = self.torch, self.w, self.a
+        gi_ = index or self.gi
+        q, dev, gt = self.q, self.dev, self.gt
+        stream = torch.cuda.current_stream()
+        nq, k = q.shape[0], w.k
+        ids = torch.empty((nq, k), dtype=torch.int32, device=dev)
+        dist = torch.empty((nq, k), dtype=torch.float32, device=dev)
+        for _ in range(a.warmup):
+            gi_.search(q, k, L, out=(ids, dist), table=table)
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True),
+               torch.cuda.Event(enable_timing=True)) for _ in range(a.steps)]
+        wall0 = time.perf_counter()
+        for e0, e1 in ev:
+            e0.record(stream)
+            gi_.search(q, k, L, out=(ids, dist), table=table)
+            e1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - wall0
+        per = np.array([e0.elapsed_time(e1) for e0, e1 in ev])  # ms/launch
+        got_ids = ids.cpu().numpy().view(np.uint32)
+        rec = recall_at_k(got_ids, gt, k)
+        # distance error against the FP64 ground truth, over the returned
+        # ids that are true neighbours
+        gd = self.d["gt_dists"][:, :k]
+        hit = got_ids == self.d["gt_ids"][:, :k]
+        dd = dist.cpu().numpy().astype(np.float64)
+        rel = np.abs(dd[hit] - gd[hit]) / np.maximum(gd[hit], 1e-30)
+        # one more (untimed) launch with counters, expanded nodes, stamps
+        cap = max(4 * L, L + 64)
+        _, _, cand, cnt, times = gi_.search(q, k, L, want_cand=cap,
+                                           want_counters=True,
+                                           want_times=True, table=table)
+        torch.cuda.synchronize()
+        cand = cand.cpu().numpy().view(np.uint32)
+        iters = cnt.cpu().numpy()[:, 0]
+        t = times.cpu().numpy().astype(np.float64)
+        # completion time of each query after the batch began, scaled so
+        # that the span of the device clock equals the measured kernel time
+        span = max(1.0, t[:, 1].max() - t[:, 0].min())
+        kern_ms = float(per.mean())
+        lat_ms = (t[:, 1] - t[:, 0].min()) / span * kern_ms
+        B = algorithmic_bytes(self.adj_deg, w.R, w.m, w.d, self.elem, k,
+                              iters, cand, 4 * L, exact=table == "exact")
+        ms_step = wall * 1e3 / a.steps
+        return {"table": table, "L": L, "recall10": round(rec, 4),
+                "adjacency_bytes_per_launch": int(iters.astype(np.int64).sum()
+                                                  * 4 * w.R),
+                "qps": round(nq / (ms_step / 1e3), 1),
+                "ms_per_step": round(ms_step, 4),
+                "p50_ms": round(float(np.percentile(lat_ms, 50)), 4),
+                "p99_ms": round(float(np.percentile(lat_ms, 99)), 4),
+                "mean_iterations": round(float(iters.mean()), 2),
+                "lambda_pct": round(iteration_overhead(float(iters.mean()),
+                                                       L), 2),
+                "kernel_ms_mean": round(kern_ms, 4),
+                "algorithmic_bytes_per_launch": B,
+                "achieved_gbs": round(B / (kern_ms / 1e3) / 1e9, 2),
+                "max_rel_dist_err_vs_fp64": float(rel.max()) if rel.size
+                else 0.0}
 
 
 def main(argv=None):
@@ -168,6 +321,8 @@ def main(argv=None):
                     help="skip the host-resident adjacency measurement")
     ap.add_argument("--no-serve", action="store_true",
                     help="skip the serving-loop measurement")
+    ap.add_argument("--no-deep", action="store_true",
+                    help="skip the precision form on the d=96 float index")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB mebibytes "
                          "(calibrates the HBM byte counters) and exit")
@@ -193,90 +348,11 @@ def main(argv=None):
               f"{store.DEFAULT_ROOT}; write them with "
               f"`python -m oracle.build_index {w.name}`", file=sys.stderr)
         return 3
-    d = store.load(w)
-    gi = bang.Index(d["base"], d["adj"], d["medoid"], d["codebooks"],
-                    d["codes"])
-    dev = torch.device("cuda:0")
-    q = torch.from_numpy(d["queries"]).to(dev)
-    gt = d["gt_ids"]
-    nq, k = q.shape[0], w.k
-    stream = torch.cuda.current_stream()
-
-    # recall sweep over L and table forms (one untimed + one timed launch)
-    sweep = []
-    for table in ([] if a.no_sweep else TABLES + ("exact",)):
-        for L in w.Ls:
-            ids, dist = gi.search(q, k, L, table=table)
-            torch.cuda.synchronize()
-            t0 = torch.cuda.Event(enable_timing=True)
-            t1 = torch.cuda.Event(enable_timing=True)
-            t0.record(stream)
-            gi.search(q, k, L, out=(ids, dist), table=table)
-            t1.record(stream)
-            torch.cuda.synchronize()
-            rec = recall_at_k(ids.cpu().numpy().view(np.uint32), gt, k)
-            sweep.append({"table": table, "L": L, "recall10": round(rec, 4),
-                          "qps": round(nq / (t0.elapsed_time(t1) / 1e3))})
-
-    def pick_L(table):
-        if a.L:
-            return a.L
-        rows = [s for s in sweep if s["table"] == table]
-        ok = [s for s in rows if s["recall10"] >= TARGET_RECALL]
-        return ok[0]["L"] if ok else max(rows, key=lambda s: s["recall10"])["L"]
-
-    adj_deg = (d["adj"] != 0xFFFFFFFF).sum(1)
-    elem = 1 if w.dtype in ("u8", "i8") else 4
-
-    def measure(table, L, index=None):
-        """K timed steps of one form; returns its record."""
-        gi_ = index or gi
-        ids = torch.empty((nq, k), dtype=torch.int32, device=dev)
-        dist = torch.empty((nq, k), dtype=torch.float32, device=dev)
-        for _ in range(a.warmup):
-            gi_.search(q, k, L, out=(ids, dist), table=table)
-        torch.cuda.synchronize()
-        ev = [(torch.cuda.Event(enable_timing=True),
-               torch.cuda.Event(enable_timing=True)) for _ in range(a.steps)]
-        wall0 = time.perf_counter()
-        for e0, e1 in ev:
-            e0.record(stream)
-            gi_.search(q, k, L, out=(ids, dist), table=table)
-            e1.record(stream)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - wall0
-        per = np.array([e0.elapsed_time(e1) for e0, e1 in ev])  # ms/launch
-        rec = recall_at_k(ids.cpu().numpy().view(np.uint32), gt, k)
-        # one more (untimed) launch with counters, expanded nodes, stamps
-        cap = max(4 * L, L + 64)
-        _, _, cand, cnt, times = gi_.search(q, k, L, want_cand=cap,
-                                           want_counters=True,
-                                           want_times=True, table=table)
-        torch.cuda.synchronize()
-        cand = cand.cpu().numpy().view(np.uint32)
-        iters = cnt.cpu().numpy()[:, 0]
-        t = times.cpu().numpy().astype(np.float64)
-        # completion time of each query after the batch began, scaled so
-        # that the span of the device clock equals the measured kernel time
-        span = max(1.0, t[:, 1].max() - t[:, 0].min())
-        kern_ms = float(per.mean())
-        lat_ms = (t[:, 1] - t[:, 0].min()) / span * kern_ms
-        B = algorithmic_bytes(adj_deg, w.R, w.m, w.d, elem, k, iters, cand,
-                              4 * L, exact=table == "exact")
-        ms_step = wall * 1e3 / a.steps
-        return {"table": table, "L": L, "recall10": round(rec, 4),
-                "adjacency_bytes_per_launch": int(iters.astype(np.int64).sum()
-                                                  * 4 * w.R),
-                "qps": round(nq / (ms_step / 1e3), 1),
-                "ms_per_step": round(ms_step, 4),
-                "p50_ms": round(float(np.percentile(lat_ms, 50)), 4),
-                "p99_ms": round(float(np.percentile(lat_ms, 99)), 4),
-                "mean_iterations": round(float(iters.mean()), 2),
-                "lambda_pct": round(iteration_overhead(float(iters.mean()),
-                                                       L), 2),
-                "kernel_ms_mean": round(kern_ms, 4),
-                "algorithmic_bytes_per_launch": B,
-                "achieved_gbs": round(B / (kern_ms / 1e3) / 1e9, 2)}
+    run = Runner(w, a, bang, torch)
+    d, gi, gt, k = run.d, run.gi, run.gt, w.k
+    sweep = run.sweep(() if a.no_sweep else TABLES + ("exact",))
+    pick_L = run.pick_L
+    measure = run.measure
 
     plain = measure("f32", pick_L("f32"))
     prec = {t: measure(t, pick_L(t)) for t in ("f16", "u8")}
@@ -351,6 +427,8 @@ def main(argv=None):
         out["host_resident"] = host
     if not a.no_serve:
         out["serving"] = serving_section(gi, d, w, gt)
+    if not a.no_deep:
+        out["precision_form_deep1m"] = deep_section(a, bang, torch)
     if exact is not None:
         out["exact_distance"] = exact
     if not a.no_cpu:

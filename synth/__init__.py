@@ -16,6 +16,12 @@ shapes and element types are listed in the paper's dataset table):
                clipped to [0,255]; 10,000 queries.  Index: Vamana R=64,
                L_build=100, alpha=1.2; PQ m=32 x 256.  Worklist sizes
                16 ... 1024 (recall@10 reaches 0.9 between 512 and 768).
+* ``deep1m``   n=1,000,000, d=96 float32, unit-normalised: 4,096 unit
+               centres (normalised Gaussian vectors), noise N(0, (0.3^2/d) I)
+               (expected noise norm 0.3), every point normalised; 10,000
+               queries.  Index: Vamana R=64, L_build=100, alpha=1.2; PQ
+               m=48 x 256 (two dims per subspace).  Shaped like the
+               paper's Deep data (float, d=96); worklist sizes 16 ... 512.
 
 Seeding: ``numpy.random.SeedSequence(240111324 + workload_index).spawn(8)``
 gives independent streams, in order ``centres, base, queries, pq_sample,
@@ -54,6 +60,10 @@ class Workload:
     # search parameters
     k: int
     Ls: tuple
+    # unit-normalised mixture: centres are unit vectors, the noise vector has
+    # expected norm sigma (per-coordinate sd sigma/sqrt(d)), every point is
+    # normalised after the noise (centre_lo/hi unused)
+    unit: bool = False
 
     def with_(self, **kw) -> "Workload":
         return dataclasses.replace(self, **kw)
@@ -65,6 +75,9 @@ WORKLOADS = {
     "sift1m": Workload("sift1m", 1, 1_000_000, 128, "u8", 1000, 0.0, 255.0,
                        20.0, 10_000, 64, 100, 1.2, 32, 10, 100_000, 10,
                        (16, 32, 64, 128, 256, 512, 768, 1024)),
+    "deep1m": Workload("deep1m", 2, 1_000_000, 96, "f32", 4096, 0.0, 0.0,
+                       0.3, 10_000, 64, 100, 1.2, 48, 10, 100_000, 10,
+                       (16, 32, 64, 128, 192, 256, 384, 512), unit=True),
 }
 
 
@@ -79,6 +92,9 @@ def streams(w: Workload) -> dict:
 
 
 def _centres(w: Workload, rng) -> np.ndarray:
+    if w.unit:
+        c = rng.standard_normal((w.ncent, w.d))
+        return c / np.linalg.norm(c, axis=1, keepdims=True)
     return rng.uniform(w.centre_lo, w.centre_hi, size=(w.ncent, w.d))
 
 
@@ -93,7 +109,10 @@ def _draw(w: Workload, centres: np.ndarray, rng, count: int,
     out = np.empty((count, w.d), dtype=np_dtype(w.dtype))
     for s in range(0, count, chunk):
         e = min(count, s + chunk)
-        x = centres[comp[s:e]] + w.sigma * rng.standard_normal((e - s, w.d))
+        sd = w.sigma / np.sqrt(w.d) if w.unit else w.sigma
+        x = centres[comp[s:e]] + sd * rng.standard_normal((e - s, w.d))
+        if w.unit:
+            x = x / np.linalg.norm(x, axis=1, keepdims=True)
         if w.dtype == "f32":
             out[s:e] = x.astype(np.float32)
         elif w.dtype == "u8":

@@ -481,3 +481,29 @@ def test_server_threads_submit_and_wait(small_indexes):
         t.join()
     sv.close()
     assert not errors, errors
+
+
+def test_deep1m_sampled_bit_exact():
+    """1M float32 points, d=96, m=48 (a 48 KB FP32 table): every table form
+    and the exact-distance search on the full batch; a seeded sample is
+    recomputed by the oracle and compared bit for bit."""
+    w, ix, d = load_workload("deep1m")
+    gi = bang_mod().Index(ix.base, ix.adj, ix.medoid, ix.codebooks, ix.codes)
+    q = d["queries"]
+    qt = to_dev(q)
+    sample = np.sort(np.random.default_rng(2027).choice(len(q), 96,
+                                                        replace=False))
+    for L, table in [(128, "f32"), (256, "f32"), (256, "f16"), (256, "u8"),
+                     (128, "exact"), (512, "f32")]:
+        cap = oracle.iter_cap_for(L)
+        ids, dist, cand, cnt = gi.search(qt, w.k, L, want_cand=cap,
+                                         want_counters=True, table=table)
+        torch.cuda.synchronize()
+        ref = oracle.search(ix, q[sample], w.k, L, want_cand=True,
+                            table=table)
+        assert np.array_equal(u32(cnt)[sample, 0], ref["iters"]), (L, table)
+        assert np.array_equal(u32(cand)[sample], ref["cand"]), (L, table)
+        assert np.array_equal(u32(ids)[sample], ref["ids"]), (L, table)
+        assert np.array_equal(f32bits(dist.cpu().numpy()[sample]),
+                              f32bits(ref["dists"])), (L, table)
+    gi.close()

@@ -1,5 +1,6 @@
-"""Host-side pieces of the serving measurement (no GPU): the seeded
-request stream and the autotuner's choice rule."""
+"""Host-side pieces (no GPU): the seeded serving request stream, the
+autotuner's choice rule, and the packed adjacency storage of the index
+files."""
 import numpy as np
 
 import synth
@@ -39,3 +40,15 @@ def test_autotune_prefers_lower_p99_when_rates_tie():
          {"max_batch": 2, "slots": 2, "sustained_qps": 99.5, "p99_ms": 3.0},
          {"max_batch": 3, "slots": 2, "sustained_qps": 90.0, "p99_ms": 1.0}]
     assert serving.choose(t, 50.0)["max_batch"] == 2
+
+
+def test_packed_adjacency_roundtrip():
+    from synth import store
+    rng = np.random.default_rng(5)
+    for n, R in ((1, 3), (1000, 7), (1_000_000, 64), (5, 64)):
+        a = rng.integers(0, n, size=(min(n, 500), R)).astype(np.uint32)
+        a[rng.random(a.shape) < 0.1] = 0xFFFFFFFF
+        words, wbits = store.pack_ids(a, n)
+        assert wbits == n.bit_length()
+        assert words.nbytes <= (a.size * wbits + 63) // 64 * 8 + 64 * 8
+        assert np.array_equal(store.unpack_ids(words, a.shape, n, wbits), a)
