@@ -865,7 +865,10 @@ void search_kernel(SearchArgs a) {
                  first_of((uint32_t)va, am);
         }
       }
-      const uint64_t bkey = wave_min64(kk);
+      // no live key (most expansions once the worklist is full): b does
+      // not exist and the wave minimum is skipped
+      const uint64_t km = __ballot(keep);
+      const uint64_t bkey = km ? wave_min64(kk) : kInf;
       uint32_t best = kNone;
       uint64_t bestkey = kInf;
       if (bkey < akey) {
@@ -885,7 +888,6 @@ void search_kernel(SearchArgs a) {
       else
         nb = kNone;
 
-      const uint64_t km = __ballot(keep);
       const uint32_t nv = __popcll(km);
       if (nv == 0) {
         // nothing enters the worklist: it keeps its order, u* is already
