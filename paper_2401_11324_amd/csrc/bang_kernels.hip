@@ -812,19 +812,20 @@ void search_kernel(SearchArgs a) {
           key = make_key(exact_dist<DT, D, true>(a.base, nb, q, qq), nb);
       } else {
         gather_codes<M>(a, nb, code);
-        if (nb != kNone) key = make_key(adc_codes<M, TT>(code), nb);
+        // every lane sums (no branch): an empty slot has zero codes, a lane
+        // past R reads table entries it then discards
+        const uint64_t k2 = make_key(adc_codes<M, TT>(code), nb);
+        key = nb != kNone ? k2 : kInf;
       }
 
       // rank in the worklist; a node already in it is dropped (set union);
       // a key ranked past a full worklist is cut whatever the other new keys
-      // are, so only the remaining ("live") keys take part in the merge
-      uint32_t r = 0;
-      bool keep = false;
-      if (key != kInf) {
-        uint64_t ge;
-        r = rank_in(Lc, Llen, last, key, ge);
-        keep = (ge >> 1) != (key >> 1) && r < Lq;
-      }
+      // are, so only the remaining ("live") keys take part in the merge.
+      // No branch for empty slots: kInf ranks past the last entry, with no
+      // entry equal to it, and is never kept.
+      uint64_t ge;
+      const uint32_t r = rank_in(Lc, Llen, last, key, ge);
+      const bool keep = (ge >> 1) != (key >> 1) && r < Lq;
       const uint64_t kk = keep ? key : kInf;
 
       // next node, decided before the merge: the smaller of the first
