@@ -507,3 +507,41 @@ def test_deep1m_sampled_bit_exact():
         assert np.array_equal(f32bits(dist.cpu().numpy()[sample]),
                               f32bits(ref["dists"])), (L, table)
     gi.close()
+
+
+def test_server_rejects_bad_requests_and_times_out_cleanly(small_indexes):
+    """Validation happens at submit; an unknown ticket and a wait that
+    times out are errors that leave the server usable."""
+    ix, q, gi = small_indexes["u8-d128-m32"]
+    bang = bang_mod()
+    with pytest.raises(bang.BangError):
+        bang.Server(gi, max_batch=0)
+    with pytest.raises(bang.BangError):
+        bang.Server(gi, max_k=64, max_L=32)
+    sv = bang.Server(gi, max_batch=8, slots=1, max_k=10, max_L=64)
+    for args in ((q[:9], 10, 64),      # more queries than max_batch
+                 (q[:2], 11, 64),      # k above max_k
+                 (q[:2], 10, 65),      # L above max_L
+                 (q[:2], 20, 16)):     # k above L
+        with pytest.raises(bang.BangError) as e:
+            sv.submit(*args)
+        assert e.value.code == -1
+    with pytest.raises(bang.BangError):
+        sv._shapes = {12345: (1, 1)}
+        sv.wait(12345)
+    t = sv.submit(q[:3], 5, 32)
+    ids, d = sv.wait(t)
+    a_ids, a_d = _alone(gi, q[:3], 5, 32, "f32")
+    assert np.array_equal(ids, a_ids)
+    assert np.array_equal(f32bits(d), f32bits(a_d))
+    sv.close()
+
+
+def test_mixed_batch_rejects_explicit_caps(small_indexes):
+    ix, q, gi = small_indexes["u8-d64-m16"]
+    bang = bang_mod()
+    Ls = to_dev(np.full(len(q), 16, np.int32))
+    with pytest.raises(bang.BangError):
+        gi.search(to_dev(q), 10, 16, c_max=8, query_L=Ls)
+    with pytest.raises(ValueError):
+        gi.search(to_dev(q), 10, 16, query_L=Ls[:3])
