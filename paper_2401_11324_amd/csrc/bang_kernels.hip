@@ -478,6 +478,70 @@ __device__ __forceinline__ uint64_t wave_min64(uint64_t v) {
   return ((uint64_t)hi << 32) | lo;
 }
 
+// Exact distances of the wave's 64 neighbours (lane r: neighbour nb of lane
+// r) for integer data, with the base rows read cooperatively: G lanes, one
+// 16-byte chunk each, share a row, so one load instruction covers 64/G
+// whole rows instead of 64 scattered pieces.  Each lane adds the dot
+// products of its chunk (sum x^2 - 2 sum x q: exact integers), a DPP
+// reduction leaves each row's total in the last lane of its group, and
+// lane r collects neighbour r's.  Integer sums are exact in any order, so
+// the value equals exact_dist's.  qc = this lane's query chunk (zero past
+// the row), qq = query_sq.  Every lane must call it (cross-lane).
+template <int DT, int D>
+__device__ __forceinline__ float coop_dist(const void* __restrict__ base,
+                                           uint32_t nb, const uint4& qc,
+                                           int32_t qq, int lane) {
+  constexpr int CH = D / 16;
+  static_assert(D % 16 == 0 && CH >= 1 && CH <= 8, "rows of 16..128 bytes");
+  constexpr int G = CH <= 2 ? 2 : (CH <= 4 ? 4 : 8);  // lanes per row
+  constexpr int RPI = kWave / G;                      // rows per load
+  const int c = lane % G, g = lane / G;
+  const int cc = c < CH ? c : CH - 1;  // in-row chunk (masked below)
+  uint4 v[G];
+  bool ok[G];
+#pragma unroll
+  for (int t = 0; t < G; ++t) {
+    const uint32_t id = __shfl(nb, t * RPI + g);
+    ok[t] = id != kNone && c < CH;
+    v[t] = reinterpret_cast<const uint4*>(
+        (const uint8_t*)base + (size_t)(id != kNone ? id : 0u) * D)[cc];
+  }
+  const uint32_t qw[4] = {qc.x, qc.y, qc.z, qc.w};
+  uint32_t part[G];
+#pragma unroll
+  for (int t = 0; t < G; ++t) {
+    const uint32_t w[4] = {v[t].x, v[t].y, v[t].z, v[t].w};
+    uint32_t xx = 0, xq = 0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if constexpr (DT == kU8) {
+        xx = __builtin_amdgcn_udot4(w[u], w[u], xx, false);
+        xq = __builtin_amdgcn_udot4(w[u], qw[u], xq, false);
+      } else {
+        xx = (uint32_t)__builtin_amdgcn_sdot4((int)w[u], (int)w[u], (int)xx,
+                                              false);
+        xq = (uint32_t)__builtin_amdgcn_sdot4((int)w[u], (int)qw[u], (int)xq,
+                                              false);
+      }
+    }
+    uint32_t s = ok[t] ? xx - 2u * xq : 0u;
+    // group total into the group's last lane (groups lie inside DPP rows)
+    s += dpp<0x111>(0u, s);                     // row_shr:1
+    if constexpr (G >= 4) s += dpp<0x112>(0u, s);  // row_shr:2
+    if constexpr (G >= 8) s += dpp<0x114>(0u, s);  // row_shr:4
+    part[t] = s;
+  }
+  // neighbour r was row slot r % RPI of load t = r / RPI
+  const int src = (lane % RPI) * G + (G - 1);
+  uint32_t tot = 0;
+#pragma unroll
+  for (int t = 0; t < G; ++t) {
+    const uint32_t x = __shfl(part[t], src);
+    if (lane / RPI == t) tot = x;
+  }
+  return (float)(int32_t)(tot + (uint32_t)qq);
+}
+
 // Number P of entries of the sorted LDS list A[0..len) whose key, visited
 // bit ignored, is below x's (1 <= len <= 1024, last = A[len-1]), and in ge
 // the entry A[P] (kInf when P = len).  (a >> 1) < (x >> 1) is tested as
@@ -756,7 +820,16 @@ void search_kernel(SearchArgs a) {
     // constant term of integer exact distances (the PQ forms compute it
     // after the search, so the query is not held through the loop)
     int32_t qq = 0;
-    if constexpr (kExact) qq = query_sq<DT, D>(q);
+    uint4 qc = make_uint4(0u, 0u, 0u, 0u);  // this lane's query chunk
+    if constexpr (kExact) {
+      qq = query_sq<DT, D>(q);
+      if constexpr (DT != kF32) {
+        constexpr int CH = D / 16;
+        constexpr int G = CH <= 2 ? 2 : (CH <= 4 ? 4 : 8);
+        const int c = lane % G;
+        if (c < CH) qc = reinterpret_cast<const uint4*>(q)[c];
+      }
+    }
     uint32_t nb;
     uint4 code[M / 16];
     load_row<M, !kExact>(a, s, lane, nb, code);  // in flight meanwhile
@@ -807,7 +880,10 @@ void search_kernel(SearchArgs a) {
 
       // distances of the neighbours (row of u*, loaded earlier)
       uint64_t key = kInf;
-      if constexpr (kExact) {
+      if constexpr (kExact && DT != kF32) {
+        const float dq = coop_dist<DT, D>(a.base, nb, qc, qq, lane);
+        key = nb != kNone ? make_key(dq, nb) : kInf;
+      } else if constexpr (kExact) {
         if (nb != kNone)
           key = make_key(exact_dist<DT, D, true>(a.base, nb, q, qq), nb);
       } else {

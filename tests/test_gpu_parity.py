@@ -545,3 +545,18 @@ def test_mixed_batch_rejects_explicit_caps(small_indexes):
         gi.search(to_dev(q), 10, 16, c_max=8, query_L=Ls)
     with pytest.raises(ValueError):
         gi.search(to_dev(q), 10, 16, query_L=Ls[:3])
+
+
+@pytest.mark.parametrize("dtype,d,m", [("u8", 32, 16), ("i8", 32, 16),
+                                       ("u8", 64, 32), ("i8", 128, 64)])
+def test_exact_distance_integer_row_widths_bit_exact(dtype, d, m):
+    """The integer exact distances read each base row with 2, 4 or 8 lanes
+    (d = 32, 64, 128 bytes); every width against the oracle."""
+    w = synth.small(dtype, n=1500, d=d, nq=40, m=m, R=32,
+                    seed_index=130 + d + (dtype == "i8"))
+    ix, q = make_index(w)
+    gi = bang_mod().Index(ix.base, ix.adj, ix.medoid, ix.codebooks, ix.codes)
+    for k, L in ((1, 1), (10, 33), (10, 200)):
+        run_and_compare(ix, gi, q, k, L, table="exact",
+                        label=f"exact {dtype} d={d} k={k} L={L}")
+    gi.close()
