@@ -560,3 +560,48 @@ def test_exact_distance_integer_row_widths_bit_exact(dtype, d, m):
         run_and_compare(ix, gi, q, k, L, table="exact",
                         label=f"exact {dtype} d={d} k={k} L={L}")
     gi.close()
+
+
+@pytest.mark.parametrize("table", ["f32", "u8", "exact"])
+def test_ties_are_broken_by_id(table):
+    """Every base vector appears four times (ids 4i..4i+3), so PQ and exact
+    distances tie in groups: orders (worklist, re-rank, results) must fall
+    back to the node id exactly as the oracle's do."""
+    w = synth.small("u8", n=1200, d=64, nq=30, m=16, R=24, seed_index=140)
+    base0, q = synth.base_and_queries(w)
+    base = np.repeat(base0[:300], 4, axis=0)
+    rs = synth.streams(w)
+    cb = train_pq(base, w.m, 4, rs["pq_init"])
+    codes = pq_encode(base, cb)
+    s = oracle.medoid(base)
+    perm = rs["vamana_order"].permutation(len(base)).astype(np.uint32)
+    adj, _ = build_graph(base, w.R, w.L_build, w.alpha, perm, s)
+    ix = oracle.Index(base, adj, s, cb, codes)
+    gi = bang_mod().Index(base, adj, s, cb, codes)
+    ref = run_and_compare(ix, gi, q, 10, 48, table=table,
+                          label=f"ties {table}")
+    # tied neighbours come out in id order
+    for ids, d in zip(ref["ids"], ref["dists"]):
+        for a, b, da, db in zip(ids[:-1], ids[1:], d[:-1], d[1:]):
+            if da == db:
+                assert a < b
+    gi.close()
+
+
+def test_single_node_and_isolated_start():
+    """n = 1, and a start node without edges: one expansion, the start
+    node alone in the result, the rest padded."""
+    w = synth.small("f32", n=300, d=32, nq=4, m=16, seed_index=141)
+    base, q = synth.base_and_queries(w)
+    cb = train_pq(base, 16, 3, synth.streams(w)["pq_init"])
+    codes = pq_encode(base, cb)
+    for n in (1, 64):
+        adj = np.full((n, 8), NONE, dtype=np.uint32)
+        ix = oracle.Index(base[:n], adj, 0, cb, codes[:n])
+        gi = bang_mod().Index(base[:n], adj, 0, cb, codes[:n])
+        for table in ("f32", "exact"):
+            ref = run_and_compare(ix, gi, q, 1 if n == 1 else 5, 8,
+                                  table=table, label=f"n={n} {table}")
+            assert (ref["iters"] == 1).all()
+            assert (ref["ids"][:, 0] == 0).all()
+        gi.close()
