@@ -302,6 +302,7 @@ class Server:
                                         ctypes.byref(h)))
         self._h = h
         self.dtype = np.dtype(index.torch_dtype)
+        self._shapes = {}  # ticket -> (nq, k); dict updates are atomic
 
     def _q(self, q):
         q = np.ascontiguousarray(q, dtype=self.dtype)
@@ -314,17 +315,18 @@ class Server:
         t = ctypes.c_uint64()
         _check(lib().bang_server_submit(self._h, q.ctypes.data, q.shape[0], k,
                                         L, ctypes.byref(t)))
-        self._shapes = getattr(self, "_shapes", {})
         self._shapes[t.value] = (q.shape[0], k)
         return t.value
 
     def wait(self, ticket: int, timeout_ms: int = -1):
+        if ticket not in self._shapes:
+            raise BangError(-1, f"unknown ticket {ticket}")
         nq, k = self._shapes[ticket]
         ids = np.empty((nq, k), dtype=np.uint32)
         d = np.empty((nq, k), dtype=np.float32)
         _check(lib().bang_server_wait(self._h, ticket, ids.ctypes.data,
                                       d.ctypes.data, timeout_ms))
-        del self._shapes[ticket]
+        self._shapes.pop(ticket, None)
         return ids, d
 
     def replay(self, queries, nq, k, L, arrival_s, kstride: int | None = None):

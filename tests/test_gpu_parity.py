@@ -527,8 +527,11 @@ def test_server_rejects_bad_requests_and_times_out_cleanly(small_indexes):
             sv.submit(*args)
         assert e.value.code == -1
     with pytest.raises(bang.BangError):
-        sv._shapes = {12345: (1, 1)}
-        sv.wait(12345)
+        sv.wait(12345)                 # unknown ticket (binding)
+    with pytest.raises(bang.BangError):
+        sv._shapes[12345] = (1, 1)
+        sv.wait(12345)                 # unknown ticket (library)
+    sv._shapes.pop(12345)
     t = sv.submit(q[:3], 5, 32)
     ids, d = sv.wait(t)
     a_ids, a_d = _alone(gi, q[:3], 5, 32, "f32")
