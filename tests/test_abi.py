@@ -104,6 +104,23 @@ def test_calls_with_null_index_fail_cleanly():
     assert L.bang_index_destroy(None) == 0
 
 
+def test_server_calls_with_null_arguments_fail_cleanly():
+    import ctypes
+    L = bang.lib()
+    o = bang.ServerOpts(16, 1, 10, 64, 0, 0)
+    h = ctypes.c_void_p()
+    assert L.bang_server_create(None, ctypes.byref(o), ctypes.byref(h)) == -1
+    assert not h.value
+    t = ctypes.c_uint64()
+    assert L.bang_server_submit(None, None, 1, 1, 1, ctypes.byref(t)) == -1
+    assert L.bang_server_wait(None, 1, None, None, 0) == -1
+    assert L.bang_server_replay(None, None, 0, None, None, None, None, 1,
+                                None, None, None) == -1
+    assert L.bang_server_stats(None, None, 0) == -1
+    assert L.bang_server_destroy(None) == 0
+    assert "null" in L.bang_last_error().decode()
+
+
 def test_python_binding_refuses_missing_library(monkeypatch, tmp_path):
     monkeypatch.setattr(bang, "_lib", None)
     monkeypatch.setattr(bang, "LIB_PATH", str(tmp_path / "missing.so"))
