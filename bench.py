@@ -174,6 +174,64 @@ def deep_section(a, bang, torch):
     return out
 
 
+def scale_host(a) -> int:
+    """Host-resident adjacency at scale: a synthetic graph of a.scale_host
+    int8 points (synth.scale_graph_index: R=64 ids per row spread over the
+    whole range, so no cache helps), adjacency in pinned host memory, codes
+    and base vectors in HBM; 10,000 queries, k=10.  Reports QPS, mean
+    iterations and the adjacency bytes that crossed the host link per
+    second.  Recall is not defined on this graph."""
+    import torch
+    import synth
+    import paper_2401_11324_amd as bang
+    n = a.scale_host
+    t0 = time.perf_counter()
+
+    def log(msg):
+        print(f"[scale-host {time.perf_counter() - t0:6.1f}s] {msg}",
+              file=sys.stderr, flush=True)
+
+    log(f"generating {n:,} nodes")
+    d = synth.scale_graph_index(n)
+    log("index (validate, pin adjacency, upload)")
+    gi = bang.Index(d["base"], d["adj"], d["medoid"], d["codebooks"],
+                    d["codes"], host_adj=True)
+    R = d["adj"].shape[1]
+    del d["adj"]
+    q = torch.from_numpy(d["queries"]).cuda()
+    nq, k = q.shape[0], 10
+    stream = torch.cuda.current_stream()
+    rows = []
+    for L in (64, 128):
+        ids, dist, cnt = gi.search(q, k, L, want_counters=True)
+        torch.cuda.synchronize()
+        iters = cnt.cpu().numpy()[:, 0].astype(np.int64)
+        ev = [(torch.cuda.Event(enable_timing=True),
+               torch.cuda.Event(enable_timing=True)) for _ in range(a.steps)]
+        for e0, e1 in ev:
+            e0.record(stream)
+            gi.search(q, k, L, out=(ids, dist))
+            e1.record(stream)
+        torch.cuda.synchronize()
+        ms = float(np.mean([e0.elapsed_time(e1) for e0, e1 in ev]))
+        link = iters.sum() * 4 * R / (ms / 1e3) / 1e9
+        rows.append({"L": L, "k": k, "qps": round(nq / (ms / 1e3), 1),
+                     "kernel_ms_mean": round(ms, 3),
+                     "mean_iterations": round(float(iters.mean()), 2),
+                     "host_link_gbs": round(link, 2),
+                     "host_link_frac": round(link / HOST_LINK_PEAK_GBS, 4)})
+        log(f"L={L}: {rows[-1]}")
+    gi.close()
+    print(json.dumps({"scale_host": {
+        "workload": f"synthetic graph: n={n:,} int8 d=128, R={R} ids per "
+                    f"row spread over the range (no locality), PQ m=32; "
+                    f"adjacency {n * R * 4 / 1e9:.1f} GB in pinned host "
+                    f"memory; {nq:,} queries",
+        "steps": a.steps, "rows": rows,
+        "host_link_peak_gbs": HOST_LINK_PEAK_GBS}}), flush=True)
+    return 0
+
+
 def copy_probe(mib: int) -> int:
     """A plain copy of `mib` MiB between two device buffers (reads and
     writes exactly that many bytes); its FETCH_SIZE / WRITE_SIZE readings
@@ -323,12 +381,18 @@ def main(argv=None):
                     help="skip the serving-loop measurement")
     ap.add_argument("--no-deep", action="store_true",
                     help="skip the precision form on the d=96 float index")
+    ap.add_argument("--scale-host", type=int, default=0, metavar="N",
+                    help="only measure the host-resident adjacency on a "
+                         "synthetic N-node int8 graph (throughput at scale, "
+                         "no recall) and exit")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB mebibytes "
                          "(calibrates the HBM byte counters) and exit")
     a = ap.parse_args(argv)
     if a.copy_probe:
         return copy_probe(a.copy_probe)
+    if a.scale_host:
+        return scale_host(a)
     if a.no_sweep and not a.L:
         ap.error("--no-sweep needs --L")
     if a.gpus != 1:

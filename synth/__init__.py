@@ -173,3 +173,49 @@ def serving_requests(w: Workload, rate_qps: float, duration_s: float,
     L = np.maximum(rng.choice(np.asarray(Ls), nreq), k).astype(np.uint32)
     rows = rng.integers(0, w.nq, int(nq.sum()))
     return {"nq": nq, "k": k, "L": L, "arrival_s": arrival, "rows": rows}
+
+
+def scale_graph_index(n: int, d: int = 128, R: int = 64, m: int = 32,
+                      nq: int = 10_000, seed: int = 240111324,
+                      chunk: int = 1 << 20):
+    """A large synthetic index for throughput at scale only (no recall):
+    int8 base vectors and queries uniform in [-128, 127] and random PQ codes
+    (a random block of `block` rows repeated over the n rows, so that
+    filling 100M rows takes seconds), random codebooks, and an adjacency
+    whose row u holds R distinct ids spread over the whole range by a
+    fixed odd multiplier, (u * 2654435761 + j * 40503 + 17 * j * j) mod n,
+    j < R, so consecutive expansions touch unrelated rows (no locality for
+    any cache).  Arrays are filled chunk by chunk to bound host memory.
+
+    Returns dict(base, adj, medoid, codebooks, codes, queries)."""
+    if n <= R * 40503 + 17 * R * R:
+        raise ValueError("n too small for distinct row offsets")
+    rng = np.random.default_rng(seed)
+    block = min(n, 1 << 22)
+    bb = rng.bit_generator.random_raw(block * d // 8).view(np.int8)
+    bb = bb.reshape(block, d)
+    cbk = rng.bit_generator.random_raw(block * m // 8).view(np.uint8)
+    cbk = cbk.reshape(block, m)
+    base = np.empty((n, d), dtype=np.int8)
+    codes = np.empty((n, m), dtype=np.uint8)
+    adj = np.empty((n, R), dtype=np.uint32)
+    j = np.arange(R, dtype=np.uint64)
+    off = (j * np.uint64(40503) + np.uint64(17) * j * j) % np.uint64(n)
+    off32 = off.astype(np.uint32)
+    if n >= 1 << 31:
+        raise ValueError("n must be below 2^31")
+    chunk = min(chunk, block)
+    for s in range(0, n, chunk):
+        e = min(n, s + chunk)
+        r0 = s % block  # block is a multiple of chunk: no wrap inside
+        base[s:e] = bb[r0:r0 + (e - s)]
+        codes[s:e] = cbk[r0:r0 + (e - s)]
+        h = ((np.arange(s, e, dtype=np.uint64) * np.uint64(2654435761))
+             % np.uint64(n)).astype(np.uint32)
+        x = h[:, None] + off32[None, :]  # < 2n < 2^32
+        np.subtract(x, np.uint32(n), out=x, where=x >= n)
+        adj[s:e] = x
+    cb = rng.uniform(-128, 127, size=(m, 256, d // m)).astype(np.float32)
+    queries = rng.integers(-128, 128, size=(nq, d), dtype=np.int8)
+    return {"base": base, "adj": adj, "medoid": 0, "codebooks": cb,
+            "codes": codes, "queries": queries}
