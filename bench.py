@@ -221,6 +221,18 @@ def scale_host(a) -> int:
                      "host_link_gbs": round(link, 2),
                      "host_link_frac": round(link / HOST_LINK_PEAK_GBS, 4)})
         log(f"L={L}: {rows[-1]}")
+    # the serving loop on the same host-resident index (configuration 4's
+    # request recipe; results are not checked here, recall is undefined)
+    from paper_2401_11324_amd import serving
+    w = synth.WORKLOADS["sift1m"].with_(name="scale", nq=nq)
+    serve = []
+    for i, rate in enumerate(SERVE_RATES):
+        req = synth.serving_requests(w, rate, min(1.0, 2e5 / rate),
+                                     salt=20 + i)
+        sm, _, _ = serving.run_load(gi, d["queries"], req, 16384, 2, 100,
+                                    128)
+        serve.append(sm)
+        log(f"serving {rate:.0e}: {sm}")
     gi.close()
     print(json.dumps({"scale_host": {
         "workload": f"synthetic graph: n={n:,} int8 d=128, R={R} ids per "
@@ -228,7 +240,12 @@ def scale_host(a) -> int:
                     f"adjacency {n * R * 4 / 1e9:.1f} GB in pinned host "
                     f"memory; {nq:,} queries",
         "steps": a.steps, "rows": rows,
-        "host_link_peak_gbs": HOST_LINK_PEAK_GBS}}), flush=True)
+        "host_link_peak_gbs": HOST_LINK_PEAK_GBS,
+        "serving": {"max_batch": 16384, "slots": 2,
+                    "requests": "sizes log-uniform 1-256 queries, k in "
+                                "{10,100}, L in {32,64,128} raised to k, "
+                                "Poisson arrivals", "rates": serve}}}),
+          flush=True)
     return 0
 
 
