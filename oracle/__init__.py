@@ -9,15 +9,19 @@ in oracle.c):
 
 * ``pq_tables``      stage 1, the PQ distance table, canonical FP32
 * ``adc``            asymmetric distance, canonical FP32
-* ``search``         stages 1-3: table, greedy search (Algorithm 1), re-rank
+* ``search``         stages 1-3: table (FP32, or the FP16 / u8 storage of
+                     the precision form), greedy search (Algorithm 1, or
+                     the filtered form of Algorithm 2), re-rank; or the
+                     Exact-distance Version (no table, no re-rank)
 * ``rerank``         stage 3 alone over given candidates
 * ``bruteforce``     exact k nearest (ground truth)
 * ``train_pq`` / ``pq_encode``   PQ codebooks (k-means) and codes
 * ``medoid`` / ``vamana_build`` / ``reachable``   the graph index
 
-Parity status: table, ADC, re-rank, search and brute force are pinned by the
-tests in tests/test_oracle_*.py (closed forms, brute force on tiny inputs,
-the paper's worked example).  The Vamana build and k-means training are
+Parity status: table, ADC, re-rank, search (every table form and the
+exact-distance form) and brute force are pinned by the tests in
+tests/test_oracle.py and tests/test_oracle_properties.py (closed forms,
+brute force on tiny and random inputs, the paper's worked example).  The Vamana build and k-means training are
 "parity unpinned": no reference graph or codebook exists; only structural
 invariants and Lloyd monotonicity are checked.
 """
