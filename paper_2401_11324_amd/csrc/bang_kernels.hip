@@ -863,20 +863,11 @@ void search_kernel(SearchArgs a) {
         C[iters] = curkey;
       }
       ++iters;
-      // this lane's entries of the super-row holding u* (reads past Llen
-      // stay inside the buffer, which ends on a super-row boundary)
       const uint32_t sbase = cur / sup * sup;
-      uint64_t lk[kPer];
-#pragma unroll
-      for (int t = 0; t < kPer; ++t) {
-        const uint32_t j = sbase + B * lane + t;
-        lk[t] = kInf;
-        if ((uint32_t)t < B) {
-          const uint64_t v = Lc[j];
-          lk[t] = j < Llen ? v : kInf;
-        }
-      }
       const uint64_t last = Lc[Llen - 1];
+      // the entry after u*: every entry before u* is visited, so when this
+      // one is not, it is the first unvisited entry a (the usual case)
+      const uint64_t nx = Lc[min(cur + 1, Llen - 1)];
 
       // distances of the neighbours (row of u*, loaded earlier)
       uint64_t key = kInf;
@@ -910,15 +901,22 @@ void search_kernel(SearchArgs a) {
       // and then a is cut too.  Its merged position is a's index or b's rank.
       uint32_t apos = kNone;
       uint64_t akey = kInf;
-      {
+      if (cur + 1 < Llen && !(nx & 1ull)) {
+        apos = cur + 1;
+        akey = nx;
+      } else {
+        // scan from the super-row holding u* (reads past Llen stay inside
+        // the buffer, which ends on a super-row boundary)
         uint32_t ja = kNone;
         uint64_t va = kInf;
 #pragma unroll
         for (int t = kPer - 1; t >= 0; --t) {
           const uint32_t j = sbase + B * lane + t;
-          if (lk[t] != kInf && j != cur && !(lk[t] & 1ull)) {
+          if ((uint32_t)t >= B) continue;
+          const uint64_t x = Lc[j];
+          if (j < Llen && j > cur && !(x & 1ull)) {
             ja = j;
-            va = lk[t];
+            va = x;
           }
         }
         uint64_t am = __ballot(ja != kNone);
@@ -1039,7 +1037,7 @@ void search_kernel(SearchArgs a) {
           const uint32_t j = base + B * lane + t;
           v[t] = kInf;
           if ((uint32_t)t < B) {
-            const uint64_t x = base == sbase ? lk[t] : Lc[j];
+            const uint64_t x = Lc[j];
             v[t] = j < Llen ? x : kInf;
           }
           if (j == cur) v[t] |= 1ull;  // u*, marked visited
