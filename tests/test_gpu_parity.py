@@ -608,3 +608,36 @@ def test_single_node_and_isolated_start():
             assert (ref["iters"] == 1).all()
             assert (ref["ids"][:, 0] == 0).all()
         gi.close()
+
+
+def test_search_replays_from_a_hip_graph(small_indexes):
+    """bang_search is stream-ordered with no allocation (once the workspace
+    has grown) and no memset (the kernel returns its counters to zero), so
+    a captured search replays: every replay, with new queries copied into
+    the captured input and eager searches in between, equals the eager
+    result of those queries."""
+    ix, q, gi = small_indexes["u8-d128-m32"]
+    k, L = 10, 64
+    n = len(q) // 2
+    qa, qb = to_dev(q[:n]), to_dev(q[n:2 * n])
+    qbuf = qa.clone()
+    ids = torch.empty((n, k), dtype=torch.int32, device=qa.device)
+    dist = torch.empty((n, k), dtype=torch.float32, device=qa.device)
+    gi.search(qbuf, k, L, out=(ids, dist))          # grows the workspace
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s, capture_error_mode="relaxed"):
+            gi.search(qbuf, k, L, out=(ids, dist), stream=s)
+    torch.cuda.synchronize()
+    for rep, src in enumerate((qa, qb, qa, qb)):
+        qbuf.copy_(src)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        got_ids, got_d = u32(ids).copy(), dist.cpu().numpy().copy()
+        e_ids, e_d = gi.search(src, k, L)           # eager, between replays
+        torch.cuda.synchronize()
+        assert np.array_equal(got_ids, u32(e_ids)), rep
+        assert np.array_equal(f32bits(got_d), f32bits(e_d.cpu().numpy())), rep
