@@ -1277,7 +1277,13 @@ struct RunSearch {
 
 template <typename K>
 hipError_t occupancy_of(K kernel, size_t lds, int* per_cu) {
-  hipError_t e = allow_lds(kernel, lds);
+  // adc_codes addresses the table from LDS address 0, where the dynamic
+  // LDS block starts only while the kernel declares no static LDS
+  hipFuncAttributes fa;
+  hipError_t e = hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(kernel));
+  if (e != hipSuccess) return e;
+  if (fa.sharedSizeBytes != 0) return hipErrorInvalidKernelFile;
+  e = allow_lds(kernel, lds);
   if (e != hipSuccess) return e;
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, kernel, kWave,
                                                       lds);

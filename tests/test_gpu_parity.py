@@ -641,3 +641,37 @@ def test_search_replays_from_a_hip_graph(small_indexes):
         torch.cuda.synchronize()
         assert np.array_equal(got_ids, u32(e_ids)), rep
         assert np.array_equal(f32bits(got_d), f32bits(e_d.cpu().numpy())), rep
+
+
+def test_server_admission_by_memory_budget(small_indexes):
+    """hbm_budget_bytes caps the slots: a budget for one slot gives one
+    slot (and correct results), a budget below one slot is refused."""
+    ix, q, gi = small_indexes["u8-d64-m16"]
+    bang = bang_mod()
+    with pytest.raises(bang.BangError) as e:
+        bang.Server(gi, max_batch=64, slots=4, max_k=10, max_L=64,
+                    hbm_budget_bytes=1024)
+    assert e.value.code == -2
+    big = bang.Server(gi, max_batch=64, slots=4, max_k=10, max_L=64)
+    assert big.stats()["slots"] == 4
+    big.close()
+    # grow the budget until two slots fit: the first budget that allows
+    # more than one slot lies between one and two slots' footprint
+    one = None
+    for mb in (1, 2, 4, 8, 16, 32, 64, 128, 256):
+        try:
+            sv = bang.Server(gi, max_batch=64, slots=4, max_k=10, max_L=64,
+                             hbm_budget_bytes=mb << 20)
+        except bang.BangError:
+            continue
+        n = sv.stats()["slots"]
+        if one is None:
+            one = (mb, n)
+            t = sv.submit(q[:5], 10, 64)
+            ids, d = sv.wait(t)
+            a_ids, _ = _alone(gi, q[:5], 10, 64, "f32")
+            assert np.array_equal(ids, a_ids)
+        sv.close()
+        if n == 4:
+            break
+    assert one is not None and 1 <= one[1] <= 4
