@@ -47,6 +47,9 @@ namespace {
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 constexpr uint64_t kInf = ~0ull;
 constexpr int kWave = 64;
+// s_waitcnt immediate for vmcnt(0) alone (gfx9 encoding: expcnt and lgkmcnt
+// at their maxima, no wait on them)
+constexpr unsigned kWaitVmem0 = 0x0F70;
 
 __device__ __forceinline__ uint64_t make_key(float d, uint32_t id) {
   return ((uint64_t)__float_as_uint(d) << 32) | ((uint64_t)id << 1);
@@ -721,25 +724,49 @@ constexpr int kPer = 4;
 // neighbours: one coalesced load per lane, no dependent gather.  With a
 // host-resident adjacency only the ids are requested here (4R bytes across
 // the host link); gather_codes fetches the codes once they have arrived.
-// CODES = false (exact distances) requests the ids alone.
+// CODES = false (exact distances) requests the ids alone.  Every lane
+// loads (lanes past R repeat slot R-1), so no lane-dependent branch joins
+// the two forms; the caller applies row_mask once the row is in.
 template <int M, bool CODES = true>
 __device__ __forceinline__ void load_row(const SearchArgs& a, uint32_t u,
                                          int lane, uint32_t& nb,
                                          uint4 (&code)[M / 16]) {
+  const uint32_t l = min((uint32_t)lane, a.R - 1);
   if (a.hadj) {
-    nb = (uint32_t)lane < a.R ? a.hadj[(size_t)u * a.R + lane] : kNone;
+    nb = a.hadj[(size_t)u * a.R + l];
     return;
   }
   const unsigned char* row = a.rows + (size_t)u * a.row_stride;
-  if ((uint32_t)lane < a.R) {
-    nb = reinterpret_cast<const uint32_t*>(row)[lane];
-    if (!CODES) return;
-    const uint4* c = reinterpret_cast<const uint4*>(row + a.row_ids + lane * M);
+  nb = reinterpret_cast<const uint32_t*>(row)[l];
+  if (!CODES) return;
+  const uint4* c = reinterpret_cast<const uint4*>(row + a.row_ids + l * M);
 #pragma unroll
-    for (int i = 0; i < M / 16; ++i) code[i] = c[i];
-  } else {
-    nb = kNone;
-  }
+  for (int i = 0; i < M / 16; ++i) code[i] = c[i];
+}
+
+// Lanes past R hold no neighbour.
+__device__ __forceinline__ uint32_t row_mask(const SearchArgs& a, int lane,
+                                             uint32_t nb) {
+  return (uint32_t)lane < a.R ? nb : kNone;
+}
+
+// Touches node u's packed row, one word per lane spread over the part that
+// load_row reads: the row comes into the caches while the current
+// neighbours are scored, so that load_row, if u is chosen, finds it there.
+// With a host-resident adjacency u's codes in device memory are touched
+// instead (no host-link traffic; the load only keeps the loads outstanding
+// the same on every path).  `touched` receives the word; the previous one
+// is consumed first, which keeps each load from being dropped.
+template <int M, bool CODES = true>
+__device__ __forceinline__ void touch_row(const SearchArgs& a, uint32_t u,
+                                          int lane, uint32_t& touched) {
+  const uint32_t bytes = a.row_ids + (CODES ? a.R * M : 0u);
+  const uint32_t step = (bytes / kWave) & ~3u;
+  const unsigned char* p =
+      a.hadj ? a.codes + (size_t)u * M
+             : a.rows + (size_t)u * a.row_stride + lane * step;
+  asm volatile("" ::"v"(touched));
+  touched = *reinterpret_cast<const uint32_t*>(p);
 }
 
 // Waves per SIMD that the table alone still lets share a CU's 160 KB of
@@ -850,6 +877,10 @@ void search_kernel(SearchArgs a) {
     uint64_t curkey = make_key(d0, s);
     if (lane == 0) Lc[0] = curkey;
     uint32_t Llen = 1, cur = 0, iters = 0, status = 0;
+    uint32_t touched = 0;  // result of the last touch_row (never read)
+    // the expanded keys, written to C 64 at a time: lane e holds that of
+    // expansion e mod 64 until its group of 64 is stored
+    uint64_t ckey = 0;
     __syncthreads();
 
     while (cur != kNone) {
@@ -858,9 +889,13 @@ void search_kernel(SearchArgs a) {
         break;
       }
       // expand u* = Lc[cur]: mark visited, record it as a candidate
-      if (lane == 0) {
-        Lc[cur] = curkey | 1ull;
-        C[iters] = curkey;
+      if (lane == 0) Lc[cur] = curkey | 1ull;
+      if ((uint32_t)lane == (iters & (kWave - 1))) ckey = curkey;
+      if ((iters & (kWave - 1)) == kWave - 1) {
+        C[iters - (kWave - 1) + lane] = ckey;
+        // completed here: with a store outstanding among the row loads the
+        // compiler can only wait for every access, the touch below included
+        __builtin_amdgcn_s_waitcnt(kWaitVmem0);
       }
       ++iters;
       const uint32_t sbase = cur / sup * sup;
@@ -868,17 +903,25 @@ void search_kernel(SearchArgs a) {
       // the entry after u*: every entry before u* is visited, so when this
       // one is not, it is the first unvisited entry a (the usual case)
       const uint64_t nx = Lc[min(cur + 1, Llen - 1)];
+      // it is usually the next node too: its row is touched below, after
+      // this row's ids are in (when nx is visited or past the end the touch
+      // is wasted, not wrong).  The previous touch was issued before this
+      // row was requested, so it is complete.
 
       // distances of the neighbours (row of u*, loaded earlier)
+      nb = row_mask(a, lane, nb);
       uint64_t key = kInf;
       if constexpr (kExact && DT != kF32) {
+        touch_row<M, false>(a, key_id(nx), lane, touched);
         const float dq = coop_dist<DT, D>(a.base, nb, qc, qq, lane);
         key = nb != kNone ? make_key(dq, nb) : kInf;
       } else if constexpr (kExact) {
+        touch_row<M, false>(a, key_id(nx), lane, touched);
         if (nb != kNone)
           key = make_key(exact_dist<DT, D, true>(a.base, nb, q, qq), nb);
       } else {
         gather_codes<M>(a, nb, code);
+        touch_row<M>(a, key_id(nx), lane, touched);
         // every lane sums (no branch): an empty slot has zero codes, a lane
         // past R reads table entries it then discards
         const uint64_t k2 = make_key(adc_codes<M, TT>(code), nb);
@@ -1063,8 +1106,10 @@ void search_kernel(SearchArgs a) {
       __syncthreads();
     }
 
-    // stage 3: re-rank the expanded nodes.  C was written by lane 0 and is
-    // read by every lane: an agent-scope fence also drops stale L1 lines.
+    // stage 3: re-rank the expanded nodes.  The last group of C is written
+    // out; an agent-scope fence then also drops stale L1 lines.
+    if ((iters & ~(kWave - 1u)) + lane < iters)
+      C[(iters & ~(kWave - 1u)) + lane] = ckey;
     __threadfence();
     __syncthreads();
     if (a.out_counters && lane == 0) {
