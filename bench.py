@@ -174,6 +174,90 @@ def deep_section(a, bang, torch):
     return out
 
 
+BATCH_SIZES = (1, 10, 100, 500, 1000, 2000, 4000, 10000, 20000)
+M_SWEEP = (16, 32, 64)
+
+
+def batch_section(run, L):
+    """QPS of the plain FP32 search at the bench point against the size of
+    the query batch (the paper's batch-size study): one launch per batch,
+    the mean of several; past 10,000 the queries repeat."""
+    torch, gi, q, k = run.torch, run.gi, run.q, run.w.k
+    stream = torch.cuda.current_stream()
+    rows = []
+    for nq in BATCH_SIZES:
+        reps = -(-nq // q.shape[0])
+        qb = q.repeat(reps, 1)[:nq].contiguous() if reps > 1 else q[:nq]
+        ids = torch.empty((nq, k), dtype=torch.int32, device=q.device)
+        dist = torch.empty((nq, k), dtype=torch.float32, device=q.device)
+        gi.search(qb, k, L, out=(ids, dist))
+        torch.cuda.synchronize()
+        n = 5
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(n):
+            gi.search(qb, k, L, out=(ids, dist))
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / n
+        rows.append({"batch": nq, "ms_per_launch": round(ms, 4),
+                     "qps": round(nq / (ms / 1e3), 1)})
+    top = max(r["qps"] for r in rows)
+    sat = next(r["batch"] for r in rows if r["qps"] >= 0.9 * top)
+    return {"table": "f32", "L": L, "rows": rows,
+            "saturation_batch_90pct": sat,
+            "waves_resident": "CUs x waves per CU set by the table's LDS"}
+
+
+def m_section(run, bang):
+    """Recall and QPS against the number m of PQ subspaces (the paper's
+    compression-ratio study): the same base, graph and queries encoded with
+    m = 16, 32, 64 (m/d = 0.125, 0.25, 0.5 code bytes per base byte), FP32
+    tables, every swept L; per m also the smallest L with recall@10 >= 0.9.
+    The extra encodings sit beside the index (written by
+    `python -m oracle.build_index <workload> --extra-m 16 64`)."""
+    from synth import store
+    torch, w, d, q, k = run.torch, run.w, run.d, run.q, run.w.k
+    stream = torch.cuda.current_stream()
+    have = store.extra_names(w)
+    out = {"table": "f32", "per_m": []}
+    for m in M_SWEEP:
+        if m == w.m:
+            cb, codes = d["codebooks"], d["codes"]
+        elif f"codes_m{m}" in have:
+            ex = store.load_extra(w, [f"codebooks_m{m}", f"codes_m{m}"])
+            cb, codes = ex[f"codebooks_m{m}"], ex[f"codes_m{m}"]
+        else:
+            out["per_m"].append({"m": m, "skipped": "encoding missing"})
+            continue
+        gi = bang.Index(d["base"], d["adj"], d["medoid"], cb, codes)
+        rows = []
+        for L in w.Ls:
+            ids, dist = gi.search(q, k, L)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            gi.search(q, k, L, out=(ids, dist))
+            e1.record(stream)
+            torch.cuda.synchronize()
+            rec = recall_at_k(ids.cpu().numpy().view(np.uint32), run.gt, k)
+            rows.append({"L": L, "recall10": round(rec, 4),
+                         "qps": round(q.shape[0] / (e0.elapsed_time(e1)
+                                                    / 1e3))})
+        gi.close()
+        ok = [r for r in rows if r["recall10"] >= TARGET_RECALL]
+        out["per_m"].append({
+            "m": m, "code_bytes_per_vector": m,
+            "compression_ratio": round(m / (w.d * (1 if w.dtype in
+                                                   ("u8", "i8") else 4)), 4),
+            "fp32_table_kb": m, "sweep": rows,
+            "at_target": ok[0] if ok else None,
+            "best_recall10": max(r["recall10"] for r in rows)})
+    return out
+
+
 def scale_host(a) -> int:
     """Host-resident adjacency at scale: a synthetic graph of a.scale_host
     int8 points (synth.scale_graph_index: R=64 ids per row spread over the
@@ -396,6 +480,8 @@ def main(argv=None):
                     help="skip the host-resident adjacency measurement")
     ap.add_argument("--no-serve", action="store_true",
                     help="skip the serving-loop measurement")
+    ap.add_argument("--no-ablation", action="store_true",
+                    help="skip the batch-size and PQ-subspace studies")
     ap.add_argument("--no-deep", action="store_true",
                     help="skip the precision form on the d=96 float index")
     ap.add_argument("--scale-host", type=int, default=0, metavar="N",
@@ -506,6 +592,9 @@ def main(argv=None):
     }
     if host is not None:
         out["host_resident"] = host
+    if not a.no_ablation:
+        out["batch_size"] = batch_section(run, L)
+        out["pq_subspaces"] = m_section(run, bang)
     if not a.no_serve:
         out["serving"] = serving_section(gi, d, w, gt)
     if not a.no_deep:

@@ -2,6 +2,11 @@
 
     python -m oracle.build_index tiny
     python -m oracle.build_index sift1m [--threads N]
+    python -m oracle.build_index sift1m --extra-m 16 64
+
+The second form adds, beside an existing index, the base encoded with other
+numbers of subspaces (codebooks_m<m>, codes_m<m>): the same training sample,
+the k-means init stream from its start.
 
 Steps: generate base vectors and queries (synth), train PQ on a seeded
 sample, encode every base vector, pick the medoid, build the graph (Vamana
@@ -63,13 +68,36 @@ def build(w: synth.Workload, nthreads: int = 0, root: str | None = None,
     return p
 
 
+def add_pq(w: synth.Workload, ms, nthreads: int = 0, root: str | None = None,
+           log=print) -> str:
+    nthreads = nthreads or default_threads()
+    t0 = time.time()
+    base, _ = synth.base_and_queries(w)
+    ns = min(w.n, w.pq_sample)
+    arrays = {}
+    for m in ms:
+        rs = synth.streams(w)
+        sample = base[np.sort(rs["pq_sample"].choice(w.n, ns, replace=False))]
+        cb = train_pq(sample, m, w.kmeans_iters, rs["pq_init"], nthreads)
+        arrays[f"codebooks_m{m}"] = cb
+        arrays[f"codes_m{m}"] = pq_encode(base, cb, nthreads)
+        log(f"[{w.name}] PQ m={m} trained and encoded ({time.time() - t0:.1f}s)")
+    p = store.save_extra(w, arrays, root=root)
+    log(f"[{w.name}] added {sorted(arrays)} to {p}")
+    return p
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("workload", choices=sorted(synth.WORKLOADS))
     ap.add_argument("--threads", type=int, default=0)
     ap.add_argument("--root", default=None)
+    ap.add_argument("--extra-m", type=int, nargs="+", default=None)
     a = ap.parse_args(argv)
-    build(synth.WORKLOADS[a.workload], a.threads, a.root)
+    if a.extra_m:
+        add_pq(synth.WORKLOADS[a.workload], a.extra_m, a.threads, a.root)
+    else:
+        build(synth.WORKLOADS[a.workload], a.threads, a.root)
 
 
 if __name__ == "__main__":

@@ -1266,7 +1266,7 @@ __global__ __launch_bounds__(kWave) void rerank_kernel(
 // dispatch over the compiled (dtype, m, d/m) combinations
 // ---------------------------------------------------------------------------
 #define BANG_SHAPES(X) \
-  X(16, 2) X(16, 4) X(32, 2) X(32, 4) X(48, 2) X(64, 2)
+  X(16, 2) X(16, 4) X(16, 8) X(32, 2) X(32, 4) X(48, 2) X(64, 2)
 
 template <template <int, int, int> class F, typename... Args>
 hipError_t dispatch(int dt, uint32_t m, uint32_t ds, Args&&... args) {

@@ -13,6 +13,9 @@ generator.  Layout of ``<root>/<workload>/``:
                    little-endian within uint64 words
   gt_ids.npy       uint32  [nq][k_gt]   exact nearest neighbours
   gt_dists.npy     float64 [nq][k_gt]
+  <name>.npy       optional further arrays (manifest "extra_arrays"), e.g.
+                   codebooks_m16 / codes_m16: the same base encoded with
+                   another number of subspaces
 
 Base vectors and queries are not stored: ``load`` regenerates them from the
 workload's seeds and checks them against the digests in the manifest.
@@ -142,6 +145,52 @@ def save(w: Workload, arrays: dict, medoid: int, extra: dict | None = None,
     os.replace(os.path.join(p, "manifest.json.tmp"),
                os.path.join(p, "manifest.json"))
     return p
+
+
+def save_extra(w: Workload, arrays: dict, root: str | None = None) -> str:
+    """Add arrays beside an existing index (digests in the manifest)."""
+    p = path_for(w, root)
+    with open(os.path.join(p, "manifest.json")) as f:
+        man = json.load(f)
+    ex = man.setdefault("extra_arrays", {})
+    for name, a in arrays.items():
+        if name in ARRAYS or not name.isidentifier():
+            raise ValueError(f"bad extra array name {name!r}")
+        a = np.ascontiguousarray(a)
+        np.save(os.path.join(p, name + ".npy"), a, allow_pickle=False)
+        ex[name] = {"shape": list(a.shape), "dtype": str(a.dtype),
+                    "sha256": digest(a)}
+    with open(os.path.join(p, "manifest.json.tmp"), "w") as f:
+        json.dump(man, f, indent=1)
+    os.replace(os.path.join(p, "manifest.json.tmp"),
+               os.path.join(p, "manifest.json"))
+    return p
+
+
+def extra_names(w: Workload, root: str | None = None) -> list:
+    with open(os.path.join(path_for(w, root), "manifest.json")) as f:
+        return sorted(json.load(f).get("extra_arrays", {}))
+
+
+def load_extra(w: Workload, names, root: str | None = None,
+               verify: bool = True) -> dict:
+    p = path_for(w, root)
+    with open(os.path.join(p, "manifest.json")) as f:
+        man = json.load(f)
+    if _stored_params(man) != _index_params(w):
+        raise ValueError(f"{p}: built for different workload parameters")
+    out = {}
+    for name in names:
+        meta = man.get("extra_arrays", {}).get(name)
+        if meta is None:
+            raise KeyError(f"{p}: no extra array {name!r}")
+        a = np.load(os.path.join(p, name + ".npy"), allow_pickle=False)
+        if list(a.shape) != meta["shape"] or str(a.dtype) != meta["dtype"]:
+            raise ValueError(f"{p}/{name}.npy: shape/dtype mismatch")
+        if verify and digest(a) != meta["sha256"]:
+            raise ValueError(f"{p}/{name}.npy: content digest mismatch")
+        out[name] = a
+    return out
 
 
 def exists(w: Workload, root: str | None = None) -> bool:

@@ -44,7 +44,7 @@ def make_index(w):
 
 
 SMALL = {
-    # (dtype, d, m): covers the three element types and d/m = 2 and 4
+    # (dtype, d, m): covers the three element types and d/m = 2, 4 and 8
     "f32-d32-m16": synth.small("f32", n=1500, d=32, nq=37, m=16, R=24,
                                seed_index=110),
     "u8-d64-m16": synth.small("u8", n=2000, d=64, nq=41, m=16, R=32,
@@ -53,6 +53,9 @@ SMALL = {
                               seed_index=112),
     "u8-d128-m32": synth.small("u8", n=3000, d=128, nq=45, m=32, R=64,
                                ncent=12, seed_index=113),
+    # d/m = 8 (the m = 16 encoding of d = 128 data)
+    "f32-d128-m16": synth.small("f32", n=1600, d=128, nq=31, m=16, R=32,
+                                seed_index=114),
 }
 
 
@@ -286,6 +289,39 @@ def test_sift1m_full_batch_sampled_bit_exact():
         dd = dist.cpu().numpy()
         assert (np.diff(dd, axis=1) >= 0).all()
         assert all(len(set(r)) == len(r) for r in allids[:500])
+
+
+@pytest.mark.parametrize("m", [16, 64])
+def test_sift1m_other_subspace_counts_sampled_bit_exact(m):
+    """The compression-ratio study's encodings (the same base with m = 16 or
+    64 subspaces): the full batch on the GPU, a seeded sample of queries
+    recomputed by the oracle."""
+    w, ix, d = load_workload("sift1m")
+    names = store.extra_names(w)
+    if f"codes_m{m}" not in names:
+        pytest.skip(f"no m={m} encoding beside the index (python -m "
+                    f"oracle.build_index sift1m --extra-m {m})")
+    ex = store.load_extra(w, [f"codebooks_m{m}", f"codes_m{m}"])
+    cb, codes = ex[f"codebooks_m{m}"], ex[f"codes_m{m}"]
+    ixm = oracle.Index(d["base"], d["adj"], d["medoid"], cb, codes)
+    gi = bang_mod().Index(d["base"], d["adj"], d["medoid"], cb, codes)
+    q = d["queries"]
+    qt = to_dev(q)
+    sample = np.sort(np.random.default_rng(2025 + m).choice(len(q), 96,
+                                                            replace=False))
+    for L, table in [(64, "f32"), (768, "f32"), (256, "u8")]:
+        cap = oracle.iter_cap_for(L)
+        ids, dist, cand, cnt = gi.search(qt, w.k, L, want_cand=cap,
+                                         want_counters=True, table=table)
+        torch.cuda.synchronize()
+        ref = oracle.search(ixm, q[sample], w.k, L, want_cand=True,
+                            table=table)
+        assert np.array_equal(u32(cnt)[sample, 0], ref["iters"]), (m, L)
+        assert np.array_equal(u32(cand)[sample], ref["cand"]), (m, L)
+        assert np.array_equal(u32(ids)[sample], ref["ids"]), (m, L)
+        assert np.array_equal(f32bits(dist.cpu().numpy()[sample]),
+                              f32bits(ref["dists"])), (m, L)
+    gi.close()
 
 
 # --------------------------------------------------------------------------

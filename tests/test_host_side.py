@@ -52,3 +52,39 @@ def test_packed_adjacency_roundtrip():
         assert wbits == n.bit_length()
         assert words.nbytes <= (a.size * wbits + 63) // 64 * 8 + 64 * 8
         assert np.array_equal(store.unpack_ids(words, a.shape, n, wbits), a)
+
+
+def test_extra_arrays_roundtrip_and_checks(tmp_path):
+    """Arrays added beside an index (e.g. another PQ encoding) come back
+    bit-identical, bad names are refused and a changed file is caught."""
+    import pytest
+    from synth import store
+    w = synth.small("u8", n=300, d=16, nq=3, m=4, R=8, seed_index=150)
+    rng = np.random.default_rng(7)
+    arrays = {"codebooks": rng.random((4, 256, 4), dtype=np.float32),
+              "codes": rng.integers(0, 256, (300, 4), dtype=np.uint8),
+              "adj": rng.integers(0, 300, (300, 8)).astype(np.uint32),
+              "gt_ids": np.zeros((3, 10), np.uint32),
+              "gt_dists": np.zeros((3, 10), np.float64)}
+    store.save(w, arrays, 0, root=str(tmp_path))
+    extra = {"codes_m8": rng.integers(0, 256, (300, 8), dtype=np.uint8),
+             "codebooks_m8": rng.random((8, 256, 2), dtype=np.float32)}
+    store.save_extra(w, extra, root=str(tmp_path))
+    assert store.extra_names(w, root=str(tmp_path)) == ["codebooks_m8",
+                                                        "codes_m8"]
+    got = store.load_extra(w, ["codes_m8", "codebooks_m8"],
+                           root=str(tmp_path))
+    for k, v in extra.items():
+        assert got[k].dtype == v.dtype and np.array_equal(got[k], v)
+    with pytest.raises(ValueError):
+        store.save_extra(w, {"codes": extra["codes_m8"]}, root=str(tmp_path))
+    with pytest.raises(KeyError):
+        store.load_extra(w, ["codes_m99"], root=str(tmp_path))
+    bad = extra["codes_m8"].copy()
+    bad[0, 0] ^= 1
+    np.save(tmp_path / w.name / "codes_m8.npy", bad, allow_pickle=False)
+    with pytest.raises(ValueError):
+        store.load_extra(w, ["codes_m8"], root=str(tmp_path))
+    # the index itself is untouched by the extra arrays
+    assert np.array_equal(store.load(w, root=str(tmp_path), with_base=False)
+                          ["codes"], arrays["codes"])
