@@ -67,6 +67,9 @@ def lib():
         L.or_f16_to_f32.argtypes = [ctypes.c_uint16]
         L.or_f16_to_f32.restype = ctypes.c_float
         L.or_search.restype = ctypes.c_int
+        L.or_fnv1a32.argtypes = [P, u64, u32]
+        L.or_fnv1a32.restype = u32
+        L.or_bloom_slots.argtypes = [u32, P, P]
         L.or_rerank.argtypes = [P, P, u64, P, u32, u32, P, P, ctypes.c_int]
         L.or_rerank.restype = ctypes.c_int
         L.or_bruteforce.argtypes = [P, ctypes.c_int, u64, u32, P, u64, u32,
@@ -196,6 +199,27 @@ def quantize_tables(T: np.ndarray, table: str):
     return out
 
 
+# visited filters of the search (oracle.c greedy_search): Algorithm 1's
+# set union, Algorithm 2 with an exact seen-set, Algorithm 2 with the
+# paper's Bloom filter
+MODES = {"union": 0, "exact": 1, "bloom": 2}
+BLOOM_Z = 399887
+
+
+def fnv1a32(data: bytes, basis: int = 0x811C9DC5) -> int:
+    """FNV-1a-32 of a byte string (oracle.c or_fnv1a32)."""
+    buf = ctypes.create_string_buffer(bytes(data), max(1, len(data)))
+    return int(lib().or_fnv1a32(ctypes.cast(buf, ctypes.c_void_p),
+                                len(data), basis))
+
+
+def bloom_slots(x: int):
+    """The two Bloom-filter entries of node x (oracle.c or_bloom_slots)."""
+    h1, h2 = ctypes.c_uint32(), ctypes.c_uint32()
+    lib().or_bloom_slots(x, ctypes.byref(h1), ctypes.byref(h2))
+    return int(h1.value), int(h2.value)
+
+
 def search(index: Index, queries: np.ndarray, k: int, L: int,
            c_max: int | None = None, iter_cap: int | None = None,
            mode: int = 0, want_pq: bool = False, want_cand: bool = False,
@@ -204,7 +228,9 @@ def search(index: Index, queries: np.ndarray, k: int, L: int,
     table, re-ranking).  `table` picks the table storage the search ranks
     by: "f32" (canonical), "f16" or "u8" (the precision form, oracle.c),
     or "exact": exact distances in the search and no re-rank (section
-    "Implementation Variants", Exact-distance Version).
+    "Implementation Variants", Exact-distance Version).  `mode` picks
+    the visited filter (MODES: 0 Algorithm 1's set union, 1 Algorithm 2
+    with an exact seen-set, 2 Algorithm 2 with the paper's Bloom filter).
     Returns a dict with ids, dists and, on request,
     pq_ids/pq_dists (Algorithm 1's own top-k), cand (expanded nodes in
     expansion order, NONE padded) and counters [I, status, added]."""

@@ -305,6 +305,50 @@ static int entry_cmp(const void* a, const void* b) {
   return 0;
 }
 
+/*
+ * The paper's visited filter (section "Parallel Filtering of Visited
+ * Neighbours"; parameters in section "Algorithm Parameters"): one array of
+ * z = 399,887 boolean entries per query and two FNV-1a hash functions.
+ * FNV-1a-32 is the published one (offset basis 2166136261, prime 16777619:
+ * for each byte, xor it in, then multiply).  The paper does not say how its
+ * two functions differ; read here as the same function over the id's four
+ * little-endian bytes with two offset bases, the standard one and the
+ * standard one xor 0xA5A5A5A5, each taken mod z.
+ */
+#define OR_BLOOM_Z 399887u
+#define OR_FNV_BASIS 0x811C9DC5u
+#define OR_FNV_PRIME 0x01000193u
+#define OR_BLOOM_SALT 0xA5A5A5A5u
+
+uint32_t or_fnv1a32(const uint8_t* p, uint64_t n, uint32_t basis) {
+  uint32_t h = basis;
+  for (uint64_t i = 0; i < n; ++i) {
+    h ^= p[i];
+    h *= OR_FNV_PRIME;
+  }
+  return h;
+}
+
+/* The two entries of node x. */
+void or_bloom_slots(uint32_t x, uint32_t* h1, uint32_t* h2) {
+  uint8_t b[4] = {(uint8_t)x, (uint8_t)(x >> 8), (uint8_t)(x >> 16),
+                  (uint8_t)(x >> 24)};
+  *h1 = or_fnv1a32(b, 4, OR_FNV_BASIS) % OR_BLOOM_Z;
+  *h2 = or_fnv1a32(b, 4, OR_FNV_BASIS ^ OR_BLOOM_SALT) % OR_BLOOM_Z;
+}
+
+/* Algorithm 2's GetBloomFilter followed, when it fails, by SetBloomFilter:
+ * returns 1 when both entries of x are already set (x counts as visited),
+ * else sets both and returns 0. */
+static int bloom_test_and_set(uint8_t* bf, uint32_t x) {
+  uint32_t h1, h2;
+  or_bloom_slots(x, &h1, &h2);
+  if (bf[h1] && bf[h2]) return 1;
+  bf[h1] = 1;
+  bf[h2] = 1;
+  return 0;
+}
+
 /* Per-query results of stage 2. */
 typedef struct {
   uint32_t iters;  /* I = number of expanded nodes = |C| */
@@ -322,14 +366,20 @@ typedef struct {
  *         the worklist, which keeps its t nearest entries.
  * Both modes expand the same nodes in the same order and end with the same
  * worklist; the tests check that.
+ * mode 2: Algorithm 2 with the paper's Bloom filter in place of the exact
+ *         seen-set: the neighbours of u* are tested and set one after the
+ *         other in stored order, so a neighbour sees the entries set by the
+ *         ones before it in the same row.  A false positive drops a node
+ *         that was never seen; nothing seen is ever kept.
  *
  * On return C[0..iters) holds the expanded nodes with their PQ distances in
  * expansion order, and Lout[0..*Llen) the final worklist.
  */
 static void greedy_search(const or_index* ix, const qtable* T, uint32_t Lcap,
                           uint32_t iter_cap, int mode, uint32_t* seen,
-                          uint32_t stamp, entry* L, uint32_t* Llen, entry* C,
-                          entry* scratch, or_counters* cnt) {
+                          uint32_t stamp, uint8_t* bloom, entry* L,
+                          uint32_t* Llen, entry* C, entry* scratch,
+                          or_counters* cnt) {
   uint32_t R = ix->R;
   uint32_t s = ix->medoid;
   uint32_t len = 1;
@@ -337,6 +387,10 @@ static void greedy_search(const or_index* ix, const qtable* T, uint32_t Lcap,
   L[0].id = s;
   L[0].visited = 0;
   if (mode == 1) seen[s] = stamp;
+  if (mode == 2) {
+    memset(bloom, 0, OR_BLOOM_Z);
+    bloom_test_and_set(bloom, s);
+  }
   cnt->iters = 0;
   cnt->status = 0;
   cnt->added = 0;
@@ -383,8 +437,13 @@ static void greedy_search(const or_index* ix, const qtable* T, uint32_t Lcap,
       uint32_t np = 0;
       for (uint32_t r = 0; r < R; ++r) {
         uint32_t x = nb[r];
-        if (x == OR_NONE || seen[x] == stamp) continue;
-        seen[x] = stamp;
+        if (x == OR_NONE) continue;
+        if (mode == 2) {
+          if (bloom_test_and_set(bloom, x)) continue;
+        } else {
+          if (seen[x] == stamp) continue;
+          seen[x] = stamp;
+        }
         scratch[np].dist = node_dist(ix, T, x);
         scratch[np].id = x;
         scratch[np].visited = 0;
@@ -452,7 +511,8 @@ int or_search(const or_index* ix, const void* queries, uint64_t nq, uint32_t k,
               uint32_t* ids, float* dists, uint32_t* pq_ids, float* pq_dists,
               uint32_t* cand, uint32_t cand_cap, uint32_t* counters,
               int nthreads) {
-  if (k == 0 || Lcap < k || ix->d % ix->m != 0) return -1;
+  if (k == 0 || Lcap < k || ix->d % ix->m != 0 || mode < 0 || mode > 2)
+    return -1;
   int64_t qi;
   int bad = 0;
 #pragma omp parallel num_threads(nthreads)
@@ -464,8 +524,10 @@ int or_search(const or_index* ix, const void* queries, uint64_t nq, uint32_t k,
     entry* C = (entry*)malloc((size_t)(iter_cap + 1) * sizeof(entry));
     entry* scr = (entry*)malloc((size_t)(2 * ix->R + Lcap) * sizeof(entry));
     uint32_t* seen = (uint32_t*)calloc(ix->n, sizeof(uint32_t));
+    uint8_t* bloom = mode == 2 ? (uint8_t*)malloc(OR_BLOOM_Z) : NULL;
     uint32_t stamp = 0;
-    if (!T || !T16 || !T8 || !L || !C || !scr || !seen) {
+    if (!T || !T16 || !T8 || !L || !C || !scr || !seen ||
+        (mode == 2 && !bloom)) {
 #pragma omp atomic write
       bad = 1;
     } else {
@@ -479,8 +541,8 @@ int or_search(const or_index* ix, const void* queries, uint64_t nq, uint32_t k,
         or_counters cn;
         uint32_t Llen;
         ++stamp;
-        greedy_search(ix, &qt, Lcap, iter_cap, mode, seen, stamp, L, &Llen, C,
-                      scr, &cn);
+        greedy_search(ix, &qt, Lcap, iter_cap, mode, seen, stamp, bloom, L,
+                      &Llen, C, scr, &cn);
         if (pq_ids)
           for (uint32_t i = 0; i < k; ++i) {
             pq_ids[qi * k + i] = i < Llen ? L[i].id : OR_NONE;
@@ -514,6 +576,7 @@ int or_search(const or_index* ix, const void* queries, uint64_t nq, uint32_t k,
     free(C);
     free(scr);
     free(seen);
+    free(bloom);
   }
   return bad ? -2 : 0;
 }

@@ -544,3 +544,106 @@ def test_exact_distance_beats_pq_recall(small_u8):
     ex = oracle.search(ix, q, 10, 16, table="exact")
     pq = oracle.search(ix, q, 10, 16)
     assert recall(ex["ids"]) >= recall(pq["ids"])
+
+
+# --------------------------------------------------------------------------
+# The paper's Bloom filter (section "Parallel Filtering of Visited
+# Neighbours"; z and the hash family in section "Algorithm Parameters")
+# --------------------------------------------------------------------------
+def test_fnv1a32_published_check_values():
+    """FNV-1a-32 reference values of the FNV specification: the empty
+    string is the offset basis, "a" and "foobar" are its test vectors."""
+    assert oracle.fnv1a32(b"") == 0x811C9DC5
+    assert oracle.fnv1a32(b"a") == 0xE40C292C
+    assert oracle.fnv1a32(b"foobar") == 0xBF9CF968
+
+
+def test_bloom_slots_are_the_hashes_of_the_id_bytes_mod_z():
+    """The two entries of a node are FNV-1a-32 of its four little-endian
+    bytes under the two offset bases, mod z (the reading in oracle.c)."""
+    for x in (0, 1, 255, 256, 65537, 999_999, 0xFFFFFFFE):
+        b = int(x).to_bytes(4, "little")
+        h1, h2 = oracle.bloom_slots(x)
+        assert h1 == oracle.fnv1a32(b, 0x811C9DC5) % oracle.BLOOM_Z
+        assert h2 == oracle.fnv1a32(b, 0x811C9DC5 ^ 0xA5A5A5A5) % oracle.BLOOM_Z
+        assert 0 <= h1 < oracle.BLOOM_Z and 0 <= h2 < oracle.BLOOM_Z
+
+
+def test_bloom_false_positive_rate_matches_closed_form():
+    """A two-hash Bloom filter of z entries holding n keys answers a fresh
+    key positively with probability (1 - e^(-2n/z))^2 when the hashes
+    spread evenly; at n = 9,600 that is 0.22%.  Checked within 5 sigma
+    on 120,000 fresh ids."""
+    rng = np.random.default_rng(11)
+    ids = rng.choice(1 << 24, 9600 + 120_000, replace=False)
+    ins, fresh = ids[:9600], ids[9600:]
+    setb = set()
+    for x in ins:
+        setb.update(oracle.bloom_slots(int(x)))
+    fp = sum(all(h in setb for h in oracle.bloom_slots(int(x))) for x in fresh)
+    p = (1 - np.exp(-2 * 9600 / oracle.BLOOM_Z)) ** 2
+    mu, sd = p * len(fresh), np.sqrt(p * (1 - p) * len(fresh))
+    assert abs(fp - mu) < 5 * sd, (fp, mu, sd)
+
+
+def _nodes_at_risk(n):
+    """Nodes both of whose entries are also entries of other nodes: the
+    only ones a Bloom filter over this graph can wrongly drop."""
+    from collections import Counter
+    sl = [oracle.bloom_slots(x) for x in range(n)]
+    cnt = Counter(h for s in sl for h in set(s))
+    return [x for x, s in enumerate(sl) if all(cnt[h] > 1 for h in set(s))]
+
+
+@pytest.mark.parametrize("fx", ["small_f32", "small_u8"])
+@pytest.mark.parametrize("L", [10, 33, 64])
+def test_bloom_search_equals_exact_seen_set_without_collisions(fx, L,
+                                                              request):
+    """A Bloom filter has no false negatives, so where no node can be a
+    false positive (no node's two entries are both shared with other
+    nodes) Algorithm 2 with the Bloom filter is Algorithm 2 with an exact
+    seen-set: same expansions, same answer."""
+    ix, q, _ = request.getfixturevalue(fx)
+    assert _nodes_at_risk(ix.n) == []
+    a = oracle.search(ix, q, 10, L, mode=1, want_pq=True, want_cand=True)
+    b = oracle.search(ix, q, 10, L, mode=2, want_pq=True, want_cand=True)
+    for key in ("ids", "dists", "pq_ids", "pq_dists", "cand", "iters",
+                "added"):
+        assert np.array_equal(a[key], b[key]), key
+
+
+def _collision_graph(row):
+    """Medoid s = 12446 with the given adjacency row; every other row
+    empty.  Node 11616's first entry is one of s's and its second one of
+    node 12330's (found by search over the hash values)."""
+    s, a, y = 12446, 12330, 11616
+    hs, ha, hy = (oracle.bloom_slots(v) for v in (s, a, y))
+    assert hy[0] in hs and hy[1] in ha
+    assert hy[1] not in hs and hy[0] not in ha
+    n, R = s + 1, 2
+    rng = np.random.default_rng(5)
+    base = rng.random((n, 4), dtype=np.float32)
+    adj = np.full((n, R), NONE, dtype=np.uint32)
+    adj[s, :len(row)] = row
+    cb = rng.random((1, 256, 4), dtype=np.float32)
+    codes = rng.integers(0, 256, (n, 1), dtype=np.uint8)
+    return oracle.Index(base, adj, s, cb, codes), base[:1].copy(), s, a, y
+
+
+def test_bloom_false_positive_depends_on_row_order():
+    """Algorithm 2 tests and then sets each neighbour's entries; read with
+    sequential in-row semantics, a neighbour sees the entries set by the
+    ones before it.  Row [a, y] under s: y's entries were set by s (at the
+    start) and by a (just before), so y counts as visited and is dropped,
+    a false positive.  Row [y, a]: y is tested before a sets its entry, so
+    it is kept.  The exact seen-set keeps y either way."""
+    ix, q, s, a, y = _collision_graph([12330, 11616])
+    exact = oracle.search(ix, q, 1, 8, mode=1, want_cand=True)
+    bloom = oracle.search(ix, q, 1, 8, mode=2, want_cand=True)
+    assert sorted(exact["cand"][0][:exact["iters"][0]].tolist()) == sorted(
+        [s, a, y])
+    assert bloom["cand"][0][:bloom["iters"][0]].tolist() == [s, a]
+    ix2, q2, *_ = _collision_graph([11616, 12330])
+    bloom2 = oracle.search(ix2, q2, 1, 8, mode=2, want_cand=True)
+    assert sorted(bloom2["cand"][0][:bloom2["iters"][0]].tolist()) == sorted(
+        [s, a, y])
