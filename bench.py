@@ -37,7 +37,8 @@ TARGET_RECALL = 0.9
 TABLES = ("f32", "f16", "u8")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "search_sift1m_traffic.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2401_11324_amd", "csrc", f)
-                  for f in ("bang_kernels.hip", "bang_api.cpp", "internal.h")]
+                  for f in ("search_kernel.h", "search_variants.hip",
+                            "bang_kernels.hip", "bang_api.cpp", "internal.h")]
 
 
 def kernel_hash() -> str:

@@ -112,7 +112,28 @@ typedef struct {
                                Each query's result equals a search of that
                                query alone with (k_i, L_i). */
   const uint32_t* query_k;  /* device [nq] or NULL (every k_i = k) */
+  uint32_t filter;          /* visited filter: BANG_FILTER_EXACT (default)
+                               or BANG_FILTER_BLOOM */
 } bang_search_opts;
+
+/* Visited filters.
+ *  - EXACT: set union into the worklist (Algorithm 1): a neighbour already
+ *    in the worklist is dropped; one evicted from a full worklist can never
+ *    re-enter, so this is an exact seen-set.  No extra memory.
+ *  - BLOOM: the paper's filter (section "Parallel Filtering of Visited
+ *    Neighbours"): per query z = BANG_BLOOM_Z entries and two FNV-1a-32
+ *    hashes of the id's four little-endian bytes (offset bases 0x811C9DC5
+ *    and 0x811C9DC5 ^ 0xA5A5A5A5), mod z; a neighbour whose two entries are
+ *    both set counts as visited and is dropped, otherwise both are set.  The
+ *    neighbours of a row are filtered in stored order (a neighbour sees the
+ *    entries set by those before it).  False positives drop nodes that were
+ *    never seen, so results differ from EXACT.  Device memory: 4*z bytes
+ *    per resident wave (entries are 32-bit tags ordered by query, row and
+ *    neighbour, which resolve the in-row order in one round trip), taken
+ *    with the search workspace the first time. */
+#define BANG_FILTER_EXACT 0u
+#define BANG_FILTER_BLOOM 1u
+#define BANG_BLOOM_Z 399887u
 
 /* The re-rank sorts a query's expanded nodes in on-chip memory when they
  * fit there and otherwise selects them in device memory; this flag takes

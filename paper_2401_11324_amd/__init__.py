@@ -23,6 +23,8 @@ MAX_R = 64
 DTYPES = {"f32": 0, "u8": 1, "i8": 2}
 TABLES = {"f32": 0, "f16": 1, "u8": 2, "exact": 3}
 INDEX_HOST_ADJ = 1
+# visited filters (bang.h BANG_FILTER_*)
+FILTERS = {"exact": 0, "bloom": 1}
 ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EUNSUPPORTED",
           -5: "EABORTED"}
 EXPORTS = ("bang_index_create", "bang_index_destroy", "bang_build_pq_tables",
@@ -52,7 +54,8 @@ class SearchOpts(ctypes.Structure):
                 ("out_counters", ctypes.c_void_p),
                 ("out_times", ctypes.c_void_p),
                 ("table", ctypes.c_uint32), ("flags", ctypes.c_uint32),
-                ("query_L", ctypes.c_void_p), ("query_k", ctypes.c_void_p)]
+                ("query_L", ctypes.c_void_p), ("query_k", ctypes.c_void_p),
+                ("filter", ctypes.c_uint32)]
 
 
 class ServerOpts(ctypes.Structure):
@@ -207,7 +210,7 @@ class Index:
                want_cand: int = 0, want_counters: bool = False,
                want_times: bool = False, table: str = "f32",
                rerank_global: bool = False, query_L=None, query_k=None,
-               out=None, stream=None):
+               filter: str = "exact", out=None, stream=None):
         """Stages 1-3.  Returns (ids uint32-as-int32 [nq][k], dists
         float32 [nq][k]) and, on request, the expanded nodes [nq][want_cand]
         `table` is the PQ table storage the search ranks by: "f32", the
@@ -216,7 +219,9 @@ class Index:
         [nq]) make a mixed batch: query i with its own L_i <= L and
         k_i <= min(k, L_i), row i holding k_i results then padding.
         and counters [nq][4] (iterations, status) and device wall-clock
-        ticks [nq][2] (begin, end)."""
+        ticks [nq][2] (begin, end).  `filter` is the visited filter:
+        "exact" (set union, the default) or "bloom" (the paper's Bloom
+        filter, BANG_FILTER_BLOOM)."""
         import torch
         qp = self._queries(q)
         nq = q.shape[0]
@@ -228,6 +233,7 @@ class Index:
             _check_out(ids, dists, nq, k, q.device)
         opts = SearchOpts(c_max, iter_cap, None, 0, None, None, TABLES[table],
                           1 if rerank_global else 0)
+        opts.filter = FILTERS[filter]
         for t, nm in ((query_L, "query_L"), (query_k, "query_k")):
             if t is not None:
                 if tuple(t.shape) != (nq,):

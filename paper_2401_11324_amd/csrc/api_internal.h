@@ -22,6 +22,11 @@ struct Workspace {
   uint64_t* cscratch = nullptr;
   size_t cscratch_bytes = 0;
   uint32_t* qcounter = nullptr;
+  // Bloom filter (BANG_FILTER_BLOOM only): BANG_BLOOM_Z entries and one
+  // query epoch per resident wave, for bloom_waves waves
+  uint32_t* bloom = nullptr;
+  uint32_t* bloom_epoch = nullptr;
+  uint64_t bloom_waves = 0;
 };
 
 int workspace_init(Workspace* ws, size_t cscratch_bytes);

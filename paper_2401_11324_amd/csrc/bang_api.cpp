@@ -58,6 +58,10 @@ int workspace_init(Workspace* ws, size_t cscratch_bytes) {
 void workspace_free(Workspace* ws) {
   (void)hipFree(ws->cscratch);
   (void)hipFree(ws->qcounter);
+  (void)hipFree(ws->bloom);
+  (void)hipFree(ws->bloom_epoch);
+  ws->bloom = ws->bloom_epoch = nullptr;
+  ws->bloom_waves = 0;
   *ws = Workspace{};
 }
 
@@ -267,7 +271,7 @@ int check_queries(const bang_index* ix, const void* queries) {
 
 // Launch geometry of a search: LDS bytes and resident workgroups.
 int search_geometry(bang_index* ix, uint64_t nq, uint32_t L, uint32_t iter_cap,
-                    uint32_t table, size_t* lds, uint64_t* grid) {
+                    uint32_t table, bool bloom, size_t* lds, uint64_t* grid) {
   *lds = bang::search_lds_bytes(ix->dev.m, L, iter_cap, (int)table);
   hipError_t e = hipSetDevice(ix->device);
   if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
@@ -277,7 +281,7 @@ int search_geometry(bang_index* ix, uint64_t nq, uint32_t L, uint32_t iter_cap,
                     " bytes of LDS, the device allows " +
                     std::to_string(ix->max_lds) + " (lower L or iter_cap)");
   int per_cu = 0;
-  e = bang::search_occupancy(ix->dev, (int)table, *lds, &per_cu);
+  e = bang::search_occupancy(ix->dev, (int)table, bloom, *lds, &per_cu);
   if (e != hipSuccess) return hip_fail(e, "occupancy query");
   if (per_cu < 1) return fail(BANG_EUNSUPPORTED, "search kernel cannot be resident");
   *grid = std::min<uint64_t>((uint64_t)per_cu * ix->num_cus, nq);
@@ -292,7 +296,8 @@ size_t search_workspace_bytes(bang_index* ix, uint64_t nq, uint32_t L,
                               uint32_t iter_cap, uint32_t table) {
   size_t lds;
   uint64_t grid;
-  if (search_geometry(ix, nq, L, iter_cap, table, &lds, &grid)) return 0;
+  if (search_geometry(ix, nq, L, iter_cap, table, false, &lds, &grid))
+    return 0;
   return (size_t)grid * iter_cap * sizeof(uint64_t);
 }
 
@@ -328,10 +333,14 @@ int search_with(bang_index* ix, Workspace* ws, bool grow, const void* queries,
   const uint32_t flags = o ? o->flags : 0u;
   if (flags & ~BANG_SEARCH_RERANK_GLOBAL)
     return fail(BANG_EINVAL, "unknown search flags");
+  const uint32_t filter = o ? o->filter : BANG_FILTER_EXACT;
+  if (filter > BANG_FILTER_BLOOM)
+    return fail(BANG_EINVAL, "unknown visited filter");
 
   size_t lds;
   uint64_t grid;
-  rc = search_geometry(ix, nq, L, iter_cap, table, &lds, &grid);
+  rc = search_geometry(ix, nq, L, iter_cap, table,
+                       filter == BANG_FILTER_BLOOM, &lds, &grid);
   if (rc) return rc;
   size_t need = (size_t)grid * iter_cap * sizeof(uint64_t);
   if (need > ws->cscratch_bytes) {
@@ -351,6 +360,37 @@ int search_with(bang_index* ix, Workspace* ws, bool grow, const void* queries,
       return fail(BANG_ENOMEM, std::string("search workspace: ") +
                                    hipGetErrorString(e));
     ws->cscratch_bytes = need;
+  }
+  if (filter == BANG_FILTER_BLOOM && grid > ws->bloom_waves) {
+    if (!grow)
+      return fail(BANG_ENOMEM, "Bloom filters for " +
+                                   std::to_string(ws->bloom_waves) +
+                                   " waves, the launch needs " +
+                                   std::to_string(grid));
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+    (void)hipFree(ws->bloom);
+    (void)hipFree(ws->bloom_epoch);
+    ws->bloom = ws->bloom_epoch = nullptr;
+    ws->bloom_waves = 0;
+    const size_t fb = (size_t)grid * BANG_BLOOM_Z * sizeof(uint32_t);
+    e = hipMalloc(reinterpret_cast<void**>(&ws->bloom), fb);
+    if (e == hipSuccess)
+      e = hipMalloc(reinterpret_cast<void**>(&ws->bloom_epoch),
+                    (size_t)grid * sizeof(uint32_t));
+    if (e != hipSuccess) {
+      (void)hipFree(ws->bloom);
+      ws->bloom = nullptr;
+      return fail(BANG_ENOMEM, std::string("Bloom filters: ") +
+                                   hipGetErrorString(e));
+    }
+    // every entry unset (above any tag) and every epoch at its start
+    e = hipMemset(ws->bloom, 0xFF, fb);
+    if (e == hipSuccess)
+      e = hipMemset(ws->bloom_epoch, 0, (size_t)grid * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(e, "Bloom filter init");
+    ws->bloom_waves = grid;
   }
 
   bang::SearchLaunch l{};
@@ -372,6 +412,8 @@ int search_with(bang_index* ix, Workspace* ws, bool grow, const void* queries,
   l.out_times = o ? o->out_times : nullptr;
   l.cscratch = ws->cscratch;
   l.qcounter = ws->qcounter;
+  l.bloom = filter == BANG_FILTER_BLOOM ? ws->bloom : nullptr;
+  l.bloom_epoch = filter == BANG_FILTER_BLOOM ? ws->bloom_epoch : nullptr;
   l.grid = (uint32_t)grid;
   hipError_t e = bang::launch_search(ix->dev, l, s);
   if (e != hipSuccess) return hip_fail(e, "search launch");

@@ -1,1203 +1,13 @@
-// HIP kernels for gfx950 (MI355X): PQ distance table, batched greedy search
-// with asymmetric distances, exact re-rank.
-//
-// Design (one wavefront of 64 lanes per query, persistent workgroups):
-//  * the query's FP32 PQ table (m x 256) is built into LDS by the wave and
-//    stays there for the whole search (section "Construction of PQDistTable
-//    in Parallel": one query per block, centroids across threads, subspaces
-//    sequential in a thread);
-//  * lane r owns slot r of the expanded node's adjacency row (R <= 64), so
-//    the row is one coalesced load and each lane gathers its neighbour's m
-//    code bytes with 16-byte loads and sums m table lookups in subspace
-//    order (section "Parallel Neighbour Distance Computation");
-//  * the new keys are sorted across the 64 lanes by a bitonic network
-//    (section "Parallel Merge Sort" sorts the same <= 64 items);
-//  * each sorted key finds its rank in the worklist by binary search in
-//    LDS, which also detects a node already in the worklist (the union of
-//    Algorithm 1 is a set union), and every worklist key finds its rank
-//    among the new keys; position = own index + rank in the other list
-//    (section "Parallel Merge"), keys past t are dropped;
-//  * the next node to expand is chosen from the two candidates the paper's
-//    eager rule names (best new key, first unvisited worklist entry) before
-//    the merged list is written, and its adjacency row is requested at once
-//    (section "Prefetching Candidate Nodes"), so the load overlaps the merge;
-//  * after convergence the expanded nodes are re-ranked with exact
-//    distances and sorted in LDS (section "Re-ranking").
-//
-// Keys: (float bits of the distance) << 32 | id << 1 | visited.  Distances
-// are non-negative, so unsigned key order is (distance, id) order; ids are
-// unique in a worklist, so the visited bit never decides an order.
-//
-// All floating point here is FP32 with contraction off and a fixed order,
-// which makes results bit-identical to a sequential reference.
+// HIP kernels for gfx950 (MI355X) besides the search (search_kernel.h,
+// search_variants.hip): the stand-alone PQ table and re-rank kernels, the
+// packing of adjacency rows with their neighbours' codes, and the host side
+// of every launch (LDS sizes, occupancy, variant choice).
 
-#include <hip/hip_runtime.h>
-#include <stdint.h>
-
-#include <algorithm>
-
-#include "internal.h"
-
-#pragma clang fp contract(off)
+#include "search_kernel.h"
 
 namespace bang {
 
 namespace {
-
-constexpr uint32_t kNone = 0xFFFFFFFFu;
-constexpr uint64_t kInf = ~0ull;
-constexpr int kWave = 64;
-// s_waitcnt immediate for vmcnt(0) alone (gfx9 encoding: expcnt and lgkmcnt
-// at their maxima, no wait on them)
-constexpr unsigned kWaitVmem0 = 0x0F70;
-
-__device__ __forceinline__ uint64_t make_key(float d, uint32_t id) {
-  return ((uint64_t)__float_as_uint(d) << 32) | ((uint64_t)id << 1);
-}
-__device__ __forceinline__ uint32_t key_id(uint64_t k) {
-  return ((uint32_t)k) >> 1;
-}
-__device__ __forceinline__ float key_dist(uint64_t k) {
-  return __uint_as_float((uint32_t)(k >> 32));
-}
-
-template <int DT>
-struct Elem;
-template <>
-struct Elem<kF32> {
-  static constexpr int size = 4;
-  __device__ static float f(const unsigned char* p, int i) {
-    return reinterpret_cast<const float*>(p)[i];
-  }
-};
-template <>
-struct Elem<kU8> {
-  static constexpr int size = 1;
-  __device__ static float f(const unsigned char* p, int i) {
-    return (float)p[i];
-  }
-};
-template <>
-struct Elem<kI8> {
-  static constexpr int size = 1;
-  __device__ static float f(const unsigned char* p, int i) {
-    return (float)(int8_t)p[i];
-  }
-};
-
-// One table entry: sum over the subvector in coordinate order, FP32.
-template <int DS>
-__device__ __forceinline__ float table_entry(const float* qv,
-                                             const float* __restrict__ cent) {
-  float cv[DS];
-  if constexpr (DS % 4 == 0) {
-#pragma unroll
-    for (int t = 0; t < DS; t += 4) {
-      float4 v = *reinterpret_cast<const float4*>(cent + t);
-      cv[t] = v.x; cv[t + 1] = v.y; cv[t + 2] = v.z; cv[t + 3] = v.w;
-    }
-  } else if constexpr (DS % 2 == 0) {
-#pragma unroll
-    for (int t = 0; t < DS; t += 2) {
-      float2 v = *reinterpret_cast<const float2*>(cent + t);
-      cv[t] = v.x; cv[t + 1] = v.y;
-    }
-  } else {
-#pragma unroll
-    for (int t = 0; t < DS; ++t) cv[t] = cent[t];
-  }
-  float acc = 0.0f;
-#pragma unroll
-  for (int t = 0; t < DS; ++t) {
-    float diff = qv[t] - cv[t];
-    float sq = diff * diff;
-    acc = acc + sq;
-  }
-  return acc;
-}
-
-// Table of one query: T[j*256 + c], `nthr` threads starting at `tid`.
-template <int DT, int M, int DS>
-__device__ __forceinline__ void build_table(const unsigned char* q,
-                                            const float* __restrict__ cb,
-                                            float* T, int tid, int nthr) {
-  for (int j = 0; j < M; ++j) {
-    float qv[DS];
-#pragma unroll
-    for (int t = 0; t < DS; ++t) qv[t] = Elem<DT>::f(q, j * DS + t);
-    for (int c = tid; c < 256; c += nthr)
-      T[j * 256 + c] = table_entry<DS>(qv, cb + ((size_t)j * 256 + c) * DS);
-  }
-}
-
-// ADC of one compressed vector: sum of m table entries, subspace order.
-template <int M>
-__device__ __forceinline__ float adc(const float* T,
-                                     const uint8_t* __restrict__ code) {
-  static_assert(M % 16 == 0, "codes are gathered 16 bytes at a time");
-  uint4 v[M / 16];
-#pragma unroll
-  for (int c = 0; c < M / 16; ++c)
-    v[c] = *reinterpret_cast<const uint4*>(code + 16 * c);
-  float acc = 0.0f;
-#pragma unroll
-  for (int c = 0; c < M / 16; ++c) {
-    const uint32_t w[4] = {v[c].x, v[c].y, v[c].z, v[c].w};
-#pragma unroll
-    for (int b = 0; b < 16; ++b) {
-      uint32_t byte = (w[b >> 2] >> (8 * (b & 3))) & 0xFFu;
-      acc = acc + T[(16 * c + b) * 256 + byte];
-    }
-  }
-  return acc;
-}
-
-// Table storage of the search: canonical FP32, or the precision form's
-// half (times a power-of-two scale) or u8 (per-subspace offset, one scale).
-// Both reduced forms are derived from the canonical FP32 entries, so they
-// are as deterministic as the FP32 table itself.  kTabExact: no table; the
-// search ranks by exact distances and skips the re-rank (the paper's
-// Exact-distance Version, section "Implementation Variants").
-enum TableKind : int { kTabF32 = 0, kTabF16 = 1, kTabU8 = 2, kTabExact = 3 };
-
-template <int TT>
-struct Tab;
-template <>
-struct Tab<kTabF32> {
-  using E = float;
-};
-template <>
-struct Tab<kTabF16> {
-  using E = uint16_t;
-};
-template <>
-struct Tab<kTabU8> {
-  using E = uint8_t;
-};
-template <>
-struct Tab<kTabExact> {
-  using E = uint8_t;  // no table
-};
-template <int TT>
-constexpr int table_bytes(int M) {
-  return TT == kTabExact ? 0 : M * 256 * (int)sizeof(typename Tab<TT>::E);
-}
-
-__device__ __forceinline__ float f16_bits_to_f32(uint16_t h) {
-  return (float)__builtin_bit_cast(_Float16, h);
-}
-
-// Maximum / minimum of one float per lane across the wave (DPP), returned
-// to every lane.  `ident` is the identity for lanes outside a row.
-template <bool MAX>
-__device__ __forceinline__ float wave_minmax(float v, float ident) {
-  const uint32_t id = __float_as_uint(ident);
-#define BANG_MM(CTRL, RM)                                                    \
-  {                                                                          \
-    float t = __uint_as_float((uint32_t)__builtin_amdgcn_update_dpp(         \
-        (int)id, (int)__float_as_uint(v), CTRL, RM, 0xF, false));            \
-    v = MAX ? (t > v ? t : v) : (t < v ? t : v);                             \
-  }
-  BANG_MM(0x111, 0xF) BANG_MM(0x112, 0xF) BANG_MM(0x114, 0xF)
-  BANG_MM(0x118, 0xF) BANG_MM(0x142, 0xA) BANG_MM(0x143, 0xC)
-#undef BANG_MM
-  return __uint_as_float(
-      __builtin_amdgcn_readlane(__float_as_uint(v), 63));
-}
-
-// The query's table in LDS, in the storage form TT (one wave, 64 lanes).
-// lo (U8 only): m floats of LDS for the per-subspace offsets.
-template <int DT, int M, int DS, int TT>
-__device__ __forceinline__ void build_table_q(const unsigned char* q,
-                                              const float* __restrict__ cb,
-                                              void* Tv, float* lo, int lane) {
-  if constexpr (TT == kTabF32) {
-    build_table<DT, M, DS>(q, cb, reinterpret_cast<float*>(Tv), lane, kWave);
-  } else {
-    // pass 1: the statistics the storage needs
-    float mx = 0.0f;  // F16: largest entry; U8: widest subspace range
-    for (int j = 0; j < M; ++j) {
-      float qv[DS];
-#pragma unroll
-      for (int t = 0; t < DS; ++t) qv[t] = Elem<DT>::f(q, j * DS + t);
-      float vmin = __uint_as_float(0x7F800000u), vmax = 0.0f;
-#pragma unroll
-      for (int r = 0; r < 256 / kWave; ++r) {
-        const int c = lane + kWave * r;
-        const float e = table_entry<DS>(qv, cb + ((size_t)j * 256 + c) * DS);
-        vmin = e < vmin ? e : vmin;
-        vmax = e > vmax ? e : vmax;
-      }
-      if constexpr (TT == kTabF16) {
-        mx = vmax > mx ? vmax : mx;
-      } else {
-        const float l = wave_minmax<false>(vmin, __uint_as_float(0x7F800000u));
-        const float h = wave_minmax<true>(vmax, 0.0f);
-        const float range = h - l;
-        mx = range > mx ? range : mx;
-        if (lane == 0) lo[j] = l;
-      }
-    }
-    float mul;
-    if constexpr (TT == kTabF16) {
-      mx = wave_minmax<true>(mx, 0.0f);
-      mul = 1.0f;
-      while (mx * mul > 65504.0f) mul = mul * 0.5f;
-    } else {
-      mul = mx > 0.0f ? 255.0f / mx : 0.0f;
-      __syncthreads();  // lo[] visible to every lane
-    }
-    // pass 2: the entries again (bit-identical), stored in the reduced form
-    typename Tab<TT>::E* T = reinterpret_cast<typename Tab<TT>::E*>(Tv);
-    for (int j = 0; j < M; ++j) {
-      float qv[DS];
-#pragma unroll
-      for (int t = 0; t < DS; ++t) qv[t] = Elem<DT>::f(q, j * DS + t);
-      const float lj = (TT == kTabU8) ? lo[j] : 0.0f;
-#pragma unroll
-      for (int r = 0; r < 256 / kWave; ++r) {
-        const int c = lane + kWave * r;
-        const float e = table_entry<DS>(qv, cb + ((size_t)j * 256 + c) * DS);
-        if constexpr (TT == kTabF16) {
-          const float sv = e * mul;
-          T[j * 256 + c] = __builtin_bit_cast(uint16_t, (_Float16)sv);
-        } else {
-          const float diff = e - lj;
-          const float v = __builtin_rintf(diff * mul);
-          T[j * 256 + c] = (uint8_t)(v > 255.0f ? 255.0f : v);
-        }
-      }
-    }
-  }
-}
-
-// ADC under storage TT: FP32 sum of the (widened) entries in subspace order;
-// for U8 the exact integer sum, returned as FP32 (exact below 2^24).
-// (byte B of w) << S in one instruction (SDWA byte select): the byte
-// offset of entry `code` in a table row of 2^S-byte entries.
-#define BANG_SDWA_SHL(S, B)                                               \
-  asm("v_lshlrev_b32_sdwa %0, " #S ", %1 dst_sel:DWORD "                   \
-      "dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_" #B             \
-      : "=v"(r) : "v"(w))
-template <int S, int B>
-__device__ __forceinline__ uint32_t byte_shl(uint32_t w) {
-  static_assert(S >= 0 && S <= 2 && B >= 0 && B <= 3, "byte_shl");
-  if constexpr (S == 0) {
-    return (w >> (8 * B)) & 0xFFu;
-  } else {
-    uint32_t r;
-    if constexpr (S == 1 && B == 0) BANG_SDWA_SHL(1, 0);
-    else if constexpr (S == 1 && B == 1) BANG_SDWA_SHL(1, 1);
-    else if constexpr (S == 1 && B == 2) BANG_SDWA_SHL(1, 2);
-    else if constexpr (S == 1 && B == 3) BANG_SDWA_SHL(1, 3);
-    else if constexpr (B == 0) BANG_SDWA_SHL(2, 0);
-    else if constexpr (B == 1) BANG_SDWA_SHL(2, 1);
-    else if constexpr (B == 2) BANG_SDWA_SHL(2, 2);
-    else BANG_SDWA_SHL(2, 3);
-    return r;
-  }
-}
-#undef BANG_SDWA_SHL
-
-// ADC of one neighbour from its m codes (16 per uint4) against the query's
-// table, which must start at LDS address 0: the search kernel puts it first
-// in its dynamic LDS block and declares no static LDS.
-template <int M, int TT>
-__device__ __forceinline__ float adc_codes(const uint4 (&v)[M / 16]) {
-  using E = typename Tab<TT>::E;
-  // all M lookups are issued before the first add, so their LDS latencies
-  // overlap; the adds then run in subspace order
-  E e[M];
-#pragma unroll
-  for (int c = 0; c < M / 16; ++c) {
-    const uint32_t w[4] = {v[c].x, v[c].y, v[c].z, v[c].w};
-#pragma unroll
-    for (int b = 0; b < 16; ++b) {
-      // entry (j, code) at byte offset (j*256 + code) * sizeof(E); the
-      // byte offset of the code comes from one SDWA instruction, and the
-      // table, the first thing in the dynamic LDS block, starts at LDS
-      // address 0 (search_kernel declares no static LDS), so no base is
-      // added
-      constexpr int S = sizeof(E) == 4 ? 2 : (sizeof(E) == 2 ? 1 : 0);
-      uint32_t off;
-      switch (b & 3) {
-        case 0: off = byte_shl<S, 0>(w[b >> 2]); break;
-        case 1: off = byte_shl<S, 1>(w[b >> 2]); break;
-        case 2: off = byte_shl<S, 2>(w[b >> 2]); break;
-        default: off = byte_shl<S, 3>(w[b >> 2]); break;
-      }
-      using lds_E = __attribute__((address_space(3))) const E;
-      e[16 * c + b] = *(reinterpret_cast<lds_E*>(static_cast<uintptr_t>(off)) +
-                        (16 * c + b) * 256);
-    }
-  }
-  __builtin_amdgcn_sched_barrier(0);
-  float acc = 0.0f;
-  uint32_t iacc = 0;
-#pragma unroll
-  for (int j = 0; j < M; ++j) {
-    if constexpr (TT == kTabF32) acc = acc + e[j];
-    else if constexpr (TT == kTabF16) acc = acc + f16_bits_to_f32(e[j]);
-    else iacc += e[j];
-  }
-  return TT == kTabU8 ? (float)iacc : acc;
-}
-
-// Sum of the squares of the query's coordinates, integer data only (0 for
-// FP32): the constant term of exact_dist.
-template <int DT, int D>
-__device__ __forceinline__ int32_t query_sq(const unsigned char* q) {
-  if constexpr (DT == kF32) {
-    return 0;
-  } else {
-    const uint32_t* qw = reinterpret_cast<const uint32_t*>(q);
-    uint32_t s = 0;
-#pragma unroll
-    for (int i = 0; i < D / 4; ++i) {
-      if constexpr (DT == kU8)
-        s = __builtin_amdgcn_udot4(qw[i], qw[i], s, false);
-      else
-        s = (uint32_t)__builtin_amdgcn_sdot4((int)qw[i], (int)qw[i], (int)s,
-                                             false);
-    }
-    return (int32_t)s;
-  }
-}
-
-// Exact squared distance between base row `id` and the query.  FP32 data:
-// the differences squared and added left to right over the d coordinates.
-// Integer data: sum (x - q)^2 = sum x^2 - 2 sum x q + qq (qq = query_sq),
-// each sum exact from four-byte dot products, so the value is the plain
-// integer sum (below 2^24, exact in FP32).
-// EAGER: every load of the row is issued before the first product (one
-// memory round trip, D/4 more registers); otherwise two chunks at a time.
-template <int DT, int D, bool EAGER = false>
-__device__ __forceinline__ float exact_dist(const void* __restrict__ base,
-                                            uint32_t id,
-                                            const unsigned char* q,
-                                            int32_t qq) {
-  if constexpr (DT == kF32) {
-    const float4* x =
-        reinterpret_cast<const float4*>((const float*)base + (size_t)id * D);
-    const float* qq = reinterpret_cast<const float*>(q);
-    float acc = 0.0f;
-#pragma unroll 4
-    for (int c = 0; c < D / 4; ++c) {
-      float4 v = x[c];
-      const float xv[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        float diff = xv[t] - qq[4 * c + t];
-        float sq = diff * diff;
-        acc = acc + sq;
-      }
-    }
-    return acc;
-  } else {
-    static_assert(D % 16 == 0, "rows are read 16 bytes at a time");
-    const uint4* x = reinterpret_cast<const uint4*>(
-        (const uint8_t*)base + (size_t)id * D);
-    const uint32_t* qw = reinterpret_cast<const uint32_t*>(q);
-    uint32_t xx = 0, xq = 0;
-    uint4 row[EAGER ? D / 16 : 1];
-    if constexpr (EAGER) {
-#pragma unroll
-      for (int c = 0; c < D / 16; ++c) row[c] = x[c];
-    }
-    constexpr int kUnroll = EAGER ? D / 16 : 2;
-#pragma unroll kUnroll
-    for (int c = 0; c < D / 16; ++c) {
-      const uint4 v = EAGER ? row[EAGER ? c : 0] : x[c];
-      const uint32_t w[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        if constexpr (DT == kU8) {
-          xx = __builtin_amdgcn_udot4(w[t], w[t], xx, false);
-          xq = __builtin_amdgcn_udot4(w[t], qw[4 * c + t], xq, false);
-        } else {
-          xx = (uint32_t)__builtin_amdgcn_sdot4((int)w[t], (int)w[t], (int)xx,
-                                                false);
-          xq = (uint32_t)__builtin_amdgcn_sdot4((int)w[t], (int)qw[4 * c + t],
-                                                (int)xq, false);
-        }
-      }
-    }
-    return (float)(int32_t)(xx - 2u * xq + (uint32_t)qq);
-  }
-}
-
-__device__ __forceinline__ uint64_t shfl_xor64(uint64_t v, int m) {
-  uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
-  lo = __shfl_xor(lo, m);
-  hi = __shfl_xor(hi, m);
-  return ((uint64_t)hi << 32) | lo;
-}
-
-// v of the lowest lane set in the wave-uniform mask (nonzero): a scalar
-// read of one lane, no LDS round trip.
-__device__ __forceinline__ uint32_t first_of(uint32_t v, uint64_t mask) {
-  return __builtin_amdgcn_readlane(v, __builtin_ctzll(mask));
-}
-
-// Cross-lane helpers on DPP (data-parallel primitives; no LDS round trip).
-// dpp_ctrl encodings of the GFX9 family: row_shr:n = 0x110 + n,
-// row_bcast:15 = 0x142, row_bcast:31 = 0x143.
-template <int CTRL, int ROW_MASK = 0xF>
-__device__ __forceinline__ uint32_t dpp(uint32_t old, uint32_t v) {
-  return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)v, CTRL,
-                                               ROW_MASK, 0xF, false);
-}
-
-// Exclusive prefix sum of one value per lane across the wave.
-__device__ __forceinline__ uint32_t wave_exclusive_scan(uint32_t x) {
-  uint32_t v = x;
-  v += dpp<0x111>(0u, v);  // row_shr:1
-  v += dpp<0x112>(0u, v);  // row_shr:2
-  v += dpp<0x114>(0u, v);  // row_shr:4
-  v += dpp<0x118>(0u, v);  // row_shr:8
-  v += dpp<0x142, 0xA>(0u, v);  // row_bcast:15 into rows 1 and 3
-  v += dpp<0x143, 0xC>(0u, v);  // row_bcast:31 into rows 2 and 3
-  return v - x;
-}
-
-template <int CTRL, int ROW_MASK = 0xF>
-__device__ __forceinline__ uint64_t min_dpp(uint64_t v) {
-  const uint32_t lo = dpp<CTRL, ROW_MASK>(0xFFFFFFFFu, (uint32_t)v);
-  const uint32_t hi = dpp<CTRL, ROW_MASK>(0xFFFFFFFFu, (uint32_t)(v >> 32));
-  const uint64_t t = ((uint64_t)hi << 32) | lo;
-  return t < v ? t : v;
-}
-
-// Minimum of one u64 per lane across the wave, returned to every lane.
-__device__ __forceinline__ uint64_t wave_min64(uint64_t v) {
-  v = min_dpp<0x111>(v);
-  v = min_dpp<0x112>(v);
-  v = min_dpp<0x114>(v);
-  v = min_dpp<0x118>(v);
-  v = min_dpp<0x142, 0xA>(v);
-  v = min_dpp<0x143, 0xC>(v);
-  const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, 63);
-  const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(v >> 32), 63);
-  return ((uint64_t)hi << 32) | lo;
-}
-
-// Exact distances of the wave's 64 neighbours (lane r: neighbour nb of lane
-// r) for integer data, with the base rows read cooperatively: G lanes, one
-// 16-byte chunk each, share a row, so one load instruction covers 64/G
-// whole rows instead of 64 scattered pieces.  Each lane adds the dot
-// products of its chunk (sum x^2 - 2 sum x q: exact integers), a DPP
-// reduction leaves each row's total in the last lane of its group, and
-// lane r collects neighbour r's.  Integer sums are exact in any order, so
-// the value equals exact_dist's.  qc = this lane's query chunk (zero past
-// the row), qq = query_sq.  Every lane must call it (cross-lane).
-template <int DT, int D>
-__device__ __forceinline__ float coop_dist(const void* __restrict__ base,
-                                           uint32_t nb, const uint4& qc,
-                                           int32_t qq, int lane) {
-  constexpr int CH = D / 16;
-  static_assert(D % 16 == 0 && CH >= 1 && CH <= 8, "rows of 16..128 bytes");
-  constexpr int G = CH <= 2 ? 2 : (CH <= 4 ? 4 : 8);  // lanes per row
-  constexpr int RPI = kWave / G;                      // rows per load
-  const int c = lane % G, g = lane / G;
-  const int cc = c < CH ? c : CH - 1;  // in-row chunk (masked below)
-  uint4 v[G];
-  bool ok[G];
-#pragma unroll
-  for (int t = 0; t < G; ++t) {
-    const uint32_t id = __shfl(nb, t * RPI + g);
-    ok[t] = id != kNone && c < CH;
-    v[t] = reinterpret_cast<const uint4*>(
-        (const uint8_t*)base + (size_t)(id != kNone ? id : 0u) * D)[cc];
-  }
-  const uint32_t qw[4] = {qc.x, qc.y, qc.z, qc.w};
-  uint32_t part[G];
-#pragma unroll
-  for (int t = 0; t < G; ++t) {
-    const uint32_t w[4] = {v[t].x, v[t].y, v[t].z, v[t].w};
-    uint32_t xx = 0, xq = 0;
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      if constexpr (DT == kU8) {
-        xx = __builtin_amdgcn_udot4(w[u], w[u], xx, false);
-        xq = __builtin_amdgcn_udot4(w[u], qw[u], xq, false);
-      } else {
-        xx = (uint32_t)__builtin_amdgcn_sdot4((int)w[u], (int)w[u], (int)xx,
-                                              false);
-        xq = (uint32_t)__builtin_amdgcn_sdot4((int)w[u], (int)qw[u], (int)xq,
-                                              false);
-      }
-    }
-    uint32_t s = ok[t] ? xx - 2u * xq : 0u;
-    // group total into the group's last lane (groups lie inside DPP rows)
-    s += dpp<0x111>(0u, s);                     // row_shr:1
-    if constexpr (G >= 4) s += dpp<0x112>(0u, s);  // row_shr:2
-    if constexpr (G >= 8) s += dpp<0x114>(0u, s);  // row_shr:4
-    part[t] = s;
-  }
-  // neighbour r was row slot r % RPI of load t = r / RPI
-  const int src = (lane % RPI) * G + (G - 1);
-  uint32_t tot = 0;
-#pragma unroll
-  for (int t = 0; t < G; ++t) {
-    const uint32_t x = __shfl(part[t], src);
-    if (lane / RPI == t) tot = x;
-  }
-  return (float)(int32_t)(tot + (uint32_t)qq);
-}
-
-// Number P of entries of the sorted LDS list A[0..len) whose key, visited
-// bit ignored, is below x's (1 <= len <= 1024, last = A[len-1]), and in ge
-// the entry A[P] (kInf when P = len).  (a >> 1) < (x >> 1) is tested as
-// a < (x & ~1).  Radix-4 lifting: three independent probes per level, half
-// the dependent LDS reads of a binary search.  The probe at index P is the
-// first failing one of the last level that fails, so ge comes for free;
-// probes past A[len-2] are clamped to A[len-1] = last, which is known not
-// to be below x (a clamp instead of a branch).
-__device__ __forceinline__ uint32_t rank_in(const uint64_t* A, uint32_t len,
-                                            uint64_t last, uint64_t x,
-                                            uint64_t& ge) {
-  const uint64_t xs = x & ~1ull;
-  if (last < xs) {
-    ge = kInf;
-    return len;
-  }
-  const uint32_t lim = len - 1;  // the answer is at most lim
-  uint32_t pos = 0;
-  uint64_t g = last;
-  for (uint32_t s = 256; s > 0; s >>= 2) {
-    if (s > lim) continue;
-    const uint32_t i1 = pos + s - 1, i2 = i1 + s, i3 = i2 + s;
-    const uint64_t v1 = A[min(i1, lim)];
-    const uint64_t v2 = A[min(i2, lim)];
-    const uint64_t v3 = A[min(i3, lim)];
-    const bool p1 = v1 < xs, p2 = v2 < xs, p3 = v3 < xs;
-    if (!p1)
-      g = v1;
-    else if (!p2)
-      g = v2;
-    else if (!p3)
-      g = v3;
-    pos += s * ((uint32_t)p1 + (uint32_t)p2 + (uint32_t)p3);
-  }
-  ge = g;
-  return pos;
-}
-
-// Ascending bitonic sort of S[0..P) in LDS by one wave (P a power of two).
-__device__ void lds_sort(uint64_t* S, uint32_t P, int lane) {
-  for (uint32_t size = 2; size <= P; size <<= 1) {
-    for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
-      for (uint32_t i = lane; i < P / 2; i += kWave) {
-        uint32_t lo = 2 * i - (i & (stride - 1));
-        uint32_t hi = lo + stride;
-        bool asc = (lo & size) == 0;
-        uint64_t x = S[lo], y = S[hi];
-        if ((x > y) == asc) {
-          S[lo] = y;
-          S[hi] = x;
-        }
-      }
-      __syncthreads();
-    }
-  }
-}
-
-__device__ __forceinline__ uint32_t pow2ceil_dev(uint32_t x) {
-  uint32_t p = 1;
-  while (p < x) p <<= 1;
-  return p;
-}
-
-// Sort the first `cnt` keys of S (padding to a power of two with +inf) and
-// write the first k as (id, distance), padding with (NONE, +inf).
-__device__ void sort_and_emit(uint64_t* S, uint32_t cnt, uint32_t k,
-                              uint32_t* out_ids, float* out_d, int lane) {
-  uint32_t P = pow2ceil_dev(cnt > 0 ? cnt : 1);
-  for (uint32_t i = cnt + lane; i < P; i += kWave) S[i] = kInf;
-  __syncthreads();
-  lds_sort(S, P, lane);
-  for (uint32_t i = lane; i < k; i += kWave) {
-    uint64_t key = i < cnt ? S[i] : kInf;
-    out_ids[i] = key == kInf ? kNone : key_id(key);
-    out_d[i] = key == kInf ? __uint_as_float(0x7F800000u) : key_dist(key);
-  }
-}
-
-// The k <= 64 smallest of the distinct keys S[i], i < cnt, ascending, to
-// the outputs (padded with (NONE, +inf)).  Lane l holds in best/at the
-// smallest of its own keys (i = l mod 64).  Each round the wave minimum is
-// the next result; only the lane that owned it rescans its keys.  k rounds
-// of a wave minimum instead of a sort of all cnt keys.
-__device__ void select_and_emit(uint64_t* S, uint32_t cnt, uint32_t k,
-                                uint64_t best, uint32_t at, uint32_t* out_ids,
-                                float* out_d, int lane) {
-  uint64_t mine = kInf;  // lane r: the r-th result
-  for (uint32_t r = 0; r < k; ++r) {
-    const uint64_t m = wave_min64(best);
-    if ((uint32_t)lane == r) mine = m;
-    if (m == kInf) break;
-    if (best == m) {  // one lane: the keys are distinct
-      S[at] = kInf;
-      best = kInf;
-      at = kNone;
-      for (uint32_t i = lane; i < cnt; i += kWave) {
-        const uint64_t v = S[i];
-        if (v < best) {
-          best = v;
-          at = i;
-        }
-      }
-    }
-  }
-  if ((uint32_t)lane < k) {
-    out_ids[lane] = mine == kInf ? kNone : key_id(mine);
-    out_d[lane] = mine == kInf ? __uint_as_float(0x7F800000u) : key_dist(mine);
-  }
-}
-
-// Partial selection sort in global memory: C[0..kk) become the kk smallest
-// of C[0..n), ascending.  For re-ranks too large for LDS (rare: an
-// expansion count far above L); one wave, with a device fence per round so
-// every lane sees lane 0's swap.
-__device__ void global_select(uint64_t* C, uint32_t n, uint32_t kk, int lane) {
-  for (uint32_t r = 0; r < kk && r < n; ++r) {
-    uint64_t best = kInf;
-    uint32_t at = kNone;
-    for (uint32_t i = r + lane; i < n; i += kWave) {
-      const uint64_t v = C[i];
-      if (v < best) {
-        best = v;
-        at = i;
-      }
-    }
-    const uint64_t m = wave_min64(best);
-    const uint64_t who = __ballot(best == m && at != kNone);
-    const uint32_t src = first_of(at, who);
-    if (lane == 0 && src != kNone && src != r) {
-      const uint64_t t = C[r];
-      C[r] = m;
-      C[src] = t;
-    }
-    __threadfence();
-    __syncthreads();
-  }
-}
-
-struct SearchArgs {
-  const void* base;
-  const unsigned char* rows;  // packed rows: ids, then the neighbours' codes
-  const uint8_t* codes;
-  const float* cb;
-  const uint32_t* hadj;  // host-resident adjacency [n][R], or null
-  const unsigned char* queries;
-  uint64_t nq;
-  uint32_t n, R, medoid;
-  uint32_t row_stride, row_ids;  // bytes per row; bytes of the id part
-  uint32_t k, Lcap, c_max, iter_cap;
-  uint32_t lblock;   // worklist entries per lane in a super-row, <= kPer
-  uint32_t lrow;     // worklist buffer entries: Lcap rounded up to 64*lblock
-  uint32_t region0;  // bytes of the table region (re-rank keys reuse it
-                     // together with the worklist buffer)
-  uint32_t s_cap;    // keys that fit there: (region0 + 8 * lrow) / 8, or
-                     // 0 to make the re-rank select in global memory
-  uint32_t* out_ids;   // [nq][k]: k is the row stride
-  float* out_dists;
-  // optional per-query worklist size and k (mixed batches): L_q in [1,
-  // Lcap] and k_q in [1, min(k, L_q)] (clamped into range); the iteration
-  // cap and c_max then follow L_q as their defaults do
-  const uint32_t* qL;
-  const uint32_t* qk;
-  uint32_t* out_cand;
-  uint32_t cand_stride;
-  uint32_t* out_counters;
-  uint64_t* out_times;
-  uint64_t* cscratch;
-  uint32_t* qcounter;
-};
-
-// The worklist is handled in super-rows of 64*B entries, B = ceil(L/64)
-// capped at kPer; inside one, lane l owns the B entries
-// [base + B*l, base + B*l + B).  L <= 256 is a single super-row.
-constexpr int kPer = 4;
-
-// Adjacency row of node u and, in the same row, the codes of its
-// neighbours: one coalesced load per lane, no dependent gather.  With a
-// host-resident adjacency only the ids are requested here (4R bytes across
-// the host link); gather_codes fetches the codes once they have arrived.
-// CODES = false (exact distances) requests the ids alone.  Every lane
-// loads (lanes past R repeat slot R-1), so no lane-dependent branch joins
-// the two forms; the caller applies row_mask once the row is in.
-template <int M, bool CODES = true>
-__device__ __forceinline__ void load_row(const SearchArgs& a, uint32_t u,
-                                         int lane, uint32_t& nb,
-                                         uint4 (&code)[M / 16]) {
-  const uint32_t l = min((uint32_t)lane, a.R - 1);
-  if (a.hadj) {
-    nb = a.hadj[(size_t)u * a.R + l];
-    return;
-  }
-  const unsigned char* row = a.rows + (size_t)u * a.row_stride;
-  nb = reinterpret_cast<const uint32_t*>(row)[l];
-  if (!CODES) return;
-  const uint4* c = reinterpret_cast<const uint4*>(row + a.row_ids + l * M);
-#pragma unroll
-  for (int i = 0; i < M / 16; ++i) code[i] = c[i];
-}
-
-// Lanes past R hold no neighbour.
-__device__ __forceinline__ uint32_t row_mask(const SearchArgs& a, int lane,
-                                             uint32_t nb) {
-  return (uint32_t)lane < a.R ? nb : kNone;
-}
-
-// Touches node u's packed row, one word per lane spread over the part that
-// load_row reads: the row comes into the caches while the current
-// neighbours are scored, so that load_row, if u is chosen, finds it there.
-// With a host-resident adjacency u's codes in device memory are touched
-// instead (no host-link traffic; the load only keeps the loads outstanding
-// the same on every path).  `touched` receives the word; the previous one
-// is consumed first, which keeps each load from being dropped.
-template <int M, bool CODES = true>
-__device__ __forceinline__ void touch_row(const SearchArgs& a, uint32_t u,
-                                          int lane, uint32_t& touched) {
-  const uint32_t bytes = a.row_ids + (CODES ? a.R * M : 0u);
-  const uint32_t step = (bytes / kWave) & ~3u;
-  const unsigned char* p =
-      a.hadj ? a.codes + (size_t)u * M
-             : a.rows + (size_t)u * a.row_stride + lane * step;
-  asm volatile("" ::"v"(touched));
-  touched = *reinterpret_cast<const uint32_t*>(p);
-}
-
-// Waves per SIMD that the table alone still lets share a CU's 160 KB of
-// LDS: the register allocator may spend up to that share, so it keeps more
-// LDS reads in flight where few waves are resident anyway.
-constexpr int max_waves_per_simd(int table_bytes) {
-  const int per_cu = (160 * 1024) / (table_bytes + 1280);
-  const int w = (per_cu + 3) / 4;
-  return w < 1 ? 1 : (w > 8 ? 8 : w);
-}
-
-// Codes of neighbour nb from the [n][m] code array in device memory (host-
-// resident adjacency only; the packed rows carry them otherwise).
-template <int M>
-__device__ __forceinline__ void gather_codes(const SearchArgs& a, uint32_t nb,
-                                             uint4 (&code)[M / 16]) {
-  if (a.hadj && nb != kNone) {
-    const uint4* c = reinterpret_cast<const uint4*>(a.codes + (size_t)nb * M);
-#pragma unroll
-    for (int i = 0; i < M / 16; ++i) code[i] = c[i];
-  }
-}
-
-template <int DT, int M, int DS, int TT>
-__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(
-    1, max_waves_per_simd(table_bytes<TT>(M)))))
-void search_kernel(SearchArgs a) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  constexpr int D = M * DS;
-  constexpr int kTableBytes = table_bytes<TT>(M);
-  constexpr bool kExact = TT == kTabExact;
-  const int lane = threadIdx.x;
-  void* T = smem;
-  float* lo = reinterpret_cast<float*>(smem + kTableBytes);  // U8 offsets
-  uint64_t* S = reinterpret_cast<uint64_t*>(smem);  // re-rank keys
-  const uint32_t B = a.lblock;
-  const uint32_t sup = kWave * B;  // super-row size
-  // the worklist (merged in place), the live new keys, and a histogram of
-  // the live keys' worklist ranks: one byte per position (a count is at
-  // most 64), added to as 32-bit words
-  uint64_t* Lc = reinterpret_cast<uint64_t*>(smem + a.region0);  // lrow
-  uint64_t* Nb = Lc + a.lrow;                                     // kWave + 4
-  uint8_t* H = reinterpret_cast<uint8_t*>(Nb + kWave + 4);        // lrow + 4
-  uint32_t* Hw = reinterpret_cast<uint32_t*>(H);
-  uint64_t* C = a.cscratch + (size_t)blockIdx.x * a.iter_cap;
-  for (uint32_t t = lane; t < (a.lrow + 4) / 4; t += kWave) Hw[t] = 0u;
-
-  for (;;) {
-    uint32_t qi = 0;
-    if (lane == 0) qi = atomicAdd(a.qcounter, 1u);
-    qi = __builtin_amdgcn_readfirstlane(qi);
-    if (qi >= a.nq) {
-      // the last workgroup out returns both counters to zero for the next
-      // launch (no reset kernel or memset on the stream)
-      if (lane == 0) {
-        __threadfence();
-        if (atomicAdd(a.qcounter + 1, 1u) == gridDim.x - 1) {
-          atomicExch(a.qcounter, 0u);
-          atomicExch(a.qcounter + 1, 0u);
-        }
-      }
-      break;
-    }
-    const unsigned char* q = a.queries + (size_t)qi * D * Elem<DT>::size;
-    const uint64_t t_begin = a.out_times ? wall_clock64() : 0;
-    // this query's worklist size, result count, iteration cap and c_max
-    uint32_t Lq = a.Lcap, kq = a.k, capq = a.iter_cap, cmq = a.c_max;
-    if (a.qL) {
-      Lq = min(max(a.qL[qi], 1u), a.Lcap);
-      capq = min(max(4u * Lq, Lq + 64u), a.iter_cap);
-      cmq = 4u * Lq;
-    }
-    if (a.qk) kq = min(max(a.qk[qi], 1u), min(a.k, Lq));
-
-    // stage 1: the table (the previous query's re-rank is done with S)
-    __syncthreads();
-    const uint32_t s = a.medoid;
-    // constant term of integer exact distances (the PQ forms compute it
-    // after the search, so the query is not held through the loop)
-    int32_t qq = 0;
-    uint4 qc = make_uint4(0u, 0u, 0u, 0u);  // this lane's query chunk
-    if constexpr (kExact) {
-      qq = query_sq<DT, D>(q);
-      if constexpr (DT != kF32) {
-        constexpr int CH = D / 16;
-        constexpr int G = CH <= 2 ? 2 : (CH <= 4 ? 4 : 8);
-        const int c = lane % G;
-        if (c < CH) qc = reinterpret_cast<const uint4*>(q)[c];
-      }
-    }
-    uint32_t nb;
-    uint4 code[M / 16];
-    load_row<M, !kExact>(a, s, lane, nb, code);  // in flight meanwhile
-    if constexpr (!kExact) build_table_q<DT, M, DS, TT>(q, a.cb, T, lo, lane);
-    __syncthreads();
-
-    // stage 2: L = [(dist(s), s)]
-    float d0;
-    if constexpr (kExact) {
-      d0 = exact_dist<DT, D>(a.base, s, q, qq);
-    } else {
-      uint4 scode[M / 16];
-#pragma unroll
-      for (int i = 0; i < M / 16; ++i)
-        scode[i] = reinterpret_cast<const uint4*>(a.codes + (size_t)s * M)[i];
-      d0 = adc_codes<M, TT>(scode);
-    }
-    uint64_t curkey = make_key(d0, s);
-    if (lane == 0) Lc[0] = curkey;
-    uint32_t Llen = 1, cur = 0, iters = 0, status = 0;
-    uint32_t touched = 0;  // result of the last touch_row (never read)
-    // the expanded keys, written to C 64 at a time: lane e holds that of
-    // expansion e mod 64 until its group of 64 is stored
-    uint64_t ckey = 0;
-    __syncthreads();
-
-    while (cur != kNone) {
-      if (iters == capq) {
-        status = 1;
-        break;
-      }
-      // expand u* = Lc[cur]: mark visited, record it as a candidate
-      if (lane == 0) Lc[cur] = curkey | 1ull;
-      if ((uint32_t)lane == (iters & (kWave - 1))) ckey = curkey;
-      if ((iters & (kWave - 1)) == kWave - 1) {
-        C[iters - (kWave - 1) + lane] = ckey;
-        // completed here: with a store outstanding among the row loads the
-        // compiler can only wait for every access, the touch below included
-        __builtin_amdgcn_s_waitcnt(kWaitVmem0);
-      }
-      ++iters;
-      const uint32_t sbase = cur / sup * sup;
-      const uint64_t last = Lc[Llen - 1];
-      // the entry after u*: every entry before u* is visited, so when this
-      // one is not, it is the first unvisited entry a (the usual case)
-      const uint64_t nx = Lc[min(cur + 1, Llen - 1)];
-      // it is usually the next node too: its row is touched below, after
-      // this row's ids are in (when nx is visited or past the end the touch
-      // is wasted, not wrong).  The previous touch was issued before this
-      // row was requested, so it is complete.
-
-      // distances of the neighbours (row of u*, loaded earlier)
-      nb = row_mask(a, lane, nb);
-      uint64_t key = kInf;
-      if constexpr (kExact && DT != kF32) {
-        touch_row<M, false>(a, key_id(nx), lane, touched);
-        const float dq = coop_dist<DT, D>(a.base, nb, qc, qq, lane);
-        key = nb != kNone ? make_key(dq, nb) : kInf;
-      } else if constexpr (kExact) {
-        touch_row<M, false>(a, key_id(nx), lane, touched);
-        if (nb != kNone)
-          key = make_key(exact_dist<DT, D, true>(a.base, nb, q, qq), nb);
-      } else {
-        gather_codes<M>(a, nb, code);
-        touch_row<M>(a, key_id(nx), lane, touched);
-        // every lane sums (no branch): an empty slot has zero codes, a lane
-        // past R reads table entries it then discards
-        const uint64_t k2 = make_key(adc_codes<M, TT>(code), nb);
-        key = nb != kNone ? k2 : kInf;
-      }
-
-      // rank in the worklist; a node already in it is dropped (set union);
-      // a key ranked past a full worklist is cut whatever the other new keys
-      // are, so only the remaining ("live") keys take part in the merge.
-      // No branch for empty slots: kInf ranks past the last entry, with no
-      // entry equal to it, and is never kept.
-      uint64_t ge;
-      const uint32_t r = rank_in(Lc, Llen, last, key, ge);
-      const bool keep = (ge >> 1) != (key >> 1) && r < Lq;
-      const uint64_t kk = keep ? key : kInf;
-
-      // next node, decided before the merge: the smaller of the first
-      // unvisited worklist entry a and the best new key b.  a is never cut
-      // when it is the smaller; b is cut when its worklist rank reaches L,
-      // and then a is cut too.  Its merged position is a's index or b's rank.
-      uint32_t apos = kNone;
-      uint64_t akey = kInf;
-      if (cur + 1 < Llen && !(nx & 1ull)) {
-        apos = cur + 1;
-        akey = nx;
-      } else {
-        // scan from the super-row holding u* (reads past Llen stay inside
-        // the buffer, which ends on a super-row boundary)
-        uint32_t ja = kNone;
-        uint64_t va = kInf;
-#pragma unroll
-        for (int t = kPer - 1; t >= 0; --t) {
-          const uint32_t j = sbase + B * lane + t;
-          if ((uint32_t)t >= B) continue;
-          const uint64_t x = Lc[j];
-          if (j < Llen && j > cur && !(x & 1ull)) {
-            ja = j;
-            va = x;
-          }
-        }
-        uint64_t am = __ballot(ja != kNone);
-        for (uint32_t base = sbase + sup; !am && base < Llen; base += sup) {
-#pragma unroll
-          for (int t = kPer - 1; t >= 0; --t) {
-            const uint32_t j = base + B * lane + t;
-            if ((uint32_t)t >= B) continue;
-            const uint64_t x = Lc[j];
-            const uint64_t v = j < Llen ? x : 1ull;
-            if (!(v & 1ull)) {
-              ja = j;
-              va = v;
-            }
-          }
-          am = __ballot(ja != kNone);
-        }
-        if (am) {
-          apos = first_of(ja, am);
-          akey = ((uint64_t)first_of((uint32_t)(va >> 32), am) << 32) |
-                 first_of((uint32_t)va, am);
-        }
-      }
-      // no live key (most expansions once the worklist is full): b does
-      // not exist and the wave minimum is skipped
-      const uint64_t km = __ballot(keep);
-      const uint64_t bkey = km ? wave_min64(kk) : kInf;
-      uint32_t best = kNone;
-      uint64_t bestkey = kInf;
-      if (bkey < akey) {
-        const uint64_t bl = __ballot(kk == bkey);
-        const uint32_t bpos = first_of(r, bl);
-        if (bpos < Lq) {
-          best = bpos;
-          bestkey = bkey;
-        }
-      } else if (akey != kInf) {
-        best = apos;
-        bestkey = akey;
-      }
-      // request the next row now; it arrives during the merge
-      if (best != kNone)
-        load_row<M, !kExact>(a, key_id(bestkey), lane, nb, code);
-      else
-        nb = kNone;
-
-      const uint32_t nv = __popcll(km);
-      if (nv == 0) {
-        // nothing enters the worklist: it keeps its order, u* is already
-        // marked, and the next node is the first unvisited entry
-        cur = best;
-        curkey = bestkey;
-        __syncthreads();
-        continue;
-      }
-      // smallest worklist rank of a live key (b's): entries below it stay
-      const uint32_t rmin = first_of(r, __ballot(kk == bkey));
-      const uint32_t idx = __builtin_amdgcn_mbcnt_hi(
-          (uint32_t)(km >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)km, 0u));
-      if (keep) {
-        Nb[idx] = kk;  // the live keys, compacted
-        atomicAdd(&Hw[r >> 2], 1u << (8 * (r & 3)));
-      }
-      if (lane < 4) Nb[nv + lane] = kInf;  // pad to a multiple of 4
-      __syncthreads();
-
-      // rank among the live keys (their count below mine)
-      uint32_t rn = 0;
-      for (uint32_t j = 0; j < nv; j += 4) {
-        const uint64_t x0 = Nb[j], x1 = Nb[j + 1], x2 = Nb[j + 2], x3 = Nb[j + 3];
-        rn += (x0 < kk) + (x1 < kk) + (x2 < kk) + (x3 < kk);
-      }
-
-      // merge: position = own index + rank in the other list.  New keys
-      // below worklist entry j = H[0] + ... + H[j] (live keys whose
-      // worklist rank is <= j): a prefix over super-rows of 64*B entries.
-      // In place: entries only move right, so the super-rows are moved from
-      // the last to the first, each read completely before it is written;
-      // the new keys go last, into the gaps.  Pass 1 gets each super-row's
-      // prefix from the histogram alone.
-      const uint32_t nsup = (Llen + sup - 1) / sup;
-      const uint32_t s0 = rmin / sup;  // first super-row with a moving entry
-      uint32_t carry_at[kPer];  // prefix before super-row s (s < 4 rows)
-      uint32_t excl_at[kPer];
-      uint32_t hb_at[kPer];     // this lane's B histogram bytes, per row
-      {
-        uint32_t carry = 0;
-#pragma unroll
-        for (int sr = 0; sr < kPer; ++sr) {
-          carry_at[sr] = carry;
-          excl_at[sr] = 0;
-          hb_at[sr] = 0;
-          if ((uint32_t)sr < nsup && (uint32_t)sr >= s0) {
-            const uint32_t base = sr * sup;
-            uint32_t tot = 0, hb = 0;
-#pragma unroll
-            for (int t = 0; t < kPer; ++t) {
-              // bytes past Llen count keys appended after every entry or
-              // are zero; they move no entry
-              if ((uint32_t)t < B) {
-                const uint32_t h = H[base + B * lane + t];
-                tot += h;
-                hb |= h << (8 * t);
-              }
-            }
-            const uint32_t excl = wave_exclusive_scan(tot);
-            excl_at[sr] = excl;
-            hb_at[sr] = hb;
-            carry += __builtin_amdgcn_readlane(excl + tot, kWave - 1);
-          }
-        }
-      }
-      for (int sr = (int)nsup - 1; sr >= (int)s0; --sr) {
-        const uint32_t base = sr * sup;
-        uint64_t v[kPer];
-#pragma unroll
-        for (int t = 0; t < kPer; ++t) {
-          const uint32_t j = base + B * lane + t;
-          v[t] = kInf;
-          if ((uint32_t)t < B) {
-            const uint64_t x = Lc[j];
-            v[t] = j < Llen ? x : kInf;
-          }
-          if (j == cur) v[t] |= 1ull;  // u*, marked visited
-        }
-        __syncthreads();  // the whole super-row is read before it moves
-        uint32_t sh = 0;
-#pragma unroll
-        for (int t = 0; t < kPer; ++t) {
-          const uint32_t j = base + B * lane + t;
-          sh += (hb_at[sr] >> (8 * t)) & 0xFFu;
-          if (v[t] != kInf) {
-            const uint32_t p = j + carry_at[sr] + excl_at[sr] + sh;
-            if (p < Lq) Lc[p] = v[t];
-          }
-        }
-      }
-      if (keep && r + rn < Lq) Lc[r + rn] = key;
-      // clear the histogram bytes used (positions rmin .. Llen)
-      for (uint32_t t = rmin / 4 + lane; t <= Llen / 4; t += kWave) Hw[t] = 0u;
-      Llen = min(Lq, Llen + nv);
-      cur = best;
-      curkey = bestkey;
-      __syncthreads();
-    }
-
-    // stage 3: re-rank the expanded nodes.  The last group of C is written
-    // out; an agent-scope fence then also drops stale L1 lines.
-    if ((iters & ~(kWave - 1u)) + lane < iters)
-      C[(iters & ~(kWave - 1u)) + lane] = ckey;
-    __threadfence();
-    __syncthreads();
-    if (a.out_counters && lane == 0) {
-      a.out_counters[qi * 4 + 0] = iters;
-      a.out_counters[qi * 4 + 1] = status;
-      a.out_counters[qi * 4 + 2] = 0;
-      a.out_counters[qi * 4 + 3] = 0;
-    }
-    if (a.out_cand)
-      for (uint32_t i = lane; i < a.cand_stride; i += kWave)
-        a.out_cand[(size_t)qi * a.cand_stride + i] =
-            i < iters ? key_id(C[i]) : kNone;
-    uint32_t nc = iters;
-    uint32_t* oid = a.out_ids + (size_t)qi * a.k;
-    float* od = a.out_dists + (size_t)qi * a.k;
-    if constexpr (kExact) {
-      // no re-rank: the worklist already ranks by exact distance
-      for (uint32_t i = lane; i < kq; i += kWave) {
-        const uint64_t key = i < Llen ? Lc[i] : kInf;
-        oid[i] = key == kInf ? kNone : key_id(key);
-        od[i] = key == kInf ? __uint_as_float(0x7F800000u) : key_dist(key);
-      }
-    } else if (qq = query_sq<DT, D>(q); pow2ceil_dev(nc) <= a.s_cap) {
-      // sort in LDS (table region + worklist buffer, free now)
-      if (nc > cmq) {
-        // keep the c_max smallest (PQ distance, id)
-        const uint32_t P = pow2ceil_dev(nc);
-        for (uint32_t i = lane; i < P; i += kWave)
-          S[i] = i < nc ? (C[i] & ~1ull) : kInf;
-        __syncthreads();
-        lds_sort(S, P, lane);
-        nc = cmq;
-      } else {
-        for (uint32_t i = lane; i < nc; i += kWave) S[i] = C[i] & ~1ull;
-      }
-      __syncthreads();
-      // exact keys; each lane also keeps the smallest of its own
-      uint64_t best = kInf;
-      uint32_t at = kNone;
-#pragma unroll 1
-      for (uint32_t i = lane; i < nc; i += kWave) {
-        const uint32_t id = key_id(S[i]);
-        const uint64_t key = make_key(exact_dist<DT, D>(a.base, id, q, qq), id);
-        S[i] = key;
-        if (key < best) {
-          best = key;
-          at = i;
-        }
-      }
-      __syncthreads();
-      if (kq <= kWave)
-        select_and_emit(S, nc, kq, best, at, oid, od, lane);
-      else
-        sort_and_emit(S, nc, kq, oid, od, lane);
-    } else {
-      // too many to sort in LDS: select in the candidate buffer itself
-      for (uint32_t i = lane; i < nc; i += kWave) C[i] &= ~1ull;
-      __threadfence();
-      __syncthreads();
-      if (nc > cmq) {
-        global_select(C, nc, cmq, lane);
-        nc = cmq;
-      }
-#pragma unroll 1
-      for (uint32_t i = lane; i < nc; i += kWave) {
-        const uint32_t id = key_id(C[i]);
-        C[i] = make_key(exact_dist<DT, D>(a.base, id, q, qq), id);
-      }
-      __threadfence();
-      __syncthreads();
-      global_select(C, nc, kq, lane);
-      for (uint32_t i = lane; i < kq; i += kWave) {
-        const uint64_t key = i < nc ? C[i] : kInf;
-        oid[i] = key == kInf ? kNone : key_id(key);
-        od[i] = key == kInf ? __uint_as_float(0x7F800000u) : key_dist(key);
-      }
-    }
-    // a row of a mixed batch holds k_q results, then padding
-    for (uint32_t i = kq + lane; i < a.k; i += kWave) {
-      oid[i] = kNone;
-      od[i] = __uint_as_float(0x7F800000u);
-    }
-    if (a.out_times && lane == 0) {
-      a.out_times[qi * 2] = t_begin;
-      a.out_times[qi * 2 + 1] = wall_clock64();
-    }
-  }
-}
 
 // Packed rows: row u = R neighbour ids (padded to row_ids bytes), then the
 // m code bytes of each neighbour slot (zero for an empty slot).
@@ -1261,96 +71,6 @@ __global__ __launch_bounds__(kWave) void rerank_kernel(
     __syncthreads();
   }
 }
-
-// ---------------------------------------------------------------------------
-// dispatch over the compiled (dtype, m, d/m) combinations
-// ---------------------------------------------------------------------------
-#define BANG_SHAPES(X) \
-  X(16, 2) X(16, 4) X(16, 8) X(32, 2) X(32, 4) X(48, 2) X(64, 2)
-
-template <template <int, int, int> class F, typename... Args>
-hipError_t dispatch(int dt, uint32_t m, uint32_t ds, Args&&... args) {
-#define BANG_CASE(MM, DD)                                                  \
-  if (m == MM && ds == DD) {                                               \
-    switch (dt) {                                                          \
-      case kF32: return F<kF32, MM, DD>::run(args...);                     \
-      case kU8: return F<kU8, MM, DD>::run(args...);                       \
-      case kI8: return F<kI8, MM, DD>::run(args...);                       \
-    }                                                                      \
-  }
-  BANG_SHAPES(BANG_CASE)
-#undef BANG_CASE
-  return hipErrorInvalidValue;
-}
-
-// Dynamic LDS above 64 KB per workgroup has to be enabled per kernel.
-template <typename K>
-hipError_t allow_lds(K kernel, size_t lds) {
-  if (lds <= 64 * 1024) return hipSuccess;
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
-                             hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)lds);
-}
-
-template <int DT, int M, int DS>
-struct RunSearch {
-  static hipError_t run(const SearchArgs& a, int table, uint32_t grid,
-                        size_t lds, hipStream_t s) {
-    switch (table) {
-      case kTabF32:
-        hipLaunchKernelGGL((search_kernel<DT, M, DS, kTabF32>), dim3(grid),
-                           dim3(kWave), lds, s, a);
-        break;
-      case kTabF16:
-        hipLaunchKernelGGL((search_kernel<DT, M, DS, kTabF16>), dim3(grid),
-                           dim3(kWave), lds, s, a);
-        break;
-      case kTabU8:
-        hipLaunchKernelGGL((search_kernel<DT, M, DS, kTabU8>), dim3(grid),
-                           dim3(kWave), lds, s, a);
-        break;
-      case kTabExact:
-        hipLaunchKernelGGL((search_kernel<DT, M, DS, kTabExact>), dim3(grid),
-                           dim3(kWave), lds, s, a);
-        break;
-      default:
-        return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-  }
-};
-
-template <typename K>
-hipError_t occupancy_of(K kernel, size_t lds, int* per_cu) {
-  // adc_codes addresses the table from LDS address 0, where the dynamic
-  // LDS block starts only while the kernel declares no static LDS
-  hipFuncAttributes fa;
-  hipError_t e = hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(kernel));
-  if (e != hipSuccess) return e;
-  if (fa.sharedSizeBytes != 0) return hipErrorInvalidKernelFile;
-  e = allow_lds(kernel, lds);
-  if (e != hipSuccess) return e;
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, kernel, kWave,
-                                                      lds);
-}
-
-// Also enables the kernel's LDS size, so it precedes every launch.
-template <int DT, int M, int DS>
-struct Occupancy {
-  static hipError_t run(int table, size_t lds, int* per_cu) {
-    switch (table) {
-      case kTabF32:
-        return occupancy_of(search_kernel<DT, M, DS, kTabF32>, lds, per_cu);
-      case kTabF16:
-        return occupancy_of(search_kernel<DT, M, DS, kTabF16>, lds, per_cu);
-      case kTabU8:
-        return occupancy_of(search_kernel<DT, M, DS, kTabU8>, lds, per_cu);
-      case kTabExact:
-        return occupancy_of(search_kernel<DT, M, DS, kTabExact>, lds, per_cu);
-    }
-    return hipErrorInvalidValue;
-  }
-};
 
 template <int DT, int M, int DS>
 struct RunTables {
@@ -1442,9 +162,16 @@ hipError_t launch_pack(const uint32_t* adj, const uint8_t* codes, uint32_t n,
   return hipGetLastError();
 }
 
-hipError_t search_occupancy(const DeviceIndex& ix, int table, size_t lds,
-                            int* per_cu) {
-  return dispatch<Occupancy>(ix.dtype, ix.m, ix.d / ix.m, table, lds, per_cu);
+hipError_t search_occupancy(const DeviceIndex& ix, int table, bool bloom,
+                            size_t lds, int* per_cu) {
+  const int dt = ix.dtype;
+  const uint32_t m = ix.m, ds = ix.d / ix.m;
+  switch ((ix.hadj ? 1 : 0) | (bloom ? 2 : 0)) {
+    case 0: return search_occupancy_v0(dt, m, ds, table, lds, per_cu);
+    case 1: return search_occupancy_v1(dt, m, ds, table, lds, per_cu);
+    case 2: return search_occupancy_v2(dt, m, ds, table, lds, per_cu);
+    default: return search_occupancy_v3(dt, m, ds, table, lds, per_cu);
+  }
 }
 
 hipError_t launch_tables(const DeviceIndex& ix, const void* queries,
@@ -1486,9 +213,17 @@ hipError_t launch_search(const DeviceIndex& ix, const SearchLaunch& l,
   a.out_counters = l.out_counters;
   a.out_times = l.out_times;
   a.cscratch = l.cscratch;
+  a.bloom = l.bloom;
+  a.bloom_epoch = l.bloom_epoch;
   a.qcounter = l.qcounter;
-  return dispatch<RunSearch>(ix.dtype, ix.m, ix.d / ix.m, a, l.table, l.grid,
-                             lds, s);
+  const int dt = ix.dtype;
+  const uint32_t m = ix.m, ds = ix.d / ix.m;
+  switch ((a.hadj ? 1 : 0) | (a.bloom ? 2 : 0)) {
+    case 0: return search_launch_v0(a, dt, m, ds, l.table, l.grid, lds, s);
+    case 1: return search_launch_v1(a, dt, m, ds, l.table, l.grid, lds, s);
+    case 2: return search_launch_v2(a, dt, m, ds, l.table, l.grid, lds, s);
+    default: return search_launch_v3(a, dt, m, ds, l.table, l.grid, lds, s);
+  }
 }
 
 hipError_t launch_rerank(const DeviceIndex& ix, const void* queries,

@@ -82,16 +82,19 @@ def f32bits(a):
 
 
 def run_and_compare(ix, gi, q, k, L, c_max=0, iter_cap=0, label="",
-                    table="f32", rerank_global=False):
+                    table="f32", rerank_global=False, filter="exact"):
     cap = iter_cap or oracle.iter_cap_for(L)
     qt = to_dev(q)
     ids, d, cand, cnt = gi.search(qt, k, L, c_max=c_max, iter_cap=iter_cap,
                                   want_cand=cap, want_counters=True,
-                                  table=table, rerank_global=rerank_global)
+                                  table=table, rerank_global=rerank_global,
+                                  filter=filter)
     torch.cuda.synchronize()
     ref = oracle.search(ix, q, k, L, c_max=c_max or None,
                         iter_cap=iter_cap or None, want_cand=True,
-                        table=table)
+                        table=table,
+                        mode=oracle.MODES["bloom" if filter == "bloom"
+                                          else "union"])
     ids, d, cand, cnt = u32(ids), d.cpu().numpy(), u32(cand), u32(cnt)
     assert np.array_equal(cnt[:, 0], ref["iters"]), label
     assert np.array_equal(cnt[:, 1], ref["status"]), label
@@ -711,3 +714,116 @@ def test_server_admission_by_memory_budget(small_indexes):
         if n == 4:
             break
     assert one is not None and 1 <= one[1] <= 4
+
+
+# --------------------------------------------------------------------------
+# the paper's Bloom filter (BANG_FILTER_BLOOM) against the oracle's
+# Algorithm 2 with the same filter (search mode 2)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("name", list(SMALL))
+@pytest.mark.parametrize("k,L,table", [(1, 1, "f32"), (10, 16, "f32"),
+                                       (5, 33, "u8"), (10, 100, "f16"),
+                                       (10, 64, "exact"),
+                                       (100, 1024, "f32")])
+def test_bloom_filter_bit_exact(small_indexes, name, k, L, table):
+    ix, q, gi = small_indexes[name]
+    run_and_compare(ix, gi, q, k, L, table=table, filter="bloom",
+                    label=f"bloom {name} k={k} L={L} {table}")
+
+
+@pytest.mark.parametrize("name", ["u8-d64-m16", "f32-d128-m16"])
+def test_bloom_filter_host_adjacency_bit_exact(small_indexes,
+                                               small_host_indexes, name):
+    ix, q, _ = small_indexes[name]
+    for k, L, table in [(10, 33, "f32"), (10, 64, "exact")]:
+        run_and_compare(ix, small_host_indexes[name], q, k, L, table=table,
+                        filter="bloom",
+                        label=f"bloom host {name} k={k} L={L} {table}")
+
+
+def test_bloom_filter_repeated_launches_stay_exact(small_indexes):
+    """Every wave keeps its filter entries across queries and launches
+    (tags carry a per-wave query epoch; the entries are cleared when the
+    epochs run out, after 4,095 queries per wave): 260 launches of 20,000
+    queries take every wave past that point, and results stay equal to
+    the oracle's."""
+    ix, q, gi = small_indexes["u8-d128-m32"]
+    reps = -(-20000 // len(q))
+    qq = np.ascontiguousarray(np.tile(q, (reps, 1))[:20000])
+    qt = to_dev(qq)
+    ref = oracle.search(ix, q, 10, 24, mode=oracle.MODES["bloom"])
+    for it in range(260):
+        ids, dist = gi.search(qt, 10, 24, filter="bloom")
+        if it % 65 == 64 or it == 0:
+            torch.cuda.synchronize()
+            got = u32(ids)
+            for r in range(0, 20000, len(q)):
+                n = min(len(q), 20000 - r)
+                assert np.array_equal(got[r:r + n], ref["ids"][:n]), (it, r)
+                assert np.array_equal(f32bits(dist.cpu().numpy()[r:r + n]),
+                                      f32bits(ref["dists"][:n])), (it, r)
+
+
+def _collision_index(row):
+    """Medoid s = 12446 whose only neighbours are `row`; node 11616's first
+    filter entry is one of s's and its second one of node 12330's."""
+    s = 12446
+    n, d = s + 1, 32
+    rng = np.random.default_rng(5)
+    base = rng.random((n, d), dtype=np.float32)
+    adj = np.full((n, 2), 0xFFFFFFFF, dtype=np.uint32)
+    adj[s, :len(row)] = row
+    cb = rng.random((16, 256, 2), dtype=np.float32)
+    codes = rng.integers(0, 256, (n, 16), dtype=np.uint8)
+    return (oracle.Index(base, adj, s, cb, codes),
+            bang_mod().Index(base, adj, s, cb, codes), base[:3].copy())
+
+
+@pytest.mark.parametrize("row,dropped", [([12330, 11616], True),
+                                         ([11616, 12330], False)])
+def test_bloom_filter_false_positive_follows_row_order(row, dropped):
+    """Row [a, y] under s: y's entries were set by s and then by a, so y
+    counts as visited and is never expanded (a false positive); row
+    [y, a]: y is tested before a sets its entry and is kept.  The exact
+    filter keeps y either way."""
+    ix, gi, q = _collision_index(row)
+    for flt in ("bloom", "exact"):
+        ids, dist, cand, cnt = gi.search(to_dev(q), 1, 8, want_cand=8,
+                                         want_counters=True, filter=flt)
+        torch.cuda.synchronize()
+        c, it = u32(cand), u32(cnt)[:, 0]
+        for i in range(len(q)):
+            got = set(c[i, :it[i]].tolist())
+            if flt == "bloom" and dropped:
+                assert got == {12446, 12330}
+            else:
+                assert got == {12446, 12330, 11616}
+        run_and_compare(ix, gi, q, 1, 8, filter=flt,
+                        label=f"collision {row} {flt}")
+    gi.close()
+
+
+def test_sift1m_bloom_filter_sampled_bit_exact():
+    """The full 10,000-query batch with the Bloom filter at the benchmark
+    point; a seeded sample recomputed by the oracle's Algorithm 2 with the
+    same filter."""
+    w, ix, d = load_workload("sift1m")
+    gi = bang_mod().Index(ix.base, ix.adj, ix.medoid, ix.codebooks, ix.codes)
+    q = d["queries"]
+    qt = to_dev(q)
+    sample = np.sort(np.random.default_rng(2026).choice(len(q), 64,
+                                                        replace=False))
+    for L, table in [(64, "f32"), (768, "f32"), (256, "exact")]:
+        cap = oracle.iter_cap_for(L)
+        ids, dist, cand, cnt = gi.search(qt, w.k, L, want_cand=cap,
+                                         want_counters=True, table=table,
+                                         filter="bloom")
+        torch.cuda.synchronize()
+        ref = oracle.search(ix, q[sample], w.k, L, want_cand=True,
+                            table=table, mode=oracle.MODES["bloom"])
+        assert np.array_equal(u32(cnt)[sample, 0], ref["iters"]), L
+        assert np.array_equal(u32(cand)[sample], ref["cand"]), L
+        assert np.array_equal(u32(ids)[sample], ref["ids"]), L
+        assert np.array_equal(f32bits(dist.cpu().numpy()[sample]),
+                              f32bits(ref["dists"])), L
+    gi.close()
