@@ -211,6 +211,22 @@ def batch_section(run, L):
             "waves_resident": "CUs x waves per CU set by the table's LDS"}
 
 
+def bloom_section(run, points):
+    """The paper's Bloom filter as the visited test (BANG_FILTER_BLOOM)
+    against the exact set union, at the given (table form, L) points:
+    QPS, recall@10 and iterations with each filter."""
+    out = {"z": 399887, "hashes": "FNV-1a-32 x2", "points": []}
+    for table, L, exact in points:
+        rec = run.measure(table, L, filter="bloom")
+        rec["vs_exact_filter"] = {
+            "qps_ratio": round(rec["qps"] / exact["qps"], 4),
+            "recall10_delta": round(rec["recall10"] - exact["recall10"], 4),
+            "iterations_delta": round(rec["mean_iterations"]
+                                      - exact["mean_iterations"], 2)}
+        out["points"].append(rec)
+    return out
+
+
 def m_section(run, bang):
     """Recall and QPS against the number m of PQ subspaces (the paper's
     compression-ratio study): the same base, graph and queries encoded with
@@ -401,7 +417,7 @@ class Runner:
         ok = [s for s in rows if s["recall10"] >= TARGET_RECALL]
         return ok[0]["L"] if ok else max(rows, key=lambda s: s["recall10"])["L"]
 
-    def measure(self, table, L, index=None):
+    def measure(self, table, L, index=None, filter="exact"):
         """K timed steps of one form; returns its record."""
         torch, w, a = self.torch, self.w, self.a
         gi_ = index or self.gi
@@ -411,14 +427,14 @@ class Runner:
         ids = torch.empty((nq, k), dtype=torch.int32, device=dev)
         dist = torch.empty((nq, k), dtype=torch.float32, device=dev)
         for _ in range(a.warmup):
-            gi_.search(q, k, L, out=(ids, dist), table=table)
+            gi_.search(q, k, L, out=(ids, dist), table=table, filter=filter)
         torch.cuda.synchronize()
         ev = [(torch.cuda.Event(enable_timing=True),
                torch.cuda.Event(enable_timing=True)) for _ in range(a.steps)]
         wall0 = time.perf_counter()
         for e0, e1 in ev:
             e0.record(stream)
-            gi_.search(q, k, L, out=(ids, dist), table=table)
+            gi_.search(q, k, L, out=(ids, dist), table=table, filter=filter)
             e1.record(stream)
         torch.cuda.synchronize()
         wall = time.perf_counter() - wall0
@@ -435,7 +451,8 @@ class Runner:
         cap = max(4 * L, L + 64)
         _, _, cand, cnt, times = gi_.search(q, k, L, want_cand=cap,
                                            want_counters=True,
-                                           want_times=True, table=table)
+                                           want_times=True, table=table,
+                                           filter=filter)
         torch.cuda.synchronize()
         cand = cand.cpu().numpy().view(np.uint32)
         iters = cnt.cpu().numpy()[:, 0]
@@ -448,7 +465,8 @@ class Runner:
         B = algorithmic_bytes(self.adj_deg, w.R, w.m, w.d, self.elem, k,
                               iters, cand, 4 * L, exact=table == "exact")
         ms_step = wall * 1e3 / a.steps
-        return {"table": table, "L": L, "recall10": round(rec, 4),
+        return {"table": table, "L": L, "filter": filter,
+                "recall10": round(rec, 4),
                 "adjacency_bytes_per_launch": int(iters.astype(np.int64).sum()
                                                   * 4 * w.R),
                 "qps": round(nq / (ms_step / 1e3), 1),
@@ -482,7 +500,8 @@ def main(argv=None):
     ap.add_argument("--no-serve", action="store_true",
                     help="skip the serving-loop measurement")
     ap.add_argument("--no-ablation", action="store_true",
-                    help="skip the batch-size and PQ-subspace studies")
+                    help="skip the batch-size, PQ-subspace and Bloom-filter "
+                         "studies")
     ap.add_argument("--no-deep", action="store_true",
                     help="skip the precision form on the d=96 float index")
     ap.add_argument("--scale-host", type=int, default=0, metavar="N",
@@ -596,6 +615,10 @@ def main(argv=None):
     if not a.no_ablation:
         out["batch_size"] = batch_section(run, L)
         out["pq_subspaces"] = m_section(run, bang)
+        pts = [("f32", L, plain)]
+        if exact is not None:
+            pts.append(("exact", exact["L"], exact))
+        out["bloom_filter"] = bloom_section(run, pts)
     if not a.no_serve:
         out["serving"] = serving_section(gi, d, w, gt)
     if not a.no_deep:
