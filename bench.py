@@ -176,6 +176,7 @@ def deep_section(a, bang, torch):
 
 
 BATCH_SIZES = (1, 10, 100, 500, 1000, 2000, 4000, 10000, 20000)
+SCALE_MIXED_NQ = 100_000
 M_SWEEP = (16, 32, 64)
 
 
@@ -293,13 +294,14 @@ def scale_host(a) -> int:
               file=sys.stderr, flush=True)
 
     log(f"generating {n:,} nodes")
-    d = synth.scale_graph_index(n)
+    d = synth.scale_graph_index(n, nq=SCALE_MIXED_NQ)
     log("index (validate, pin adjacency, upload)")
     gi = bang.Index(d["base"], d["adj"], d["medoid"], d["codebooks"],
                     d["codes"], host_adj=True)
     R = d["adj"].shape[1]
     del d["adj"]
-    q = torch.from_numpy(d["queries"]).cuda()
+    qall = torch.from_numpy(d["queries"]).cuda()
+    q = qall[:10_000]
     nq, k = q.shape[0], 10
     stream = torch.cuda.current_stream()
     rows = []
@@ -322,6 +324,35 @@ def scale_host(a) -> int:
                      "host_link_gbs": round(link, 2),
                      "host_link_frac": round(link / HOST_LINK_PEAK_GBS, 4)})
         log(f"L={L}: {rows[-1]}")
+    # one persistent launch of the 100M configuration's mixed batch: 100,000
+    # queries, k in {1, 10, 100}, L = max(k, round(exp(U[ln 16, ln 256])))
+    kq, Lq = synth.mixed_batch(SCALE_MIXED_NQ, salt=3)
+    qk = torch.from_numpy(kq.astype(np.int32)).cuda()
+    qL = torch.from_numpy(Lq.astype(np.int32)).cuda()
+    kmax, Lmax = int(kq.max()), int(Lq.max())
+    ids, dist, cnt = gi.search(qall, kmax, Lmax, query_L=qL, query_k=qk,
+                               want_counters=True)
+    torch.cuda.synchronize()
+    iters = cnt.cpu().numpy()[:, 0].astype(np.int64)
+    ev = [(torch.cuda.Event(enable_timing=True),
+           torch.cuda.Event(enable_timing=True)) for _ in range(a.steps)]
+    for e0, e1 in ev:
+        e0.record(stream)
+        gi.search(qall, kmax, Lmax, query_L=qL, query_k=qk, out=(ids, dist))
+        e1.record(stream)
+    torch.cuda.synchronize()
+    ms = float(np.mean([e0.elapsed_time(e1) for e0, e1 in ev]))
+    link = iters.sum() * 4 * R / (ms / 1e3) / 1e9
+    mixed = {"queries": SCALE_MIXED_NQ, "k": "uniform over {1, 10, 100}",
+             "L": "max(k, round(exp(U[ln 16, ln 256])))",
+             "mean_L": round(float(Lq.mean()), 1),
+             "qps": round(SCALE_MIXED_NQ / (ms / 1e3), 1),
+             "kernel_ms_mean": round(ms, 3),
+             "mean_iterations": round(float(iters.mean()), 2),
+             "host_link_gbs": round(link, 2),
+             "host_link_frac": round(link / HOST_LINK_PEAK_GBS, 4)}
+    log(f"mixed batch: {mixed}")
+    del ids, dist, cnt
     # the serving loop on the same host-resident index (configuration 4's
     # request recipe; results are not checked here, recall is undefined)
     from paper_2401_11324_amd import serving
@@ -330,8 +361,8 @@ def scale_host(a) -> int:
     for i, rate in enumerate(SERVE_RATES):
         req = synth.serving_requests(w, rate, min(1.0, 2e5 / rate),
                                      salt=20 + i)
-        sm, _, _ = serving.run_load(gi, d["queries"], req, 16384, 2, 100,
-                                    128)
+        sm, _, _ = serving.run_load(gi, d["queries"][:nq], req, 16384, 2,
+                                    100, 128)
         serve.append(sm)
         log(f"serving {rate:.0e}: {sm}")
     gi.close()
@@ -340,7 +371,7 @@ def scale_host(a) -> int:
                     f"row spread over the range (no locality), PQ m=32; "
                     f"adjacency {n * R * 4 / 1e9:.1f} GB in pinned host "
                     f"memory; {nq:,} queries",
-        "steps": a.steps, "rows": rows,
+        "steps": a.steps, "rows": rows, "mixed_batch": mixed,
         "host_link_peak_gbs": HOST_LINK_PEAK_GBS,
         "serving": {"max_batch": 16384, "slots": 2,
                     "requests": "sizes log-uniform 1-256 queries, k in "

@@ -175,6 +175,18 @@ def serving_requests(w: Workload, rate_qps: float, duration_s: float,
     return {"nq": nq, "k": k, "L": L, "arrival_s": arrival, "rows": rows}
 
 
+def mixed_batch(nq: int, salt: int = 0, ks=(1, 10, 100), L_lo: int = 16,
+                L_hi: int = 256):
+    """Per-query k and L of a mixed batch (the 100M configuration's query
+    recipe): k uniform over `ks`, L = max(k, round(exp(U[ln L_lo,
+    ln L_hi]))).  Seeded by salt.  Returns (k uint32[nq], L uint32[nq])."""
+    rng = np.random.default_rng(np.random.SeedSequence([SEED_BASE, 77,
+                                                        int(salt)]))
+    k = rng.choice(np.asarray(ks), nq).astype(np.uint32)
+    L = np.rint(np.exp(rng.uniform(np.log(L_lo), np.log(L_hi), nq)))
+    return k, np.maximum(L.astype(np.uint32), k)
+
+
 def scale_graph_index(n: int, d: int = 128, R: int = 64, m: int = 32,
                       nq: int = 10_000, seed: int = 240111324,
                       chunk: int = 1 << 20):

@@ -88,3 +88,19 @@ def test_extra_arrays_roundtrip_and_checks(tmp_path):
     # the index itself is untouched by the extra arrays
     assert np.array_equal(store.load(w, root=str(tmp_path), with_base=False)
                           ["codes"], arrays["codes"])
+
+
+def test_mixed_batch_recipe():
+    """The 100M configuration's query mix: k uniform over {1, 10, 100},
+    L = max(k, round(exp(U[ln 16, ln 256]))); seeded."""
+    k, L = synth.mixed_batch(60_000, salt=3)
+    k2, L2 = synth.mixed_batch(60_000, salt=3)
+    assert np.array_equal(k, k2) and np.array_equal(L, L2)
+    assert set(np.unique(k).tolist()) == {1, 10, 100}
+    assert (L >= k).all() and L.min() >= 16 and L.max() <= 256
+    # each k about a third; log L about uniform on [ln 16, ln 256]
+    for v in (1, 10, 100):
+        assert abs((k == v).mean() - 1 / 3) < 0.01
+    lo = L[k < 16]  # not raised to k
+    med = np.median(np.log(lo))
+    assert abs(med - 0.5 * (np.log(16) + np.log(256))) < 0.05
