@@ -212,6 +212,25 @@ def batch_section(run, L):
             "waves_resident": "CUs x waves per CU set by the table's LDS"}
 
 
+def gather_probe(gi, torch, nreads, reps=3):
+    """Random-row read rate of the index's adjacency (bang_index_probe):
+    rows read the way the search reads an expanded node's row, as many in
+    flight as 32 waves per CU allow.  Returns {row_bytes, reads, gbs}."""
+    stream = torch.cuda.current_stream()
+    gi.probe(nreads, seed=1)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for i in range(reps):
+        rb = gi.probe(nreads, seed=2 + i)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    return {"row_bytes": rb, "reads": nreads,
+            "gbs": round(nreads * rb / (ms / 1e3) / 1e9, 2)}
+
+
 def bloom_section(run, points):
     """The paper's Bloom filter as the visited test (BANG_FILTER_BLOOM)
     against the exact set union, at the given (table form, L) points:
@@ -585,6 +604,7 @@ def main(argv=None):
         hi = bang.Index(d["base"], d["adj"], d["medoid"], d["codebooks"],
                         d["codes"], host_adj=True)
         host = measure("f32", L, index=hi)
+        hprobe = gather_probe(hi, torch, 1 << 20)
         hi.close()
         link = host["adjacency_bytes_per_launch"] / (
             host["kernel_ms_mean"] / 1e3) / 1e9
@@ -592,7 +612,12 @@ def main(argv=None):
             "bound": "host link", "achieved": round(link, 2),
             "peak": HOST_LINK_PEAK_GBS, "unit": "GB/s",
             "frac": round(link / HOST_LINK_PEAK_GBS, 4),
-            "bytes": "adjacency rows, 4R bytes per expansion"}
+            "bytes": "adjacency rows, 4R bytes per expansion",
+            "random_row_probe": hprobe,
+            "frac_of_probe": round(link / hprobe["gbs"], 4)}
+    # the rate at which random packed rows can be read at all (the search's
+    # access pattern with no work between reads)
+    probe = gather_probe(gi, torch, 1 << 22)
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as f:
@@ -638,6 +663,7 @@ def main(argv=None):
             "algorithmic_bytes_per_launch":
                 plain["algorithmic_bytes_per_launch"],
             "kernel_ms_mean": plain["kernel_ms_mean"],
+            "random_row_probe": probe,
         },
         "precision_form": prec,
     }

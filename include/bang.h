@@ -199,6 +199,18 @@ int bang_rerank(bang_index* index, const void* queries, uint64_t nq,
                 const uint32_t* cand, uint32_t c_max, uint32_t k,
                 uint32_t* out_ids, float* out_dists, void* stream);
 
+/* Roofline probe: reads nreads adjacency rows of the index, row i of the
+ * sequence being splitmix64(seed + i) mod n, each the way the search reads
+ * an expanded node's row: with the adjacency in device memory the packed
+ * row's ids and codes (row_ids + R*m bytes, 16-byte loads), with a
+ * host-resident adjacency the R ids across the host link (4-byte loads).
+ * One wave per row, 32 waves per CU.  Nothing is computed from the data;
+ * the bytes read per row go to *row_bytes_out (may be NULL), and the
+ * caller times the launch on `stream`.  sink: device pointer to 8 bytes
+ * the kernel may write.  Errors: EINVAL, EDEVICE. */
+int bang_index_probe(bang_index* index, uint64_t nreads, uint64_t seed,
+                     uint64_t* sink, uint32_t* row_bytes_out, void* stream);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char* bang_last_error(void);
 

@@ -28,7 +28,8 @@ FILTERS = {"exact": 0, "bloom": 1}
 ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EUNSUPPORTED",
           -5: "EABORTED"}
 EXPORTS = ("bang_index_create", "bang_index_destroy", "bang_build_pq_tables",
-           "bang_search", "bang_rerank", "bang_server_create",
+           "bang_search", "bang_rerank", "bang_index_probe",
+           "bang_server_create",
            "bang_server_destroy", "bang_server_submit", "bang_server_wait",
            "bang_server_replay", "bang_server_stats", "bang_last_error")
 
@@ -85,6 +86,7 @@ def lib():
         L.bang_search.argtypes = [P, P, u64, u32, u32, P, P,
                                   ctypes.POINTER(SearchOpts), P]
         L.bang_rerank.argtypes = [P, P, u64, P, u32, u32, P, P, P]
+        L.bang_index_probe.argtypes = [P, u64, u64, P, ctypes.POINTER(u32), P]
         L.bang_server_create.argtypes = [P, ctypes.POINTER(ServerOpts),
                                          ctypes.POINTER(P)]
         L.bang_server_destroy.argtypes = [P]
@@ -148,6 +150,7 @@ class Index:
     def __init__(self, base, adj, medoid, codebooks, codes,
                  host_adj: bool = False):
         self._h = None
+        self._sink = None  # device word the probe kernel may write
         base = np.ascontiguousarray(base)
         adj = np.ascontiguousarray(adj, dtype=np.uint32)
         cb = np.ascontiguousarray(codebooks, dtype=np.float32)
@@ -263,6 +266,20 @@ class Index:
         if want_times:
             res += (times,)
         return res
+
+    def probe(self, nreads: int, seed: int = 0, stream=None) -> int:
+        """Launch the random-row read probe (bang_index_probe) on `stream`
+        (default: torch's current stream): nreads adjacency rows read the
+        way the search reads them.  Returns the bytes read per row; the
+        caller times the launch."""
+        import torch
+        if self._sink is None:
+            self._sink = torch.zeros(1, dtype=torch.int64, device="cuda")
+        rb = ctypes.c_uint32(0)
+        _check(lib().bang_index_probe(self._h, nreads, seed,
+                                      self._sink.data_ptr(),
+                                      ctypes.byref(rb), _stream(stream)))
+        return int(rb.value)
 
     def rerank(self, q, cand, k: int, out=None, stream=None):
         """Stage 3 alone over cand [nq][c_max] (int32 view of uint32 ids;

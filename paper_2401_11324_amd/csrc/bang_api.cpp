@@ -501,6 +501,26 @@ int bang_rerank(bang_index* ix, const void* queries, uint64_t nq,
   }
 }
 
+int bang_index_probe(bang_index* ix, uint64_t nreads, uint64_t seed,
+                     uint64_t* sink, uint32_t* row_bytes_out, void* stream) {
+  try {
+    if (!ix) return fail(BANG_EINVAL, "null index");
+    if (!sink || !aligned(sink, 8))
+      return fail(BANG_EINVAL, "sink null or not 8-byte aligned");
+    hipError_t e = hipSetDevice(ix->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    uint32_t rb = 0;
+    e = bang::launch_probe(ix->dev, nreads, seed, sink,
+                           (uint32_t)ix->num_cus * 8u, &rb,
+                           static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "probe launch");
+    if (row_bytes_out) *row_bytes_out = rb;
+    return BANG_OK;
+  } catch (...) {
+    return fail(BANG_ENOMEM, "exception");
+  }
+}
+
 const char* bang_last_error(void) { return bang::last_error(); }
 
 }  // extern "C"

@@ -97,6 +97,45 @@ struct RunRerank {
   }
 };
 
+// splitmix64 (Steele, Lea and Flood; the finaliser of Vigna's generator):
+// a counter-based source of uniform 64-bit values.
+__device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
+  uint64_t z = x + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ uint32_t fold(uint4 v) {
+  return v.x ^ v.y ^ v.z ^ v.w;
+}
+__device__ __forceinline__ uint32_t fold(uint32_t v) { return v; }
+
+// Reads nreads random rows of `words` W-words (row r at src + r * stride):
+// one wave per row, every lane a word (up to 8 words per lane).  The xor of
+// the data decides a store that practically never happens, which keeps
+// every load.
+template <typename W>
+__global__ __launch_bounds__(256) void probe_kernel(
+    const unsigned char* __restrict__ src, uint64_t rows, uint32_t stride,
+    uint32_t words, uint64_t nreads, uint64_t seed, uint64_t* sink) {
+  const uint32_t lane = threadIdx.x % kWave;
+  const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) /
+                        kWave;
+  const uint64_t nw = (uint64_t)gridDim.x * blockDim.x / kWave;
+  uint32_t acc = 0;
+  for (uint64_t i = wave; i < nreads; i += nw) {
+    const uint64_t r = splitmix64(seed + i) % rows;
+    const W* p = reinterpret_cast<const W*>(src + r * stride);
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const uint32_t c = lane + (uint32_t)t * kWave;
+      if (c < words) acc ^= fold(p[c]);
+    }
+  }
+  if (acc == 0x2545F491u) sink[0] = wave;
+}
+
 }  // namespace
 
 uint32_t pow2ceil(uint32_t x) {
@@ -224,6 +263,27 @@ hipError_t launch_search(const DeviceIndex& ix, const SearchLaunch& l,
     case 2: return search_launch_v2(a, dt, m, ds, l.table, l.grid, lds, s);
     default: return search_launch_v3(a, dt, m, ds, l.table, l.grid, lds, s);
   }
+}
+
+hipError_t launch_probe(const DeviceIndex& ix, uint64_t nreads, uint64_t seed,
+                        uint64_t* sink, uint32_t grid, uint32_t* row_bytes,
+                        hipStream_t s) {
+  if (ix.hadj) {
+    // the R ids of a row, as load_row reads them across the host link
+    *row_bytes = 4 * ix.R;
+    if (nreads == 0) return hipSuccess;
+    hipLaunchKernelGGL(probe_kernel<uint32_t>, dim3(grid), dim3(256), 0, s,
+                       reinterpret_cast<const unsigned char*>(ix.hadj),
+                       (uint64_t)ix.n, 4 * ix.R, ix.R, nreads, seed, sink);
+  } else {
+    const uint32_t bytes = (row_ids_bytes(ix.R) + ix.R * ix.m + 15) / 16 * 16;
+    *row_bytes = bytes;
+    if (nreads == 0) return hipSuccess;
+    hipLaunchKernelGGL(probe_kernel<uint4>, dim3(grid), dim3(256), 0, s,
+                       ix.rows, (uint64_t)ix.n, row_stride_bytes(ix.R, ix.m),
+                       bytes / 16, nreads, seed, sink);
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_rerank(const DeviceIndex& ix, const void* queries,

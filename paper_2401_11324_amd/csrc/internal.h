@@ -67,6 +67,12 @@ hipError_t launch_tables(const DeviceIndex& ix, const void* queries,
                          uint64_t nq, float* out, hipStream_t s);
 hipError_t launch_search(const DeviceIndex& ix, const SearchLaunch& a,
                          hipStream_t s);
+// Random-row read probe over the index's adjacency (bang_index_probe);
+// row_bytes receives the bytes read per row.
+hipError_t launch_probe(const DeviceIndex& ix, uint64_t nreads, uint64_t seed,
+                        uint64_t* sink, uint32_t grid, uint32_t* row_bytes,
+                        hipStream_t s);
+
 hipError_t launch_rerank(const DeviceIndex& ix, const void* queries,
                          uint64_t nq, const uint32_t* cand, uint32_t c_max,
                          uint32_t k, uint32_t* out_ids, float* out_dists,

@@ -827,3 +827,24 @@ def test_sift1m_bloom_filter_sampled_bit_exact():
         assert np.array_equal(f32bits(dist.cpu().numpy()[sample]),
                               f32bits(ref["dists"])), L
     gi.close()
+
+
+# --------------------------------------------------------------------------
+# roofline probe (bang_index_probe)
+# --------------------------------------------------------------------------
+def test_index_probe_reads_rows(small_indexes, small_host_indexes):
+    """The probe runs on both adjacency placements, reports the bytes the
+    search reads per row, accepts nreads = 0 and rejects a null sink."""
+    import ctypes
+    bang = bang_mod()
+    ix, q, gi = small_indexes["u8-d128-m32"]
+    hi = small_host_indexes["u8-d64-m16"]
+    assert gi.probe(0) == (ix.R * 4 + 15) // 16 * 16 + ix.R * ix.m
+    assert gi.probe(100_000, seed=3) == (ix.R * 4 + 15) // 16 * 16 + \
+        ix.R * ix.m
+    assert hi.probe(50_000) == 4 * small_indexes["u8-d64-m16"][0].R
+    torch.cuda.synchronize()
+    rb = ctypes.c_uint32(0)
+    rc = bang.lib().bang_index_probe(gi._h, 10, 0, None, ctypes.byref(rb),
+                                     None)
+    assert rc == -1
