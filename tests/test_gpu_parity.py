@@ -848,3 +848,26 @@ def test_index_probe_reads_rows(small_indexes, small_host_indexes):
     rc = bang.lib().bang_index_probe(gi._h, 10, 0, None, ctypes.byref(rb),
                                      None)
     assert rc == -1
+
+
+@pytest.mark.parametrize("name", ["u8-d128-m32", "f32-d128-m16"])
+def test_bloom_filter_mixed_batch_equals_oracle(small_indexes, name):
+    """A mixed batch (per-query k and L) with the Bloom filter: every query
+    equals the oracle's Algorithm 2 with the same filter at its own (k, L),
+    whatever wave and filter epoch it ran in."""
+    ix, q, gi = small_indexes[name]
+    rng = np.random.default_rng(8)
+    nq = len(q)
+    Ls = rng.choice([1, 12, 40, 128], nq).astype(np.int32)
+    ks = np.array([rng.integers(1, min(16, L) + 1) for L in Ls], np.int32)
+    kmax, Lmax = int(ks.max()), int(Ls.max())
+    ids, d = gi.search(to_dev(q), kmax, Lmax, filter="bloom",
+                       query_L=to_dev(Ls), query_k=to_dev(ks))
+    torch.cuda.synchronize()
+    ids, d = u32(ids), d.cpu().numpy()
+    for (k, L) in sorted(set(zip(ks.tolist(), Ls.tolist()))):
+        sel = np.where((ks == k) & (Ls == L))[0]
+        ref = oracle.search(ix, q[sel], k, L, mode=oracle.MODES["bloom"])
+        assert np.array_equal(ids[sel, :k], ref["ids"]), (k, L)
+        assert np.array_equal(f32bits(d[sel, :k]), f32bits(ref["dists"])), \
+            (k, L)
