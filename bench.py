@@ -231,6 +231,47 @@ def gather_probe(gi, torch, nreads, reps=3):
             "gbs": round(nreads * rb / (ms / 1e3) / 1e9, 2)}
 
 
+PHASES = ("table_and_start", "row_wait", "scoring", "rank", "next_node",
+          "merge", "rerank")
+
+
+def phase_section(run, points):
+    """Where a query's time goes (the fused kernel's counterpart of the
+    paper's per-kernel time table): one launch of the timed copy of the
+    search (bang_search_opts.out_phases) per (table form, L) point.  Cycles
+    are per query for the table and the re-rank, per expansion for the
+    loop's phases, and each phase's share of all cycles."""
+    torch, q, k = run.torch, run.q, run.w.k
+    stream = torch.cuda.current_stream()
+    out = []
+    for table, L in points:
+        ids, dist, cnt, ph = run.gi.search(q, k, L, table=table,
+                                           want_counters=True,
+                                           want_phases=True)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        run.gi.search(q, k, L, table=table, want_phases=True)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        c = ph.cpu().numpy().view(np.uint32).astype(np.float64)
+        it = float(cnt.cpu().numpy()[:, 0].astype(np.float64).sum())
+        tot = c.sum(0)
+        rec = {"table": table, "L": L,
+               "timed_kernel_ms": round(e0.elapsed_time(e1), 3),
+               "share": {n: round(float(v / tot.sum()), 4)
+                         for n, v in zip(PHASES, tot)},
+               "cycles_per_query": {n: round(float(tot[i] / len(c)), 1)
+                                    for i, n in enumerate(PHASES)
+                                    if n in ("table_and_start", "rerank")},
+               "cycles_per_expansion": {n: round(float(tot[i] / it), 1)
+                                        for i, n in enumerate(PHASES)
+                                        if n not in ("table_and_start",
+                                                     "rerank")}}
+        out.append(rec)
+    return out
+
+
 def bloom_section(run, points):
     """The paper's Bloom filter as the visited test (BANG_FILTER_BLOOM)
     against the exact set union, at the given (table form, L) points:
@@ -676,6 +717,9 @@ def main(argv=None):
         if exact is not None:
             pts.append(("exact", exact["L"], exact))
         out["bloom_filter"] = bloom_section(run, pts)
+        out["phase_split"] = phase_section(
+            run, [("f32", L), ("u8", prec["u8"]["L"])] +
+            ([("exact", exact["L"])] if exact is not None else []))
     if not a.no_serve:
         out["serving"] = serving_section(gi, d, w, gt)
     if not a.no_deep:

@@ -114,6 +114,16 @@ typedef struct {
   const uint32_t* query_k;  /* device [nq] or NULL (every k_i = k) */
   uint32_t filter;          /* visited filter: BANG_FILTER_EXACT (default)
                                or BANG_FILTER_BLOOM */
+  uint32_t* out_phases;     /* device [nq][7] or NULL: shader-clock cycles
+                               (s_memtime) of each query's phases: table and
+                               worklist start; then summed over expansions:
+                               waiting for the row, scoring the neighbours,
+                               ranking them in the worklist, choosing the
+                               next node and requesting its row, merging;
+                               then the re-rank.  Runs a timed copy of the
+                               search (same results, somewhat slower);
+                               device-resident adjacency and the exact
+                               filter only (EUNSUPPORTED otherwise). */
 } bang_search_opts;
 
 /* Visited filters.

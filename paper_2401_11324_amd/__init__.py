@@ -56,7 +56,7 @@ class SearchOpts(ctypes.Structure):
                 ("out_times", ctypes.c_void_p),
                 ("table", ctypes.c_uint32), ("flags", ctypes.c_uint32),
                 ("query_L", ctypes.c_void_p), ("query_k", ctypes.c_void_p),
-                ("filter", ctypes.c_uint32)]
+                ("filter", ctypes.c_uint32), ("out_phases", ctypes.c_void_p)]
 
 
 class ServerOpts(ctypes.Structure):
@@ -213,7 +213,8 @@ class Index:
                want_cand: int = 0, want_counters: bool = False,
                want_times: bool = False, table: str = "f32",
                rerank_global: bool = False, query_L=None, query_k=None,
-               filter: str = "exact", out=None, stream=None):
+               filter: str = "exact", want_phases: bool = False, out=None,
+               stream=None):
         """Stages 1-3.  Returns (ids uint32-as-int32 [nq][k], dists
         float32 [nq][k]) and, on request, the expanded nodes [nq][want_cand]
         `table` is the PQ table storage the search ranks by: "f32", the
@@ -224,7 +225,9 @@ class Index:
         and counters [nq][4] (iterations, status) and device wall-clock
         ticks [nq][2] (begin, end).  `filter` is the visited filter:
         "exact" (set union, the default) or "bloom" (the paper's Bloom
-        filter, BANG_FILTER_BLOOM)."""
+        filter, BANG_FILTER_BLOOM).  want_phases adds per-query cycles of
+        the search's seven phases [nq][7] (bang_search_opts.out_phases;
+        a timed copy of the search)."""
         import torch
         qp = self._queries(q)
         nq = q.shape[0]
@@ -254,6 +257,10 @@ class Index:
         if want_times:
             times = torch.empty((nq, 2), dtype=torch.int64, device=q.device)
             opts.out_times = times.data_ptr()
+        phases = None
+        if want_phases:
+            phases = torch.empty((nq, 7), dtype=torch.int32, device=q.device)
+            opts.out_phases = phases.data_ptr()
         _check(lib().bang_search(
             self._h, qp, nq, k, L, _dev_ptr(ids, torch.int32, "ids"),
             _dev_ptr(dists, torch.float32, "dists"), ctypes.byref(opts),
@@ -265,6 +272,8 @@ class Index:
             res += (cnt,)
         if want_times:
             res += (times,)
+        if want_phases:
+            res += (phases,)
         return res
 
     def probe(self, nreads: int, seed: int = 0, stream=None) -> int:

@@ -271,7 +271,8 @@ int check_queries(const bang_index* ix, const void* queries) {
 
 // Launch geometry of a search: LDS bytes and resident workgroups.
 int search_geometry(bang_index* ix, uint64_t nq, uint32_t L, uint32_t iter_cap,
-                    uint32_t table, bool bloom, size_t* lds, uint64_t* grid) {
+                    uint32_t table, bool bloom, bool phases, size_t* lds,
+                    uint64_t* grid) {
   *lds = bang::search_lds_bytes(ix->dev.m, L, iter_cap, (int)table);
   hipError_t e = hipSetDevice(ix->device);
   if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
@@ -281,7 +282,8 @@ int search_geometry(bang_index* ix, uint64_t nq, uint32_t L, uint32_t iter_cap,
                     " bytes of LDS, the device allows " +
                     std::to_string(ix->max_lds) + " (lower L or iter_cap)");
   int per_cu = 0;
-  e = bang::search_occupancy(ix->dev, (int)table, bloom, *lds, &per_cu);
+  e = bang::search_occupancy(ix->dev, (int)table, bloom, phases, *lds,
+                             &per_cu);
   if (e != hipSuccess) return hip_fail(e, "occupancy query");
   if (per_cu < 1) return fail(BANG_EUNSUPPORTED, "search kernel cannot be resident");
   *grid = std::min<uint64_t>((uint64_t)per_cu * ix->num_cus, nq);
@@ -296,7 +298,7 @@ size_t search_workspace_bytes(bang_index* ix, uint64_t nq, uint32_t L,
                               uint32_t iter_cap, uint32_t table) {
   size_t lds;
   uint64_t grid;
-  if (search_geometry(ix, nq, L, iter_cap, table, false, &lds, &grid))
+  if (search_geometry(ix, nq, L, iter_cap, table, false, false, &lds, &grid))
     return 0;
   return (size_t)grid * iter_cap * sizeof(uint64_t);
 }
@@ -339,8 +341,16 @@ int search_with(bang_index* ix, Workspace* ws, bool grow, const void* queries,
 
   size_t lds;
   uint64_t grid;
+  uint32_t* const phases = o ? o->out_phases : nullptr;
+  if (phases && (ix->dev.hadj || filter == BANG_FILTER_BLOOM))
+    return fail(BANG_EUNSUPPORTED,
+                "out_phases: the timed search has the device-resident "
+                "adjacency and the exact filter only");
+  if (phases && !aligned(phases, 4))
+    return fail(BANG_EINVAL, "out_phases not 4-byte aligned");
   rc = search_geometry(ix, nq, L, iter_cap, table,
-                       filter == BANG_FILTER_BLOOM, &lds, &grid);
+                       filter == BANG_FILTER_BLOOM, phases != nullptr, &lds,
+                       &grid);
   if (rc) return rc;
   size_t need = (size_t)grid * iter_cap * sizeof(uint64_t);
   if (need > ws->cscratch_bytes) {
@@ -410,6 +420,7 @@ int search_with(bang_index* ix, Workspace* ws, bool grow, const void* queries,
   l.cand_stride = o ? o->cand_stride : 0;
   l.out_counters = o ? o->out_counters : nullptr;
   l.out_times = o ? o->out_times : nullptr;
+  l.out_phases = phases;
   l.cscratch = ws->cscratch;
   l.qcounter = ws->qcounter;
   l.bloom = filter == BANG_FILTER_BLOOM ? ws->bloom : nullptr;

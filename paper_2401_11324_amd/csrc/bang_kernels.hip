@@ -202,9 +202,10 @@ hipError_t launch_pack(const uint32_t* adj, const uint8_t* codes, uint32_t n,
 }
 
 hipError_t search_occupancy(const DeviceIndex& ix, int table, bool bloom,
-                            size_t lds, int* per_cu) {
+                            bool phases, size_t lds, int* per_cu) {
   const int dt = ix.dtype;
   const uint32_t m = ix.m, ds = ix.d / ix.m;
+  if (phases) return search_occupancy_v4(dt, m, ds, table, lds, per_cu);
   switch ((ix.hadj ? 1 : 0) | (bloom ? 2 : 0)) {
     case 0: return search_occupancy_v0(dt, m, ds, table, lds, per_cu);
     case 1: return search_occupancy_v1(dt, m, ds, table, lds, per_cu);
@@ -251,12 +252,15 @@ hipError_t launch_search(const DeviceIndex& ix, const SearchLaunch& l,
   a.cand_stride = l.cand_stride;
   a.out_counters = l.out_counters;
   a.out_times = l.out_times;
+  a.out_phases = l.out_phases;
   a.cscratch = l.cscratch;
   a.bloom = l.bloom;
   a.bloom_epoch = l.bloom_epoch;
   a.qcounter = l.qcounter;
   const int dt = ix.dtype;
   const uint32_t m = ix.m, ds = ix.d / ix.m;
+  if (a.out_phases)
+    return search_launch_v4(a, dt, m, ds, l.table, l.grid, lds, s);
   switch ((a.hadj ? 1 : 0) | (a.bloom ? 2 : 0)) {
     case 0: return search_launch_v0(a, dt, m, ds, l.table, l.grid, lds, s);
     case 1: return search_launch_v1(a, dt, m, ds, l.table, l.grid, lds, s);

@@ -39,6 +39,7 @@ struct SearchLaunch {
   uint64_t* cscratch;    // [grid][iter_cap] expanded-node keys
   uint32_t* qcounter;    // [2]: next query, finished workgroups; zero
                          // between launches (the kernel resets them)
+  uint32_t* out_phases;  // [nq][7] per-phase cycles (timed variant) or null
   uint32_t* bloom;       // null (exact filter) or [grid][BANG_BLOOM_Z]
   uint32_t* bloom_epoch; // [grid] query epoch of each wave's filter
   uint32_t grid;         // workgroups (one wave each)
@@ -59,9 +60,9 @@ hipError_t launch_pack(const uint32_t* adj, const uint8_t* codes, uint32_t n,
                        hipStream_t s);
 
 // Resident workgroups per CU for the search kernel variant (adjacency
-// placement of ix, visited filter) at this LDS size.
+// placement of ix, visited filter, timed) at this LDS size.
 hipError_t search_occupancy(const DeviceIndex& ix, int table, bool bloom,
-                            size_t lds, int* per_cu);
+                            bool phases, size_t lds, int* per_cu);
 
 hipError_t launch_tables(const DeviceIndex& ix, const void* queries,
                          uint64_t nq, float* out, hipStream_t s);

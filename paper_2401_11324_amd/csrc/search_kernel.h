@@ -711,6 +711,7 @@ struct SearchArgs {
   uint32_t cand_stride;
   uint32_t* out_counters;
   uint64_t* out_times;
+  uint32_t* out_phases;  // [nq][kPhases] (the timed variant only)
   uint64_t* cscratch;
   uint32_t* qcounter;
   uint32_t* bloom;        // null, or [grid][kBloomZ] filter entries
@@ -849,12 +850,24 @@ __device__ __forceinline__ void gather_codes(const SearchArgs& a, uint32_t nb,
   }
 }
 
+// Phases of a query that the timed variant reports (out_phases), in
+// shader-clock cycles (s_memtime): the table and the worklist's start, then
+// summed over the expansions: waiting for the row, scoring the neighbours,
+// ranking them in the worklist (with the visited test), choosing the next
+// node and requesting its row, merging; then the re-rank.
+constexpr int kPhases = 7;
+
+__device__ __forceinline__ uint64_t phase_clock() {
+  return __builtin_amdgcn_s_memtime();
+}
+
 // HOST: adjacency rows in pinned host memory (a.hadj), the codes gathered
 // from device memory.  BLOOM: the paper's Bloom filter as the visited test
 // (a.bloom) in addition to the set union.  Each is its own instantiation,
 // so that no form's extra loads and atomics change where the others wait
-// for memory.
-template <int DT, int M, int DS, int TT, bool HOST, bool BLOOM>
+// for memory.  PHASES: the timed variant, which adds up shader-clock cycles
+// per phase of each query (out_phases) and is otherwise the same search.
+template <int DT, int M, int DS, int TT, bool HOST, bool BLOOM, bool PHASES>
 __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(
     1, max_waves_per_simd(table_bytes<TT>(M)))))
 void search_kernel(SearchArgs a) {
@@ -896,6 +909,8 @@ void search_kernel(SearchArgs a) {
     }
     const unsigned char* q = a.queries + (size_t)qi * D * Elem<DT>::size;
     const uint64_t t_begin = a.out_times ? wall_clock64() : 0;
+    uint64_t ph[kPhases] = {0, 0, 0, 0, 0, 0, 0};
+    uint64_t tp = PHASES ? phase_clock() : 0, t4 = 0;
     // this query's worklist size, result count, iteration cap and c_max
     uint32_t Lq = a.Lcap, kq = a.k, capq = a.iter_cap, cmq = a.c_max;
     if (a.qL) {
@@ -972,11 +987,16 @@ void search_kernel(SearchArgs a) {
     uint64_t ckey = 0;
     __syncthreads();
 
+    if constexpr (PHASES) {
+      const uint64_t t = phase_clock();
+      ph[0] = t - tp;
+    }
     while (cur != kNone) {
       if (iters == capq) {
         status = 1;
         break;
       }
+      if constexpr (PHASES) tp = phase_clock();
       // expand u* = Lc[cur]: mark visited, record it as a candidate
       if (lane == 0) Lc[cur] = curkey | 1ull;
       if ((uint32_t)lane == (iters & (kWave - 1))) ckey = curkey;
@@ -1000,6 +1020,12 @@ void search_kernel(SearchArgs a) {
       // distances of the neighbours (row of u*, loaded earlier)
       nb = row_mask(a, lane, nb);
       keep_alive(touched);
+      if constexpr (PHASES) {
+        keep_alive(nb);
+        const uint64_t t = phase_clock();
+        ph[1] += t - tp;
+        tp = t;
+      }
       // Bloom filter: both entries of each neighbour are updated with this
       // lane's tag below (after any code gather, so that the scoring waits
       // for neither); the previous values are used after the scoring
@@ -1033,6 +1059,12 @@ void search_kernel(SearchArgs a) {
         key = nb != kNone ? k2 : kInf;
       }
 
+      if constexpr (PHASES) {
+        keep_alive((uint32_t)key), keep_alive((uint32_t)(key >> 32));
+        const uint64_t t = phase_clock();
+        ph[2] += t - tp;
+        tp = t;
+      }
       // rank in the worklist; a node already in it is dropped (set union);
       // a key ranked past a full worklist is cut whatever the other new keys
       // are, so only the remaining ("live") keys take part in the merge.
@@ -1074,6 +1106,12 @@ void search_kernel(SearchArgs a) {
         if (c1 && c2) keep = false;  // both entries set: counted as visited
       }
       const uint64_t kk = keep ? key : kInf;
+      if constexpr (PHASES) {
+        keep_alive((uint32_t)kk), keep_alive((uint32_t)(kk >> 32));
+        const uint64_t t = phase_clock();
+        ph[3] += t - tp;
+        tp = t;
+      }
 
       // next node, decided before the merge: the smaller of the first
       // unvisited worklist entry a and the best new key b.  a is never cut
@@ -1142,6 +1180,10 @@ void search_kernel(SearchArgs a) {
         load_row<M, !kExact, HOST>(a, key_id(bestkey), lane, nb, code);
       else
         nb = kNone;
+      if constexpr (PHASES) {
+        t4 = phase_clock();
+        ph[4] += t4 - tp;
+      }
 
       const uint32_t nv = __popcll(km);
       if (nv == 0) {
@@ -1150,6 +1192,7 @@ void search_kernel(SearchArgs a) {
         cur = best;
         curkey = bestkey;
         __syncthreads();
+        if constexpr (PHASES) ph[5] += phase_clock() - t4;
         continue;
       }
       // smallest worklist rank of a live key (b's): entries below it stay
@@ -1241,7 +1284,9 @@ void search_kernel(SearchArgs a) {
       cur = best;
       curkey = bestkey;
       __syncthreads();
+      if constexpr (PHASES) ph[5] += phase_clock() - t4;
     }
+    if constexpr (PHASES) tp = phase_clock();
 
     // stage 3: re-rank the expanded nodes.  The last group of C is written
     // out; an agent-scope fence then also drops stale L1 lines.
@@ -1333,6 +1378,13 @@ void search_kernel(SearchArgs a) {
       a.out_times[qi * 2] = t_begin;
       a.out_times[qi * 2 + 1] = wall_clock64();
     }
+    if constexpr (PHASES) {
+      ph[6] = phase_clock() - tp;
+      if (lane == 0)
+        for (int p = 0; p < kPhases; ++p)
+          a.out_phases[qi * kPhases + p] =
+              (uint32_t)(ph[p] < 0xFFFFFFFFull ? ph[p] : 0xFFFFFFFFull);
+    }
   }
 }
 
@@ -1383,8 +1435,9 @@ hipError_t occupancy_of(K kernel, size_t lds, int* per_cu) {
 
 }  // namespace
 
-// The four search variants, one per translation unit (search_variants.hip):
-// v = host-resident adjacency (bit 0) | Bloom filter (bit 1).  launch runs
+// The search variants, one per translation unit (search_variants.hip):
+// v = host-resident adjacency (bit 0) | Bloom filter (bit 1), and v = 4 the
+// timed variant of v = 0.  launch runs
 // one search; occupancy gives the resident workgroups per CU at `lds` bytes
 // of LDS and enables that LDS size for the kernel, so it precedes a launch.
 #define BANG_VARIANT_DECL(V)                                                 \
@@ -1397,6 +1450,7 @@ BANG_VARIANT_DECL(0)
 BANG_VARIANT_DECL(1)
 BANG_VARIANT_DECL(2)
 BANG_VARIANT_DECL(3)
+BANG_VARIANT_DECL(4)
 #undef BANG_VARIANT_DECL
 
 }  // namespace bang

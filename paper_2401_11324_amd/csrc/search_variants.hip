@@ -1,10 +1,11 @@
 // One search variant per translation unit, so that the variants compile in
 // parallel: BANG_VARIANT = host-resident adjacency (bit 0) | Bloom filter
-// (bit 1), instantiated for every compiled (dtype, m, d/m) and table form.
+// (bit 1), or 4 for the timed variant of 0 (per-phase cycles), instantiated
+// for every compiled (dtype, m, d/m) and table form.
 #include "search_kernel.h"
 
 #ifndef BANG_VARIANT
-#error "compile with -DBANG_VARIANT=0, 1, 2 or 3"
+#error "compile with -DBANG_VARIANT=0, 1, 2, 3 or 4"
 #endif
 
 namespace bang {
@@ -13,6 +14,7 @@ namespace {
 
 constexpr bool kHostV = (BANG_VARIANT & 1) != 0;
 constexpr bool kBloomV = (BANG_VARIANT & 2) != 0;
+constexpr bool kPhasesV = BANG_VARIANT == 4;
 
 template <int DT, int M, int DS>
 struct Launch {
@@ -20,20 +22,20 @@ struct Launch {
                         size_t lds, hipStream_t s) {
     switch (table) {
       case kTabF32:
-        hipLaunchKernelGGL((search_kernel<DT, M, DS, kTabF32, kHostV, kBloomV>),
+        hipLaunchKernelGGL((search_kernel<DT, M, DS, kTabF32, kHostV, kBloomV, kPhasesV>),
                            dim3(grid), dim3(kWave), lds, s, a);
         break;
       case kTabF16:
-        hipLaunchKernelGGL((search_kernel<DT, M, DS, kTabF16, kHostV, kBloomV>),
+        hipLaunchKernelGGL((search_kernel<DT, M, DS, kTabF16, kHostV, kBloomV, kPhasesV>),
                            dim3(grid), dim3(kWave), lds, s, a);
         break;
       case kTabU8:
-        hipLaunchKernelGGL((search_kernel<DT, M, DS, kTabU8, kHostV, kBloomV>),
+        hipLaunchKernelGGL((search_kernel<DT, M, DS, kTabU8, kHostV, kBloomV, kPhasesV>),
                            dim3(grid), dim3(kWave), lds, s, a);
         break;
       case kTabExact:
         hipLaunchKernelGGL(
-            (search_kernel<DT, M, DS, kTabExact, kHostV, kBloomV>), dim3(grid),
+            (search_kernel<DT, M, DS, kTabExact, kHostV, kBloomV, kPhasesV>), dim3(grid),
             dim3(kWave), lds, s, a);
         break;
       default:
@@ -48,17 +50,17 @@ struct Occupancy {
   static hipError_t run(int table, size_t lds, int* per_cu) {
     switch (table) {
       case kTabF32:
-        return occupancy_of(search_kernel<DT, M, DS, kTabF32, kHostV, kBloomV>,
+        return occupancy_of(search_kernel<DT, M, DS, kTabF32, kHostV, kBloomV, kPhasesV>,
                             lds, per_cu);
       case kTabF16:
-        return occupancy_of(search_kernel<DT, M, DS, kTabF16, kHostV, kBloomV>,
+        return occupancy_of(search_kernel<DT, M, DS, kTabF16, kHostV, kBloomV, kPhasesV>,
                             lds, per_cu);
       case kTabU8:
-        return occupancy_of(search_kernel<DT, M, DS, kTabU8, kHostV, kBloomV>,
+        return occupancy_of(search_kernel<DT, M, DS, kTabU8, kHostV, kBloomV, kPhasesV>,
                             lds, per_cu);
       case kTabExact:
         return occupancy_of(
-            search_kernel<DT, M, DS, kTabExact, kHostV, kBloomV>, lds, per_cu);
+            search_kernel<DT, M, DS, kTabExact, kHostV, kBloomV, kPhasesV>, lds, per_cu);
     }
     return hipErrorInvalidValue;
   }

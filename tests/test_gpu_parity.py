@@ -871,3 +871,40 @@ def test_bloom_filter_mixed_batch_equals_oracle(small_indexes, name):
         assert np.array_equal(ids[sel, :k], ref["ids"]), (k, L)
         assert np.array_equal(f32bits(d[sel, :k]), f32bits(ref["dists"])), \
             (k, L)
+
+
+# --------------------------------------------------------------------------
+# the timed copy of the search (bang_search_opts.out_phases)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("table", ["f32", "u8", "exact"])
+def test_timed_search_same_results_and_phases(small_indexes, table):
+    """The timed search returns the same results bit for bit; every query
+    has positive table, scoring and re-rank times (no re-rank for exact
+    distances), and the loop phases are zero exactly when nothing was
+    expanded."""
+    ix, q, gi = small_indexes["u8-d128-m32"]
+    qt = to_dev(q)
+    ids0, d0 = gi.search(qt, 10, 64, table=table)
+    ids1, d1, cnt, ph = gi.search(qt, 10, 64, table=table,
+                                  want_counters=True, want_phases=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(u32(ids0), u32(ids1))
+    assert np.array_equal(f32bits(d0.cpu().numpy()), f32bits(d1.cpu().numpy()))
+    p = u32(ph).astype(np.int64)
+    it = u32(cnt)[:, 0]
+    assert (it > 0).all()
+    assert (p[:, 0] > 0).all() and (p[:, 2] > 0).all() and (p[:, 3] > 0).all()
+    assert (p[:, 6] > 0).all()
+    # the loop's phases sum to most of a query's cycles at this L
+    assert (p[:, 1:6].sum(1) > p[:, 0]).all()
+
+
+def test_timed_search_refused_with_host_rows_or_bloom(small_indexes,
+                                                     small_host_indexes):
+    ix, q, gi = small_indexes["u8-d64-m16"]
+    hi = small_host_indexes["u8-d64-m16"]
+    bang = bang_mod()
+    with pytest.raises(bang.BangError):
+        hi.search(to_dev(q), 10, 32, want_phases=True)
+    with pytest.raises(bang.BangError):
+        gi.search(to_dev(q), 10, 32, want_phases=True, filter="bloom")
