@@ -6,7 +6,13 @@
  * table, (2) the greedy search over a proximity graph with asymmetric (PQ)
  * distances (Algorithms 1 and 2), and (3) the exact re-rank.  The graph and
  * the compressed vectors live in device memory, as in the paper's
- * "In-memory Version" (section "Implementation Variants").
+ * "In-memory Version" (section "Implementation Variants"), or the adjacency
+ * stays in pinned host memory (BANG_INDEX_HOST_ADJ), as in the base design.
+ * Options select the table storage (FP32, the FP16 / u8 precision forms,
+ * or the paper's Exact-distance Version), the visited filter (set union or
+ * the paper's Bloom filter) and mixed per-query k and L; a serving loop
+ * (bang_server_*) batches requests continuously, and bang_index_probe
+ * measures the rate at which the search's rows can be read.
  *
  * Conventions shared by every call:
  *  - Status: every call returns 0 on success or a negative BANG_E* code;
