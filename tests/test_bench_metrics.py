@@ -48,3 +48,17 @@ def test_algorithmic_bytes_exact_distance_reads_base_rows_and_no_rerank():
             + 2 * d * elem            # two queries
             + 2 * 8 * k)              # results; no re-rank
     assert got == want
+
+
+def test_more_than_one_gpu_is_refused_with_a_message(capsys):
+    """This build runs on one GPU: --gpus N > 1 exits with status 2 and
+    says so, before touching any device."""
+    rc = bench.main(["--gpus", "2", "--no-sweep", "--L", "64"])
+    assert rc == 2
+    assert "one GPU" in capsys.readouterr().err
+
+
+def test_no_sweep_needs_L():
+    import pytest
+    with pytest.raises(SystemExit):
+        bench.main(["--no-sweep"])
