@@ -101,6 +101,8 @@ def test_calls_with_null_index_fail_cleanly():
     assert L.bang_search(None, None, 1, 10, 10, None, None, None, None) == -1
     assert L.bang_build_pq_tables(None, None, 1, None, None) == -1
     assert L.bang_rerank(None, None, 1, None, 4, 1, None, None, None) == -1
+    assert L.bang_index_probe(None, 10, 0, None, None, None) == -1
+    assert b"null index" in L.bang_last_error()
     assert L.bang_index_destroy(None) == 0
 
 
