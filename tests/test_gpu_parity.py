@@ -908,3 +908,24 @@ def test_timed_search_refused_with_host_rows_or_bloom(small_indexes,
         hi.search(to_dev(q), 10, 32, want_phases=True)
     with pytest.raises(bang.BangError):
         gi.search(to_dev(q), 10, 32, want_phases=True, filter="bloom")
+
+
+@pytest.mark.parametrize("name", ["u8-d64-m16", "f32-d128-m16"])
+def test_bloom_filter_equals_exact_filter_without_collisions(small_indexes,
+                                                            name):
+    """Where no node's two filter entries are both shared with other nodes
+    no neighbour can be a false positive, so the Bloom-filter search equals
+    the default set-union search bit for bit (no false negatives either)."""
+    from collections import Counter
+    ix, q, gi = small_indexes[name]
+    sl = [oracle.bloom_slots(x) for x in range(ix.n)]
+    cnt = Counter(h for s in sl for h in set(s))
+    assert not [x for x, s in enumerate(sl) if all(cnt[h] > 1 for h in set(s))]
+    qt = to_dev(q)
+    for k, L, table in [(10, 33, "f32"), (10, 100, "u8"), (5, 64, "exact")]:
+        a = gi.search(qt, k, L, table=table, want_cand=oracle.iter_cap_for(L))
+        b = gi.search(qt, k, L, table=table, filter="bloom",
+                      want_cand=oracle.iter_cap_for(L))
+        torch.cuda.synchronize()
+        for x, y in zip(a, b):
+            assert np.array_equal(x.cpu().numpy(), y.cpu().numpy()), (k, L)
