@@ -81,11 +81,10 @@ struct Elem<kI8> {
   }
 };
 
-// One table entry: sum over the subvector in coordinate order, FP32.
+// One centroid's DS coordinates (16-, 8- or 4-byte loads).
 template <int DS>
-__device__ __forceinline__ float table_entry(const float* qv,
-                                             const float* __restrict__ cent) {
-  float cv[DS];
+__device__ __forceinline__ void load_centroid(const float* __restrict__ cent,
+                                              float (&cv)[DS]) {
   if constexpr (DS % 4 == 0) {
 #pragma unroll
     for (int t = 0; t < DS; t += 4) {
@@ -102,6 +101,12 @@ __device__ __forceinline__ float table_entry(const float* qv,
 #pragma unroll
     for (int t = 0; t < DS; ++t) cv[t] = cent[t];
   }
+}
+
+// One table entry: sum over the subvector in coordinate order, FP32.
+template <int DS>
+__device__ __forceinline__ float entry_sum(const float* qv,
+                                           const float (&cv)[DS]) {
   float acc = 0.0f;
 #pragma unroll
   for (int t = 0; t < DS; ++t) {
@@ -110,6 +115,14 @@ __device__ __forceinline__ float table_entry(const float* qv,
     acc = acc + sq;
   }
   return acc;
+}
+
+template <int DS>
+__device__ __forceinline__ float table_entry(const float* qv,
+                                             const float* __restrict__ cent) {
+  float cv[DS];
+  load_centroid<DS>(cent, cv);
+  return entry_sum<DS>(qv, cv);
 }
 
 // Table of one query: T[j*256 + c], `nthr` threads starting at `tid`.
@@ -201,28 +214,117 @@ __device__ __forceinline__ float wave_minmax(float v, float ident) {
       __builtin_amdgcn_readlane(__float_as_uint(v), 63));
 }
 
+// The query vector spread over one wave for the table build: lane l holds
+// bytes [4l, 4l + 4) of each 256-byte block, so that every coordinate is one
+// cross-lane read away instead of a memory round trip per subspace.
+template <int DT, int D>
+struct QueryLanes {
+  static constexpr int kBytes = D * Elem<DT>::size;
+  static constexpr int kRegs = (kBytes + 4 * kWave - 1) / (4 * kWave);
+  static_assert(kBytes % 4 == 0, "the query is read in 4-byte words");
+  uint32_t w[kRegs];
+
+  __device__ __forceinline__ void load(const unsigned char* q, int lane) {
+    const uint32_t* q4 = reinterpret_cast<const uint32_t*>(q);
+#pragma unroll
+    for (int r = 0; r < kRegs; ++r) {
+      const int wi = lane + kWave * r;
+      w[r] = wi * 4 < kBytes ? q4[wi] : 0u;
+    }
+  }
+  // coordinate i (the same i on every lane), converted as Elem<DT>::f does
+  __device__ __forceinline__ float elem(int i) const {
+    const int b = i * Elem<DT>::size;
+    const int wi = b >> 2;
+    uint32_t v = w[0];
+#pragma unroll
+    for (int r = 1; r < kRegs; ++r) v = (wi >> 6) == r ? w[r] : v;
+    v = (uint32_t)__builtin_amdgcn_readlane((int)v, wi & (kWave - 1));
+    if constexpr (DT == kF32) {
+      return __uint_as_float(v);
+    } else if constexpr (DT == kU8) {
+      return (float)((v >> (8 * (b & 3))) & 0xFFu);
+    } else {
+      return (float)(int8_t)(v >> (8 * (b & 3)));
+    }
+  }
+};
+
+// This lane's entries of the query's table, subspace by subspace: f(j, e)
+// receives the entries of centroids lane + 64 r (r = 0..3) of subspace j.
+// Centroids are loaded JU subspaces (16 floats a lane, or one subspace) at a
+// time into two buffers: the loads of the next block are in flight while
+// one is scored, so the build waits about M / JU memory latencies, not 4 M.
+template <int DT, int M, int DS, bool PIPE, class F>
+__device__ __forceinline__ void table_entries(
+    const QueryLanes<DT, M * DS>& Q, const float* __restrict__ cb, int lane,
+    F&& f) {
+  constexpr int R = 256 / kWave;
+  constexpr int JU = DS >= 4 ? 1 : 4 / DS;
+  static_assert(M % (2 * JU) == 0, "subspaces are taken 2 JU at a time");
+  auto load = [&](float (&cv)[JU][R][DS], int j0) {
+#pragma unroll
+    for (int jj = 0; jj < JU; ++jj)
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+        load_centroid<DS>(
+            cb + ((size_t)(j0 + jj) * 256 + lane + kWave * r) * DS, cv[jj][r]);
+  };
+  auto score = [&](const float (&cv)[JU][R][DS], int j0) {
+#pragma unroll
+    for (int jj = 0; jj < JU; ++jj) {
+      float qv[DS];
+#pragma unroll
+      for (int t = 0; t < DS; ++t) qv[t] = Q.elem((j0 + jj) * DS + t);
+      float e[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) e[r] = entry_sum<DS>(qv, cv[jj][r]);
+      f(j0 + jj, e);
+    }
+  };
+  float ca[JU][R][DS], cbuf[JU][R][DS];
+  if constexpr (!PIPE) {
+#pragma unroll 1
+    for (int j0 = 0; j0 < M; j0 += JU) {
+      load(ca, j0);
+      score(ca, j0);
+    }
+    return;
+  }
+  load(ca, 0);
+#pragma unroll 1
+  for (int j0 = 0; j0 < M; j0 += 2 * JU) {
+    load(cbuf, j0 + JU);
+    score(ca, j0);
+    // past the last block the first one is loaded again (unused): the loads
+    // stay unconditional, so the wait for cbuf does not include them
+    load(ca, j0 + 2 * JU < M ? j0 + 2 * JU : 0);
+    score(cbuf, j0 + JU);
+  }
+}
+
 // The query's table in LDS, in the storage form TT (one wave, 64 lanes).
 // lo (U8 only): m floats of LDS for the per-subspace offsets.
 template <int DT, int M, int DS, int TT>
-__device__ __forceinline__ void build_table_q(const unsigned char* q,
+__device__ __forceinline__ void build_table_q(const QueryLanes<DT, M * DS>& Q,
                                               const float* __restrict__ cb,
                                               void* Tv, float* lo, int lane) {
+  constexpr int R = 256 / kWave;
   if constexpr (TT == kTabF32) {
-    build_table<DT, M, DS>(q, cb, reinterpret_cast<float*>(Tv), lane, kWave);
+    float* T = reinterpret_cast<float*>(Tv);
+    table_entries<DT, M, DS, true>(Q, cb, lane, [&](int j, const float (&e)[R]) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) T[j * 256 + lane + kWave * r] = e[r];
+    });
   } else {
     // pass 1: the statistics the storage needs
     float mx = 0.0f;  // F16: largest entry; U8: widest subspace range
-    for (int j = 0; j < M; ++j) {
-      float qv[DS];
-#pragma unroll
-      for (int t = 0; t < DS; ++t) qv[t] = Elem<DT>::f(q, j * DS + t);
+    table_entries<DT, M, DS, false>(Q, cb, lane, [&](int j, const float (&e)[R]) {
       float vmin = __uint_as_float(0x7F800000u), vmax = 0.0f;
 #pragma unroll
-      for (int r = 0; r < 256 / kWave; ++r) {
-        const int c = lane + kWave * r;
-        const float e = table_entry<DS>(qv, cb + ((size_t)j * 256 + c) * DS);
-        vmin = e < vmin ? e : vmin;
-        vmax = e > vmax ? e : vmax;
+      for (int r = 0; r < R; ++r) {
+        vmin = e[r] < vmin ? e[r] : vmin;
+        vmax = e[r] > vmax ? e[r] : vmax;
       }
       if constexpr (TT == kTabF16) {
         mx = vmax > mx ? vmax : mx;
@@ -233,7 +335,7 @@ __device__ __forceinline__ void build_table_q(const unsigned char* q,
         mx = range > mx ? range : mx;
         if (lane == 0) lo[j] = l;
       }
-    }
+    });
     float mul;
     if constexpr (TT == kTabF16) {
       mx = wave_minmax<true>(mx, 0.0f);
@@ -245,25 +347,21 @@ __device__ __forceinline__ void build_table_q(const unsigned char* q,
     }
     // pass 2: the entries again (bit-identical), stored in the reduced form
     typename Tab<TT>::E* T = reinterpret_cast<typename Tab<TT>::E*>(Tv);
-    for (int j = 0; j < M; ++j) {
-      float qv[DS];
-#pragma unroll
-      for (int t = 0; t < DS; ++t) qv[t] = Elem<DT>::f(q, j * DS + t);
+    table_entries<DT, M, DS, false>(Q, cb, lane, [&](int j, const float (&e)[R]) {
       const float lj = (TT == kTabU8) ? lo[j] : 0.0f;
 #pragma unroll
-      for (int r = 0; r < 256 / kWave; ++r) {
+      for (int r = 0; r < R; ++r) {
         const int c = lane + kWave * r;
-        const float e = table_entry<DS>(qv, cb + ((size_t)j * 256 + c) * DS);
         if constexpr (TT == kTabF16) {
-          const float sv = e * mul;
+          const float sv = e[r] * mul;
           T[j * 256 + c] = __builtin_bit_cast(uint16_t, (_Float16)sv);
         } else {
-          const float diff = e - lj;
+          const float diff = e[r] - lj;
           const float v = __builtin_rintf(diff * mul);
           T[j * 256 + c] = (uint8_t)(v > 255.0f ? 255.0f : v);
         }
       }
-    }
+    });
   }
 }
 
@@ -963,8 +1061,18 @@ void search_kernel(SearchArgs a) {
     }
     uint32_t nb;
     uint4 code[M / 16];
-    load_row<M, !kExact, HOST>(a, s, lane, nb, code);  // in flight meanwhile
-    if constexpr (!kExact) build_table_q<DT, M, DS, TT>(q, a.cb, T, lo, lane);
+    uint4 scode[M / 16];  // the medoid's own code (PQ forms)
+    if constexpr (!kExact) {
+      QueryLanes<DT, D> Q;
+      Q.load(q, lane);
+#pragma unroll
+      for (int i = 0; i < M / 16; ++i)
+        scode[i] = reinterpret_cast<const uint4*>(a.codes + (size_t)s * M)[i];
+      load_row<M, true, HOST>(a, s, lane, nb, code);  // in flight meanwhile
+      build_table_q<DT, M, DS, TT>(Q, a.cb, T, lo, lane);
+    } else {
+      load_row<M, false, HOST>(a, s, lane, nb, code);
+    }
     __syncthreads();
 
     // stage 2: L = [(dist(s), s)]
@@ -972,10 +1080,6 @@ void search_kernel(SearchArgs a) {
     if constexpr (kExact) {
       d0 = exact_dist<DT, D>(a.base, s, q, qq);
     } else {
-      uint4 scode[M / 16];
-#pragma unroll
-      for (int i = 0; i < M / 16; ++i)
-        scode[i] = reinterpret_cast<const uint4*>(a.codes + (size_t)s * M)[i];
       d0 = adc_codes<M, TT>(scode);
     }
     uint64_t curkey = make_key(d0, s);
