@@ -255,7 +255,7 @@ struct QueryLanes {
 // Centroids are loaded JU subspaces (16 floats a lane, or one subspace) at a
 // time into two buffers: the loads of the next block are in flight while
 // one is scored, so the build waits about M / JU memory latencies, not 4 M.
-template <int DT, int M, int DS, bool PIPE, class F>
+template <int DT, int M, int DS, class F>
 __device__ __forceinline__ void table_entries(
     const QueryLanes<DT, M * DS>& Q, const float* __restrict__ cb, int lane,
     F&& f) {
@@ -283,14 +283,6 @@ __device__ __forceinline__ void table_entries(
     }
   };
   float ca[JU][R][DS], cbuf[JU][R][DS];
-  if constexpr (!PIPE) {
-#pragma unroll 1
-    for (int j0 = 0; j0 < M; j0 += JU) {
-      load(ca, j0);
-      score(ca, j0);
-    }
-    return;
-  }
   load(ca, 0);
 #pragma unroll 1
   for (int j0 = 0; j0 < M; j0 += 2 * JU) {
@@ -312,14 +304,14 @@ __device__ __forceinline__ void build_table_q(const QueryLanes<DT, M * DS>& Q,
   constexpr int R = 256 / kWave;
   if constexpr (TT == kTabF32) {
     float* T = reinterpret_cast<float*>(Tv);
-    table_entries<DT, M, DS, true>(Q, cb, lane, [&](int j, const float (&e)[R]) {
+    table_entries<DT, M, DS>(Q, cb, lane, [&](int j, const float (&e)[R]) {
 #pragma unroll
       for (int r = 0; r < R; ++r) T[j * 256 + lane + kWave * r] = e[r];
     });
   } else {
     // pass 1: the statistics the storage needs
     float mx = 0.0f;  // F16: largest entry; U8: widest subspace range
-    table_entries<DT, M, DS, false>(Q, cb, lane, [&](int j, const float (&e)[R]) {
+    table_entries<DT, M, DS>(Q, cb, lane, [&](int j, const float (&e)[R]) {
       float vmin = __uint_as_float(0x7F800000u), vmax = 0.0f;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
@@ -347,7 +339,7 @@ __device__ __forceinline__ void build_table_q(const QueryLanes<DT, M * DS>& Q,
     }
     // pass 2: the entries again (bit-identical), stored in the reduced form
     typename Tab<TT>::E* T = reinterpret_cast<typename Tab<TT>::E*>(Tv);
-    table_entries<DT, M, DS, false>(Q, cb, lane, [&](int j, const float (&e)[R]) {
+    table_entries<DT, M, DS>(Q, cb, lane, [&](int j, const float (&e)[R]) {
       const float lj = (TT == kTabU8) ? lo[j] : 0.0f;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
