@@ -296,9 +296,11 @@ __device__ __forceinline__ void table_entries(
 }
 
 // The query's table in LDS, in the storage form TT (one wave, 64 lanes).
-// lo (U8 only): m floats of LDS for the per-subspace offsets.
+// lo (U8 only): m floats of LDS for the per-subspace offsets.  Out of line:
+// it runs once per query, and its registers are then not allocated together
+// with the search loop's (measured 1-3% faster at L=768).
 template <int DT, int M, int DS, int TT>
-__device__ __forceinline__ void build_table_q(const QueryLanes<DT, M * DS>& Q,
+__device__ __attribute__((noinline)) void build_table_q(QueryLanes<DT, M * DS> Q,
                                               const float* __restrict__ cb,
                                               void* Tv, float* lo, int lane) {
   constexpr int R = 256 / kWave;
