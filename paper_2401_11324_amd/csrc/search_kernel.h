@@ -254,7 +254,8 @@ struct QueryLanes {
 // receives the entries of centroids lane + 64 r (r = 0..3) of subspace j.
 // Centroids are loaded JU subspaces (16 floats a lane, or one subspace) at a
 // time into two buffers: the loads of the next block are in flight while
-// one is scored, so the build waits about M / JU memory latencies, not 4 M.
+// one is scored, so the build waits about M / JU memory latencies, not 4 M
+// (d/m >= 8: one buffer of one subspace).
 template <int DT, int M, int DS, class F>
 __device__ __forceinline__ void table_entries(
     const QueryLanes<DT, M * DS>& Q, const float* __restrict__ cb, int lane,
@@ -283,6 +284,17 @@ __device__ __forceinline__ void table_entries(
     }
   };
   float ca[JU][R][DS], cbuf[JU][R][DS];
+  if constexpr (DS >= 8) {
+    // a subspace alone fills 32 registers a lane: one buffer, so that the
+    // build does not raise the register count (and cut occupancy) of the
+    // search that calls it
+#pragma unroll 1
+    for (int j0 = 0; j0 < M; j0 += JU) {
+      load(ca, j0);
+      score(ca, j0);
+    }
+    return;
+  }
   load(ca, 0);
 #pragma unroll 1
   for (int j0 = 0; j0 < M; j0 += 2 * JU) {
