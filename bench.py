@@ -717,9 +717,12 @@ def main(argv=None):
         if exact is not None:
             pts.append(("exact", exact["L"], exact))
         out["bloom_filter"] = bloom_section(run, pts)
+        # plus a small worklist, where the once-per-query table build and
+        # re-rank weigh most
         out["phase_split"] = phase_section(
             run, [("f32", L), ("u8", prec["u8"]["L"])] +
-            ([("exact", exact["L"])] if exact is not None else []))
+            ([("exact", exact["L"])] if exact is not None else []) +
+            ([("f32", 64)] if L != 64 else []))
     if not a.no_serve:
         out["serving"] = serving_section(gi, d, w, gt)
     if not a.no_deep:
