@@ -1444,7 +1444,9 @@ void search_kernel(SearchArgs a) {
 #pragma unroll 1
       for (uint32_t i = lane; i < nc; i += kWave) {
         const uint32_t id = key_id(S[i]);
-        const uint64_t key = make_key(exact_dist<DT, D>(a.base, id, q, qq), id);
+        // the whole row in one round trip (the loop's registers are free)
+        const uint64_t key =
+            make_key(exact_dist<DT, D, true>(a.base, id, q, qq), id);
         S[i] = key;
         if (key < best) {
           best = key;
@@ -1468,7 +1470,7 @@ void search_kernel(SearchArgs a) {
 #pragma unroll 1
       for (uint32_t i = lane; i < nc; i += kWave) {
         const uint32_t id = key_id(C[i]);
-        C[i] = make_key(exact_dist<DT, D>(a.base, id, q, qq), id);
+        C[i] = make_key(exact_dist<DT, D, true>(a.base, id, q, qq), id);
       }
       __threadfence();
       __syncthreads();
