@@ -471,6 +471,7 @@ __device__ __forceinline__ int32_t query_sq(const unsigned char* q) {
 // integer sum (below 2^24, exact in FP32).
 // EAGER: every load of the row is issued before the first product (one
 // memory round trip, D/4 more registers); otherwise two chunks at a time.
+// Float data: the row is read eight (EAGER) or four 16-byte chunks at a time.
 template <int DT, int D, bool EAGER = false>
 __device__ __forceinline__ float exact_dist(const void* __restrict__ base,
                                             uint32_t id,
@@ -481,7 +482,9 @@ __device__ __forceinline__ float exact_dist(const void* __restrict__ base,
         reinterpret_cast<const float4*>((const float*)base + (size_t)id * D);
     const float* qq = reinterpret_cast<const float*>(q);
     float acc = 0.0f;
-#pragma unroll 4
+    // EAGER: eight 16-byte loads in flight instead of four
+    constexpr int kUnroll = EAGER ? 8 : 4;
+#pragma unroll kUnroll
     for (int c = 0; c < D / 4; ++c) {
       float4 v = x[c];
       const float xv[4] = {v.x, v.y, v.z, v.w};
