@@ -16,14 +16,20 @@ in oracle.c):
 * ``rerank``         stage 3 alone over given candidates
 * ``bruteforce``     exact k nearest (ground truth)
 * ``train_pq`` / ``pq_encode``   PQ codebooks (k-means) and codes
-* ``medoid`` / ``vamana_build`` / ``reachable``   the graph index
+* ``medoid`` / ``vamana_build`` / ``robust_prune`` / ``connect`` /
+  ``reachable``      the graph index
 
 Parity status: table, ADC, re-rank, search (every table form and the
 exact-distance form) and brute force are pinned by the tests in
 tests/test_oracle.py and tests/test_oracle_properties.py (closed forms,
-brute force on tiny and random inputs, the paper's worked example).  The Vamana build and k-means training are
-"parity unpinned": no reference graph or codebook exists; only structural
-invariants and Lloyd monotonicity are checked.
+brute force on tiny and random inputs, the paper's worked example).  The
+graph build and the PQ training are inputs both paths consume; they are
+pinned against plain re-statements on tiny inputs: RobustPrune by
+hand-worked cases (the alpha rule, its <= boundary, ties) and the exact
+greedy rule on random integer points, the whole Vamana build (sequential
+insertion) against a plain re-statement, the connectivity repair and the
+folding of coarse levels by hand-built graphs, and k-means by Lloyd's
+algorithm written out plainly.
 """
 from __future__ import annotations
 
@@ -86,6 +92,9 @@ def lib():
                                       ctypes.c_int, P, u32, f64, u32, P,
                                       ctypes.c_int]
         L.or_vamana_build.restype = ctypes.c_int
+        L.or_robust_prune.argtypes = [P, ctypes.c_int, u64, u32, u32, P, u32,
+                                      f64, u32, P]
+        L.or_robust_prune.restype = ctypes.c_int64
         L.or_reachable.argtypes = [P, u64, u32, u32]
         L.or_reachable.restype = u64
         L.or_connect.argtypes = [P, ctypes.c_int, u64, u32, P, u32, u32,
@@ -324,6 +333,36 @@ def vamana_build(base: np.ndarray, R: int, L_build: int, alpha: float,
     if rc != 0:
         raise MemoryError("or_vamana_build failed")
     return adj
+
+
+def robust_prune(base: np.ndarray, p: int, cand, alpha: float,
+                 R: int) -> np.ndarray:
+    """RobustPrune(p, cand, alpha, R) of the Vamana build (oracle.c
+    robust_prune): candidates in (distance to p, id) order, p and repeats
+    dropped; the nearest remaining one is kept and every remaining p' with
+    alpha * d(p*, p') <= d(p, p') (plain Euclidean distances) is dropped,
+    until R are kept.  Returns the kept ids in selection order."""
+    b = np.ascontiguousarray(base)
+    n, d = b.shape
+    c = np.ascontiguousarray(cand, dtype=np.uint32)
+    out = np.empty(max(1, R), dtype=np.uint32)
+    no = lib().or_robust_prune(_p(b), DT[_dtname(b)], n, d, int(p), _p(c),
+                               len(c), float(alpha), R, _p(out))
+    if no < 0:
+        raise MemoryError("or_robust_prune failed")
+    return out[:no].copy()
+
+
+def connect(base: np.ndarray, adj: np.ndarray, start: int, L_build: int,
+            max_rounds: int = 8) -> int:
+    """Connectivity repair in place (oracle.c or_connect): every node not
+    reachable from `start` gets an in-edge from the nearest node that the
+    build's greedy search toward it expands.  Returns the edges added."""
+    b = np.ascontiguousarray(base)
+    assert adj.flags["C_CONTIGUOUS"] and adj.dtype == np.uint32
+    n, R = adj.shape
+    return int(lib().or_connect(_p(b), DT[_dtname(b)], n, b.shape[1],
+                                _p(adj), R, start, L_build, max_rounds))
 
 
 def reachable(adj: np.ndarray, start: int) -> int:

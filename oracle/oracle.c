@@ -944,6 +944,20 @@ static uint32_t robust_prune(const vset* v, uint32_t p, const uint32_t* cand,
   return no;
 }
 
+/* RobustPrune alone, for the tests: the at most R out-neighbours of point
+ * p chosen from cand[0..nc) (repeats and p itself allowed in cand), in
+ * selection order.  Returns their count, or -2 when out of memory. */
+int64_t or_robust_prune(const void* base, int dt, uint64_t n, uint32_t d,
+                        uint32_t p, const uint32_t* cand, uint32_t nc,
+                        double alpha, uint32_t R, uint32_t* out) {
+  vset v = {base, dt, n, d};
+  dentry* work = (dentry*)malloc(sizeof(dentry) * (nc ? nc : 1));
+  if (!work) return -2;
+  uint32_t no = robust_prune(&v, p, cand, nc, alpha, R, work, out);
+  free(work);
+  return (int64_t)no;
+}
+
 typedef struct {
   uint32_t tgt;
   uint32_t src;

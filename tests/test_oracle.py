@@ -314,7 +314,7 @@ def test_bruteforce_matches_sorted_exact_distances(dtype):
 
 
 # --------------------------------------------------------------------------
-# PQ training and encoding (parity unpinned: properties only)
+# PQ training and encoding
 # --------------------------------------------------------------------------
 def test_kmeans_objective_non_increasing_and_assignment_optimal():
     """Lloyd's iterations never increase the k-means objective; each point
@@ -328,6 +328,48 @@ def test_kmeans_objective_non_increasing_and_assignment_optimal():
     D = ((X[:, None, :] - C[None]) ** 2).sum(-1)
     assert np.array_equal(a, D.argmin(1))
     np.testing.assert_allclose(obj, D.min(1).sum(), rtol=1e-12)
+
+
+def _lloyd_reference(X, init_idx, iters):
+    """Lloyd's k-means written out plainly: nearest centroid by squared
+    difference (ties to the lowest id), then each centroid becomes the mean
+    of its points, summed in point order; an empty cluster keeps its
+    centroid."""
+    C = [list(map(float, X[i])) for i in init_idx]
+    K = len(C)
+    for _ in range(iters):
+        assign = []
+        for x in X:
+            best, bi = None, 0
+            for c in range(K):
+                dd = sum((float(x[t]) - C[c][t]) ** 2 for t in range(len(x)))
+                if best is None or dd < best:
+                    best, bi = dd, c
+            assign.append(bi)
+        for c in range(K):
+            pts = [X[i] for i in range(len(X)) if assign[i] == c]
+            if pts:
+                C[c] = [sum(float(p[t]) for p in pts) / len(pts)
+                        for t in range(len(pts[0]))]
+    return np.array(C)
+
+
+def test_kmeans_and_train_pq_equal_plain_lloyd():
+    """k-means (the PQ training reading: K = 256, init from distinct sample
+    points, FP64 Lloyd, empty clusters keep their centroid) equals Lloyd's
+    algorithm written out plainly, on 300 integer points (exact sums), and
+    train_pq runs it per subspace in subspace order from one generator."""
+    rng = np.random.default_rng(7)
+    X = rng.integers(0, 12, size=(300, 4)).astype(np.float64)
+    g1, g2 = np.random.default_rng(8), np.random.default_rng(8)
+    C = kmeans(X[:, :2], 256, 3, g1)
+    init = g2.choice(300, 256, replace=False)
+    assert np.array_equal(C, _lloyd_reference(X[:, :2], init, 3))
+    cb = train_pq(X, 2, 3, np.random.default_rng(8))
+    assert np.array_equal(cb[0], C.astype(np.float32))
+    init2 = g2.choice(300, 256, replace=False)
+    assert np.array_equal(cb[1], _lloyd_reference(X[:, 2:], init2, 3)
+                          .astype(np.float32))
 
 
 def test_pq_encode_is_nearest_centroid_per_subspace(small_u8):
@@ -345,7 +387,8 @@ def test_medoid_is_point_nearest_the_mean(small_f32):
 
 
 # --------------------------------------------------------------------------
-# Graph (parity unpinned: structural invariants only)
+# Graph: structural invariants, RobustPrune and the whole build against
+# plain re-statements on tiny inputs
 # --------------------------------------------------------------------------
 @pytest.mark.parametrize("fx", ["small_f32", "small_u8", "small_i8"])
 def test_graph_invariants(fx, request):
@@ -362,8 +405,156 @@ def test_graph_invariants(fx, request):
     assert info["reachable"] == n
 
 
+# RobustPrune (Vamana's pruning step; the paper names the Vamana graph in
+# "Graph Index" and gives R and alpha in "Algorithm Parameters").  The
+# candidates of the hand-worked case, 2-D integer points, p = point 0 at
+# the origin (d = Euclidean distance to p):
+#   id 1 a=( 2, 0) d=2      id 2 b=( 3, 1) d=3.162   id 3 c=( 0, 3) d=3
+#   id 4 e=(-4, 0) d=4      id 5 f=( 1, 4) d=4.123   id 6 g=(-3,-3) d=4.243
+#   id 7 h=( 5, 0) d=5      id 8 k=( 4,-6) d=7.211
+_PRUNE_PTS = np.array([[0, 0], [2, 0], [3, 1], [0, 3], [-4, 0], [1, 4],
+                       [-3, -3], [5, 0], [4, -6]], dtype=np.float32)
+
+
+def test_robust_prune_hand_worked_alpha_1_2():
+    """alpha = 1.2, order a, c, b, e, f, g, h, k.
+    Keep a: b goes (1.2 d(a,b) = 1.2 sqrt 2 = 1.70 <= 3.16), h goes
+    (1.2 * 3 = 3.6 <= 5); c stays (1.2 sqrt 13 = 4.33 > 3), e (7.2 > 4),
+    f (1.2 sqrt 17 = 4.95 > 4.12), g (1.2 sqrt 34 = 7.0 > 4.24), k
+    (1.2 sqrt 40 = 7.59 > sqrt 52 = 7.21).
+    Keep c: f goes (1.2 sqrt 2 = 1.70 <= 4.12); e (6 > 4), g (8.05 > 4.24),
+    k (1.2 sqrt 97 = 11.8 > 7.21) stay.
+    Keep e: g goes (1.2 sqrt 10 = 3.79 <= 4.24); k stays (12 > 7.21).
+    Keep k.  R = 4 -> [a, c, e, k]; R = 3 stops after e.
+    Slips this separates: alpha on squared distances drops k at the first
+    step (1.2 * 40 = 48 <= 52), giving [a, c, e] for R = 4."""
+    cand = np.arange(1, 9, dtype=np.uint32)
+    assert oracle.robust_prune(_PRUNE_PTS, 0, cand, 1.2, 4).tolist() == \
+        [1, 3, 4, 8]
+    assert oracle.robust_prune(_PRUNE_PTS, 0, cand, 1.2, 3).tolist() == \
+        [1, 3, 4]
+    # order of the candidate list does not matter; p itself and repeats
+    # are not candidates
+    shuf = np.array([8, 0, 5, 3, 3, 1, 7, 2, 6, 4, 1, 8], dtype=np.uint32)
+    assert oracle.robust_prune(_PRUNE_PTS, 0, shuf, 1.2, 4).tolist() == \
+        [1, 3, 4, 8]
+    # alpha = 1 (the first Vamana pass) drops what a kept point is at least
+    # as close to: keep a, which drops b (sqrt 2 <= 3.16), h (3 <= 5), k
+    # (sqrt 40 <= sqrt 52) and f at equality (d(a,f) = d(p,f) = sqrt 17);
+    # keep c, then e, which drops g (sqrt 10 <= 4.24)
+    assert oracle.robust_prune(_PRUNE_PTS, 0, cand, 1.0, 8).tolist() == \
+        [1, 3, 4]
+
+
+def test_robust_prune_boundary_and_ties():
+    """alpha * d(p*, p') == d(p, p') drops p' (the rule is <=): with
+    alpha = 1.5 (exact in binary), p = (0,0), p* = (1,0), p' = (3,0):
+    1.5 * 2 = 3.  With alpha = 1.2 and p' = (6,0): 1.2 * 5 = 6.  Equal
+    distances to p are taken in id order."""
+    pts = np.array([[0, 0], [1, 0], [3, 0]], dtype=np.float32)
+    assert oracle.robust_prune(pts, 0, np.array([1, 2], np.uint32),
+                               1.5, 4).tolist() == [1]
+    # a slightly larger alpha keeps the far point (1.51 * 2 > 3)
+    assert oracle.robust_prune(pts, 0, np.array([1, 2], np.uint32),
+                               1.51, 4).tolist() == [1, 2]
+    pts = np.array([[0, 0], [1, 0], [6, 0]], dtype=np.float32)
+    assert oracle.robust_prune(pts, 0, np.array([2, 1], np.uint32),
+                               1.2, 4).tolist() == [1]
+    # ties: ids 3 and 5 both at distance 2; 3 first, then 5 stays
+    # (1.2 * sqrt 8 = 3.39 > 2)
+    pts = np.zeros((6, 2), np.float32)
+    pts[3] = (2, 0)
+    pts[5] = (0, 2)
+    pts[[1, 2, 4]] = (50, 50)
+    assert oracle.robust_prune(pts, 0, np.array([5, 3], np.uint32),
+                               1.2, 2).tolist() == [3, 5]
+
+
+def _prune_reference_ok(pts, p, cand, out, a2num, a2den, R):
+    """Brute-force characterisation of RobustPrune's output in exact
+    integer arithmetic (alpha^2 = a2num / a2den): in (distance, id) order,
+    a candidate is kept iff fewer than R were kept before it and no
+    earlier kept point p* has alpha^2 d2(p*, x) <= d2(p, x)."""
+    X = pts.astype(np.int64)
+
+    def d2(i, j):
+        return int(((X[i] - X[j]) ** 2).sum())
+
+    order = sorted({int(c) for c in cand if int(c) != p},
+                   key=lambda c: (d2(p, c), c))
+    kept = []
+    for x in order:
+        if len(kept) == R:
+            break
+        if all(a2num * d2(y, x) > a2den * d2(p, x) for y in kept):
+            kept.append(x)
+    return kept == [int(v) for v in out]
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_robust_prune_matches_brute_force_rule(seed):
+    """Random integer points, alpha = 1.5 (alpha^2 = 9/4 exactly), random
+    candidate lists with repeats and p itself: the kept list is exactly the
+    greedy rule's, which also means every kept pair satisfies the alpha
+    condition in selection order."""
+    rng = np.random.default_rng(seed)
+    pts = rng.integers(-20, 21, size=(60, 3)).astype(np.float32)
+    for _ in range(40):
+        p = int(rng.integers(0, 60))
+        cand = rng.integers(0, 60, size=int(rng.integers(1, 50))).astype(
+            np.uint32)
+        R = int(rng.integers(1, 12))
+        out = oracle.robust_prune(pts, p, cand, 1.5, R)
+        assert _prune_reference_ok(pts, p, cand, out, 9, 4, R)
+
+
+def test_connect_adds_the_in_edge_the_repair_rule_names():
+    """Connectivity repair (NSG's device, a reading stated with the graph
+    build): points on a line 0..3 and 10, s = 0, R = 2; node 4 has no
+    in-edge.  The greedy search toward x4 = (10, 0) from 0 expands 0, 1, 2,
+    3; by distance to x4 they are 3, 2, 1, 0.  Node 3 has a free slot, so
+    the repair adds 3 -> 4.  With 3, 2 and 1 full, the nearest expanded
+    node with a free slot is 0: 0 -> 4."""
+    pts = np.array([[0, 0], [1, 0], [2, 0], [3, 0], [10, 0]], np.float32)
+    N = NONE
+    adj = np.array([[1, N], [0, 2], [1, 3], [2, N], [3, N]], np.uint32)
+    assert oracle.reachable(adj, 0) == 4
+    assert oracle.connect(pts, adj, 0, 8) == 1
+    assert adj[3].tolist() == [2, 4]
+    assert oracle.reachable(adj, 0) == 5
+    adj = np.array([[1, N], [0, 2], [1, 3], [2, 1], [3, N]], np.uint32)
+    assert oracle.connect(pts, adj, 0, 8) == 1
+    assert adj[0].tolist() == [1, 4]
+    assert adj[1:4].tolist() == [[0, 2], [1, 3], [2, 1]]
+    assert oracle.reachable(adj, 0) == 5
+
+
+def test_fold_levels_puts_coarse_neighbours_first():
+    """Coarse levels folded into one graph (the navigability reading of the
+    graph build): a point's coarse neighbours come first, the highest level
+    first, then its base list; repeats and self ids are dropped and the row
+    is cut to R."""
+    from oracle.graph import fold_levels
+    N = NONE
+    adj0 = np.array([[1, 2, 3], [0, 2, N], [0, 1, N], [0, 2, N],
+                     [3, N, N]], np.uint32)
+    # level 1 over points {0, 3, 4}: local ids 0, 1, 2
+    lvl1 = (np.array([0, 3, 4], np.uint32),
+            np.array([[2, N], [2, 0], [0, 1]], np.uint32))
+    # level 2 over points {0, 4}
+    lvl2 = (np.array([0, 4], np.uint32), np.array([[1], [0]], np.uint32))
+    adj = fold_levels(adj0, [lvl1, lvl2])
+    assert adj[0].tolist() == [4, 1, 2]        # 4 (l2), 4 (l1, repeat), base
+    assert adj[3].tolist() == [4, 0, 2]        # l1: 4, 0; base 0 (repeat), 2
+    assert adj[4].tolist() == [0, 3, N]        # l2: 0; l1: 0, 3; base 3
+    assert adj[1].tolist() == adj0[1].tolist()  # in no coarse level
+
+
 def test_plain_vamana_degree_bound_and_prune_rule():
-    """Vamana: out-degree at most R, no self loops, no duplicate ids."""
+    """Vamana: out-degree at most R, no self loops, no duplicate ids; every
+    list the build returns is one RobustPrune can produce: its entries
+    satisfy the alpha condition pairwise in (distance, id) order, checked
+    in exact arithmetic on integer points (alpha = 1.5)."""
     w = synth.small("f32", n=800, d=16, nq=2, seed_index=105)
     base, _ = synth.base_and_queries(w)
     s = oracle.medoid(base)
@@ -375,6 +566,79 @@ def test_plain_vamana_degree_bound_and_prune_rule():
     # determinism across thread counts
     adj1 = oracle.vamana_build(base, 12, 24, 1.2, perm, s, nthreads=1)
     assert np.array_equal(adj, adj1)
+
+
+def _vamana_reference(X, R, Lb, alphas, perm, s, cap):
+    """The Vamana build as the graph reading states it, written plainly
+    for tiny inputs, one insertion at a time: greedy search from s toward
+    p (worklist of Lb, expanded nodes in order), RobustPrune of those plus
+    p's current list, back-edges appended while a list holds at most cap
+    ids (else that list is pruned), per pass; finally every list longer
+    than R is pruned with the last alpha.  Exact integer arithmetic; alpha
+    is given as alpha^2 = (num, den)."""
+    X = X.astype(np.int64)
+    n = len(X)
+
+    def d2(a, b):
+        return int(((X[a] - X[b]) ** 2).sum())
+
+    def prune(p, cand, a2):
+        order = sorted({c for c in cand if c != p}, key=lambda c: (d2(p, c), c))
+        kept = []
+        for x in order:
+            if len(kept) == R:
+                break
+            if all(a2[0] * d2(y, x) > a2[1] * d2(p, x) for y in kept):
+                kept.append(x)
+        return kept
+
+    def greedy(p, nbr):
+        L = [(d2(s, p), s, False)]
+        seen = {s}
+        V = []
+        while True:
+            i = next((i for i, e in enumerate(L) if not e[2]), None)
+            if i is None or len(V) == 4 * Lb + 64:
+                return V
+            dist, u, _ = L[i]
+            L[i] = (dist, u, True)
+            V.append(u)
+            for x in nbr[u]:
+                if x not in seen:
+                    seen.add(x)
+                    L.append((d2(x, p), x, False))
+            L = sorted(L, key=lambda e: (e[0], e[1]))[:Lb]
+
+    nbr = [[] for _ in range(n)]
+    for a2 in alphas:
+        for p in perm:
+            p = int(p)
+            new = prune(p, greedy(p, nbr) + nbr[p], a2)
+            nbr[p] = new
+            for j in new:
+                lst = nbr[j] + ([p] if p not in nbr[j] and p != j else [])
+                nbr[j] = lst if len(lst) <= cap else prune(j, lst, a2)
+    for j in range(n):
+        if len(nbr[j]) > R:
+            nbr[j] = prune(j, nbr[j], alphas[-1])
+    return nbr
+
+
+def test_vamana_build_equals_plain_reference():
+    """The oracle's Vamana build (one insertion per batch) equals a plain
+    re-statement of the build on 40 integer points in the plane: two
+    passes with alpha = 1 and alpha = 1.5, R = 4, L_build = 6, back-edge
+    slack 1.3 (lists of up to 5 before a prune), so appends, overflow
+    prunes and the final prune all occur."""
+    rng = np.random.default_rng(11)
+    X = rng.integers(-25, 26, size=(40, 2)).astype(np.float32)
+    s = oracle.medoid(X)
+    perm = rng.permutation(40).astype(np.uint32)
+    adj = oracle.vamana_build(X, 4, 6, 1.5, perm, s, slack=1.3,
+                              max_batch_frac=0.0)
+    ref = _vamana_reference(X, 4, 6, [(1, 1), (9, 4)], perm, s, 5)
+    got = [[int(x) for x in row if x != NONE] for row in adj]
+    assert got == ref
 
 
 # --------------------------------------------------------------------------
