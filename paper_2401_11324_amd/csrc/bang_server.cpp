@@ -301,9 +301,12 @@ int wait_for(bang_server* sv, uint64_t ticket, uint32_t* ids, float* dists,
              int timeout_ms, Clock::time_point* done_at) {
   if (!sv) return fail(BANG_EINVAL, "null server");
   std::unique_lock<std::mutex> lk(sv->mu);
-  auto it = sv->live.find(ticket);
-  if (it == sv->live.end()) return fail(BANG_EINVAL, "unknown ticket");
-  auto r = it->second;
+  std::shared_ptr<Request> r;
+  {
+    auto it = sv->live.find(ticket);
+    if (it == sv->live.end()) return fail(BANG_EINVAL, "unknown ticket");
+    r = it->second;  // no iterator is kept: the wait releases the lock
+  }
   auto ready = [&] { return r->status <= 0; };
   if (timeout_ms < 0) {
     sv->done_cv.wait(lk, ready);
@@ -311,7 +314,9 @@ int wait_for(bang_server* sv, uint64_t ticket, uint32_t* ids, float* dists,
                                    ready)) {
     return fail(BANG_EABORTED, "timed out; the request is still queued");
   }
-  sv->live.erase(it);
+  // another thread waiting on the same ticket may have collected it
+  if (sv->live.erase(ticket) == 0)
+    return fail(BANG_EINVAL, "ticket already collected by another wait");
   lk.unlock();
   if (r->status < 0) return fail(r->status, r->error);
   if (ids) std::memcpy(ids, r->ids.data(), r->ids.size() * 4);
