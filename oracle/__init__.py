@@ -77,6 +77,10 @@ def lib():
         L.or_fnv1a32.restype = u32
         L.or_bloom_slots.argtypes = [u32, P, P]
         L.or_rerank.argtypes = [P, P, u64, P, u32, u32, P, P, ctypes.c_int]
+        L.or_bf16_round.argtypes = [ctypes.c_float]
+        L.or_bf16_round.restype = ctypes.c_float
+        L.or_bf16_band.argtypes = [P, P, P, u64, P, P, P]
+        L.or_rerank_bf16.argtypes = [P, P, u64, P, u32, u32, P, P, P]
         L.or_rerank.restype = ctypes.c_int
         L.or_bruteforce.argtypes = [P, ctypes.c_int, u64, u32, P, u64, u32,
                                     P, P, ctypes.c_int]
@@ -285,6 +289,40 @@ def rerank(index: Index, queries: np.ndarray, cand: np.ndarray, k: int,
     lib().or_rerank(index.cptr, _p(q), nq, _p(cand), cm, k, _p(ids),
                     _p(dists), nthreads or default_threads())
     return ids, dists
+
+
+def bf16_round(x: float) -> float:
+    """x rounded to bfloat16 (nearest, ties to even), as a float."""
+    return float(lib().or_bf16_round(float(x)))
+
+
+def bf16_band(index: Index, query: np.ndarray, ids: np.ndarray):
+    """The BF16 re-rank's terms for candidates `ids` of one float query:
+    (D~ the FP32 distance over BF16-rounded rows, lower, upper) with the
+    canonical FP32 distance guaranteed inside [lower, upper]."""
+    q = np.ascontiguousarray(query, dtype=np.float32)
+    ids = np.ascontiguousarray(ids, dtype=np.uint32)
+    n = len(ids)
+    out = [np.empty(n, dtype=np.float32) for _ in range(3)]
+    lib().or_bf16_band(index.cptr, _p(q), _p(ids), n, *(_p(a) for a in out))
+    return tuple(out)
+
+
+def rerank_bf16(index: Index, queries: np.ndarray, cand: np.ndarray, k: int):
+    """The precision form's re-rank of float data: BF16 rows and FP32 sums,
+    then the canonical FP32 distance for every candidate whose lower bound
+    is within the k-th smallest upper bound.  Returns (ids, dists,
+    rechecked per query); ids and dists equal rerank()'s."""
+    q = np.ascontiguousarray(queries, dtype=np.float32)
+    cand = np.ascontiguousarray(cand, dtype=np.uint32)
+    nq, cm = cand.shape
+    ids = np.empty((nq, k), dtype=np.uint32)
+    dists = np.empty((nq, k), dtype=np.float32)
+    rc = np.empty(nq, dtype=np.uint32)
+    if lib().or_rerank_bf16(index.cptr, _p(q), nq, _p(cand), cm, k, _p(ids),
+                            _p(dists), _p(rc)) != 0:
+        raise ValueError("the BF16 re-rank needs float data")
+    return ids, dists, rc
 
 
 def bruteforce(base: np.ndarray, queries: np.ndarray, k: int,

@@ -610,6 +610,156 @@ int or_rerank(const or_index* ix, const void* queries, uint64_t nq,
 }
 
 /* ------------------------------------------------------------------------
+ * Precision form of the re-rank, float data only.  The paper re-ranks in
+ * FP32 (section "Re-ranking"); this form reads the base rows rounded to
+ * bfloat16, sums in FP32, and recomputes in FP32 every candidate that
+ * could still be among the k nearest.  Its answer is the FP32 re-rank's by
+ * construction: the band E below bounds the gap between the BF16 sum and
+ * the canonical FP32 distance of every candidate.
+ *
+ * Derivation (u = 2^-24, u_b = 2^-8 the unit roundoffs of FP32 and BF16,
+ * x~ = bf16(x), D = canonical FP32 distance, D* = exact real distance,
+ * D~ = the FP32 sum over x~, D~* its exact value, B = sum of x~^2, and
+ * g = (d+2)u/(1-(d+2)u) <= 6.2e-5 for d <= 1024):
+ *   |D - D*| <= g D*,  |D~ - D~*| <= g D~*  (sequential sums of squares);
+ *   |x~ - x| <= u_b |x| and |x| <= |x~| / (1 - u_b), so with v = u_b/(1-u_b)
+ *   |D~* - D*| <= sum |x~ - x| (|x~ - q| + |x - q|)
+ *             <= 2v sum |x~||x~ - q| + v^2 B <= 2v sqrt(B D~*) + v^2 B
+ *   (Cauchy-Schwarz).  2v = 0.00784 and v^2 = 1.54e-5, so
+ *   E = 2^-6 sqrt(B D~) + 2^-15 B + 2^-12 D~
+ * bounds |D~ - D| with a factor of two to spare in every term, which also
+ * covers the roundings of E, of B and D~ themselves and of D~ -/+ E.
+ * ---------------------------------------------------------------------- */
+
+/* x rounded to bfloat16 (8 significant bits, FP32's exponent range) to
+ * the nearest, ties to the even significand, returned widened to FP32.
+ * The two neighbours in BF16 are x with its low 16 bits cleared and that
+ * plus one BF16 step; the nearer wins. */
+float or_bf16_round(float x) {
+  if (!isfinite(x)) return x;
+  uint32_t b;
+  memcpy(&b, &x, 4);
+  uint32_t lo_b = b & 0xFFFF0000u;          /* toward zero */
+  uint32_t hi_b = lo_b + 0x10000u;           /* one step away from zero */
+  float lo, hi;
+  memcpy(&lo, &lo_b, 4);
+  memcpy(&hi, &hi_b, 4);
+  double dl = fabs((double)x - (double)lo);
+  double dh = fabs((double)hi - (double)x);
+  if (dl < dh) return lo;
+  if (dh < dl) return hi;
+  return ((lo_b >> 16) & 1u) ? hi : lo;      /* tie: the even one */
+}
+
+/* D~, B, E and the bounds [lower, upper] of one candidate row x. */
+static void bf16_terms(const float* x, const float* q, uint32_t d, float* dt,
+                       float* lower, float* upper) {
+  float acc = 0.0f, nb = 0.0f;
+  for (uint32_t t = 0; t < d; ++t) {
+    float xb = or_bf16_round(x[t]);
+    float diff = xb - q[t];
+    float sq = diff * diff;
+    acc = acc + sq;
+  }
+  for (uint32_t t = 0; t < d; ++t) {
+    float xb = or_bf16_round(x[t]);
+    float sq = xb * xb;
+    nb = nb + sq;
+  }
+  float bd = nb * acc;
+  float e1 = sqrtf(bd) * 0.015625f;          /* 2^-6 */
+  float e2 = nb * 3.0517578125e-05f;         /* 2^-15 */
+  float e3 = acc * 2.44140625e-04f;          /* 2^-12 */
+  float E = (e1 + e2) + e3;
+  float lo = acc - E;
+  *dt = acc;
+  *lower = lo > 0.0f ? lo : 0.0f;
+  *upper = acc + E;
+}
+
+/* The band of each of n candidates (no padding) of one query, for tests:
+ * D~, lower and upper bounds. */
+void or_bf16_band(const or_index* ix, const float* q, const uint32_t* ids,
+                  uint64_t n, float* dt, float* lower, float* upper) {
+  for (uint64_t i = 0; i < n; ++i)
+    bf16_terms((const float*)ix->base + (uint64_t)ids[i] * ix->d, q, ix->d,
+               dt + i, lower + i, upper + i);
+}
+
+typedef struct {
+  float key;
+  uint32_t id;
+} fkey;
+
+static int fkey_cmp(const void* a, const void* b) {
+  const fkey* x = (const fkey*)a;
+  const fkey* y = (const fkey*)b;
+  if (x->key != y->key) return x->key < y->key ? -1 : 1;
+  return x->id < y->id ? -1 : (x->id > y->id ? 1 : 0);
+}
+
+/* The BF16 re-rank of given candidates (float data): tau = the k-th
+ * smallest upper bound (+inf with k or fewer candidates); every candidate
+ * whose lower bound is <= tau gets its canonical FP32 distance; the k
+ * smallest of those by (distance, id) are the answer.  rechecked[q] = how
+ * many were recomputed.  Ids NONE or >= n are padding. */
+int or_rerank_bf16(const or_index* ix, const float* queries, uint64_t nq,
+                   const uint32_t* cand, uint32_t c_max, uint32_t k,
+                   uint32_t* ids, float* dists, uint32_t* rechecked) {
+  if (ix->dtype != OR_F32) return -1;
+  fkey* U = (fkey*)malloc((size_t)(c_max + 1) * sizeof(fkey));
+  float* lo = (float*)malloc((size_t)(c_max + 1) * sizeof(float));
+  uint32_t* id = (uint32_t*)malloc((size_t)(c_max + 1) * sizeof(uint32_t));
+  entry* C = (entry*)malloc((size_t)(c_max + 1) * sizeof(entry));
+  if (!U || !lo || !id || !C) {
+    free(U); free(lo); free(id); free(C);
+    return -2;
+  }
+  for (uint64_t qi = 0; qi < nq; ++qi) {
+    const float* q = queries + qi * ix->d;
+    uint32_t nc = 0;
+    for (uint32_t i = 0; i < c_max; ++i) {
+      uint32_t x = cand[qi * c_max + i];
+      if (x == OR_NONE || x >= ix->n) continue;
+      float dt, up;
+      bf16_terms((const float*)ix->base + (uint64_t)x * ix->d, q, ix->d, &dt,
+                 &lo[nc], &up);
+      U[nc].key = up;
+      U[nc].id = x;
+      id[nc] = x;
+      ++nc;
+    }
+    float tau = INFINITY;
+    if (nc > k) {
+      fkey* S = (fkey*)malloc((size_t)nc * sizeof(fkey));
+      memcpy(S, U, (size_t)nc * sizeof(fkey));
+      qsort(S, nc, sizeof(fkey), fkey_cmp);
+      tau = S[k - 1].key;
+      free(S);
+    }
+    uint32_t nr = 0;
+    for (uint32_t i = 0; i < nc; ++i) {
+      if (!(lo[i] <= tau)) continue;
+      C[nr].id = id[i];
+      C[nr].dist = exact_dist(ix, q, id[i]);
+      C[nr].visited = 0;
+      ++nr;
+    }
+    qsort(C, nr, sizeof(entry), entry_cmp);
+    for (uint32_t i = 0; i < k; ++i) {
+      ids[qi * k + i] = i < nr ? C[i].id : OR_NONE;
+      dists[qi * k + i] = i < nr ? C[i].dist : INFINITY;
+    }
+    if (rechecked) rechecked[qi] = nr;
+  }
+  free(U);
+  free(lo);
+  free(id);
+  free(C);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------
  * Ground truth: brute-force exact k nearest (the kNN problem statement in
  * the introduction; recall definition in "Algorithm Parameters").  Integer
  * data is exact in int64; float data in FP64.  Ordered by (dist, id).

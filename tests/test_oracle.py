@@ -911,3 +911,110 @@ def test_bloom_false_positive_depends_on_row_order():
     bloom2 = oracle.search(ix2, q2, 1, 8, mode=2, want_cand=True)
     assert sorted(bloom2["cand"][0][:bloom2["iters"][0]].tolist()) == sorted(
         [s, a, y])
+
+
+# --------------------------------------------------------------------------
+# the precision form's BF16 re-rank with an FP32 recheck (float data)
+# --------------------------------------------------------------------------
+def test_bf16_round_hand_worked_values():
+    """bfloat16 keeps 8 significant bits: near 1 the step is 2^-7, and a
+    value halfway between two neighbours goes to the one whose last
+    significand bit is 0."""
+    r = oracle.bf16_round
+    assert r(1.0) == 1.0
+    assert r(1 + 2 ** -8) == 1.0                    # tie, 1.0 is even
+    assert r(1 + 3 * 2 ** -8) == 1 + 2 ** -6        # tie, 1+2^-6 is even
+    assert r(1 + 2 ** -8 + 2 ** -20) == 1 + 2 ** -7  # just above the tie
+    assert r(1 + 2 ** -8 - 2 ** -20) == 1.0          # just below
+    assert r(-(1 + 2 ** -8 + 2 ** -20)) == -(1 + 2 ** -7)
+    assert r(float(np.float32(np.pi))) == 3.140625
+    assert r(0.0) == 0.0 and r(256.0) == 256.0 and r(257.0) == 256.0
+    assert r(259.0) == 260.0                         # step 2 at 256..512
+    assert r(1000.001) == 1000.0                      # step 4 at 512..1024
+
+
+def _fp32_dists(ix, q, ids):
+    """Canonical FP32 distances of ids, in the order given."""
+    got_ids, got_d = oracle.rerank(ix, q[None, :],
+                                   np.asarray(ids, np.uint32)[None, :],
+                                   len(ids))
+    order = {int(i): float(dv) for i, dv in zip(got_ids[0], got_d[0])}
+    return np.array([order[int(i)] for i in ids], dtype=np.float64)
+
+
+@pytest.mark.parametrize("scale,d", [(1.0, 96), (1e-3, 128), (1e3, 96),
+                                     (1.0, 1024)])
+def test_bf16_band_contains_fp32_and_exact_distances(scale, d):
+    """For random rows and queries at several magnitudes, and rows that
+    nearly equal the query (where the BF16 rounding of a large coordinate
+    is larger than the whole distance), both the canonical FP32 distance
+    and the exact FP64 one lie inside [lower, upper]; for ordinary rows
+    the band is a small fraction of the distance."""
+    rng = np.random.default_rng(int(d + scale * 7))
+    n = 400
+    base = (rng.standard_normal((n, d)) * scale).astype(np.float32)
+    q = (rng.standard_normal(d) * scale).astype(np.float32)
+    base[:40] = (q + rng.standard_normal((40, d)).astype(np.float32)
+                 * np.float32(scale * 1e-4))
+    base[40:60] = q + np.float32(1000.0 * scale)
+    base[60:70] = q
+    adj = np.full((n, 4), 0xFFFFFFFF, dtype=np.uint32)
+    ix = oracle.Index(base, adj, 0, np.zeros((1, 256, d), np.float32),
+                      np.zeros((n, 1), np.uint8))
+    ids = np.arange(n, dtype=np.uint32)
+    dt, lo, hi = oracle.bf16_band(ix, q, ids)
+    f32 = _fp32_dists(ix, q, ids)
+    exact = ((base.astype(np.float64) - q.astype(np.float64)) ** 2).sum(1)
+    assert np.all(lo <= f32) and np.all(f32 <= hi)
+    assert np.all(lo <= exact) and np.all(exact <= hi)
+    assert np.all(lo >= 0)
+    ordinary = slice(70, n)
+    width = (hi[ordinary] - lo[ordinary]) / dt[ordinary]
+    assert width.max() < 0.05
+
+
+def test_bf16_rerank_equals_fp32_rerank_on_near_ties():
+    """Candidates whose FP32 distances differ in the last bits, so that the
+    BF16 sums alone order them differently: the recheck restores the FP32
+    answer exactly (ids and distances), recomputing fewer candidates than
+    it was given."""
+    rng = np.random.default_rng(21)
+    d, n, k = 96, 600, 10
+    q = rng.standard_normal(d).astype(np.float32)
+    base = rng.standard_normal((n, d)).astype(np.float32)
+    # 30 near-copies of one row that differ by less than a BF16 step
+    anchor = rng.standard_normal(d).astype(np.float32) * np.float32(0.3) + q
+    base[:30] = anchor + (rng.standard_normal((30, d)) *
+                          1e-4).astype(np.float32)
+    adj = np.full((n, 4), 0xFFFFFFFF, dtype=np.uint32)
+    ix = oracle.Index(base, adj, 0, np.zeros((1, 256, d), np.float32),
+                      np.zeros((n, 1), np.uint8))
+    cand = np.stack([rng.permutation(n).astype(np.uint32) for _ in range(6)])
+    qs = np.tile(q, (6, 1))
+    want_ids, want_d = oracle.rerank(ix, qs, cand, k)
+    got_ids, got_d, rechecked = oracle.rerank_bf16(ix, qs, cand, k)
+    assert np.array_equal(got_ids, want_ids)
+    assert np.array_equal(got_d.view(np.uint32), want_d.view(np.uint32))
+    assert (rechecked >= k).all() and (rechecked < n).all()
+    # the BF16 sums alone order the near-copies differently from FP32: the
+    # recheck is what makes the answers equal
+    dt, _, _ = oracle.bf16_band(ix, q, np.arange(30, dtype=np.uint32))
+    f32 = _fp32_dists(ix, q, np.arange(30, dtype=np.uint32))
+    assert not np.array_equal(np.lexsort((np.arange(30), dt)),
+                              np.lexsort((np.arange(30), f32)))
+
+
+def test_bf16_rerank_with_k_candidates_or_fewer_rechecks_all():
+    rng = np.random.default_rng(4)
+    d, n = 32, 50
+    base = rng.standard_normal((n, d)).astype(np.float32)
+    q = rng.standard_normal((1, d)).astype(np.float32)
+    adj = np.full((n, 4), 0xFFFFFFFF, dtype=np.uint32)
+    ix = oracle.Index(base, adj, 0, np.zeros((1, 256, d), np.float32),
+                      np.zeros((n, 1), np.uint8))
+    cand = np.array([[3, 0xFFFFFFFF, 7, 11, 0xFFFFFFFF]], dtype=np.uint32)
+    ids, dists, rc = oracle.rerank_bf16(ix, q, cand, 5)
+    want_ids, want_d = oracle.rerank(ix, q, cand, 5)
+    assert rc[0] == 3
+    assert np.array_equal(ids, want_ids)
+    assert np.array_equal(dists.view(np.uint32), want_d.view(np.uint32))
