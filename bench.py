@@ -35,6 +35,8 @@ HBM_PEAK_GBS = 8000.0
 HOST_LINK_PEAK_GBS = 64.0
 TARGET_RECALL = 0.9
 TABLES = ("f32", "f16", "u8")
+# the unseen-neighbour count of the method's bytes runs on every 5th query
+NPRIME_EVERY = 5
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "search_sift1m_traffic.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2401_11324_amd", "csrc", f)
                   for f in ("search_kernel.h", "search_variants.hip",
@@ -62,14 +64,14 @@ def iteration_overhead(I: float, t: int) -> float:
     return (I - t) / t * 100.0
 
 
-def algorithmic_bytes(adj_deg, R, m, d, elem, k, iters, cand, c_max,
-                      exact=False):
-    """HBM bytes one launch must move, from the per-query counters:
-    per expansion the adjacency row (4R) and the m code bytes of every
-    neighbour in it; per query the query vector, the base rows of the
-    re-ranked candidates and the k (id, distance) results.  Exact-distance
-    search: the base row (d elements) of every neighbour instead of its
-    codes, and no re-rank."""
+def packed_row_bytes(adj_deg, R, m, d, elem, k, iters, cand, c_max,
+                     exact=False):
+    """Bytes this design's search reads, from the per-query counters: per
+    expansion the packed row, i.e. the adjacency ids (4R) and the m code
+    bytes of EVERY neighbour (the row carries them, seen or not); per query
+    the query vector, the base rows of the re-ranked candidates and the k
+    (id, distance) results.  Exact-distance search: the base row (d
+    elements) of every neighbour instead of its codes, and no re-rank."""
     I = iters.astype(np.int64)
     valid = cand != 0xFFFFFFFF
     deg_sum = np.where(valid, adj_deg[np.where(valid, cand, 0)], 0).sum()
@@ -81,28 +83,93 @@ def algorithmic_bytes(adj_deg, R, m, d, elem, k, iters, cand, c_max,
                + rr * d * elem + len(I) * 8 * k)
 
 
-def cpu_baseline(idx_np, queries, k, L, budget_s=15.0):
+def unseen_neighbours(adj, medoid, iters, cand):
+    """Per query, the sum over its expansions of |N'|, the neighbours not
+    seen before (Algorithm 2 with an exact visited set: the seen set starts
+    as {s} and takes each row's unseen neighbours).  Every id enters the
+    seen set once, so the sum is the number of distinct ids in the rows of
+    the expanded nodes, the start node and empty slots excluded.  cand
+    holds the expanded nodes in expansion order."""
+    # distinct count without a sort: after pos[ids] = 0..len-1, exactly one
+    # position per distinct id holds its own index (whichever repeat won)
+    pos = np.zeros(adj.shape[0], dtype=np.int64)
+    out = np.zeros(len(iters), dtype=np.int64)
+    for qi in range(len(iters)):
+        ids = adj[cand[qi, :int(iters[qi])]].ravel()
+        ids = ids[(ids != 0xFFFFFFFF) & (ids != medoid)]
+        at = np.arange(ids.size)
+        pos[ids] = at
+        out[qi] = np.count_nonzero(pos[ids] == at)
+    return out
+
+
+def method_bytes(nprime, R, m, d, elem, k, iters, c_max, exact=False):
+    """HBM bytes the method itself must move per launch: per expansion the
+    adjacency row (4R), the visited-set probes (8 bytes per neighbour slot)
+    and the codes of the unseen neighbours only (m bytes each); per query
+    the base rows re-ranked (the expanded nodes, at most c_max), the query
+    and the k results.  Exact-distance search: the base row of each unseen
+    neighbour instead of its codes, and no re-rank.  nprime[q] is the
+    query's sum of |N'| over its expansions (unseen_neighbours, or an
+    estimate from a sample of the batch).  Returns
+    (total, parts) with the terms listed separately."""
+    I = iters.astype(np.int64)
+    npr = np.asarray(nprime, dtype=np.float64).sum()
+    parts = {"adjacency": int(I.sum() * 4 * R),
+             "visited_probes": int(I.sum() * 8 * R),
+             "codes_unseen" if not exact else "base_rows_unseen":
+                 int(npr * (d * elem if exact else m)),
+             "rerank_rows": 0 if exact else
+                 int(np.minimum(I, c_max).sum() * d * elem),
+             "queries_and_results": int(len(I) * (d * elem + 8 * k))}
+    return sum(parts.values()), parts
+
+
+def cpu_model() -> str:
+    """The host CPU's model name (/proc/cpuinfo), or "unknown"."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(idx_np, queries, k, L, budget_s=15.0, budget1_s=8.0):
     """The CPU oracle (test infrastructure) on a bounded sample of the same
-    queries: 64 queries to estimate the rate, then enough for ~budget_s."""
+    queries, on every host thread this process may use: 64 queries to
+    estimate the rate, then enough for ~budget_s; then on one thread for
+    ~budget1_s."""
     import oracle
     threads = oracle.default_threads()
     ix = oracle.Index(idx_np["base"], idx_np["adj"], idx_np["medoid"],
                       idx_np["codebooks"], idx_np["codes"])
-    t = time.perf_counter()
-    oracle.search(ix, queries[:64], k, L, nthreads=threads)
-    rate = 64 / max(1e-9, time.perf_counter() - t)
-    n = int(min(len(queries), max(64, rate * budget_s)))
-    t = time.perf_counter()
-    oracle.search(ix, queries[:n], k, L, nthreads=threads)
-    dt = time.perf_counter() - t
+
+    def timed(nthreads, budget):
+        t = time.perf_counter()
+        probe = 64 if nthreads > 1 else 8
+        oracle.search(ix, queries[:probe], k, L, nthreads=nthreads)
+        rate = probe / max(1e-9, time.perf_counter() - t)
+        n = int(min(len(queries), max(probe, rate * budget)))
+        t = time.perf_counter()
+        oracle.search(ix, queries[:n], k, L, nthreads=nthreads)
+        return n, time.perf_counter() - t
+
+    n, dt = timed(threads, budget_s)
+    n1, dt1 = timed(1, budget1_s)
     return {"value": round(n / dt, 1), "unit": "queries/s", "cores": threads,
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": cpu_model(),
             "sample": f"first {n} of {len(queries)} queries, k={k}, L={L}, "
                       f"{dt:.1f} s; table + Algorithm 1 + re-rank, "
-                      f"{threads} threads"}
+                      f"{threads} threads",
+            "one_thread": {"value": round(n1 / dt1, 1), "unit": "queries/s",
+                           "sample": f"first {n1} queries, {dt1:.1f} s"}}
 
 
-SERVE_RATES = (1e4, 1e5, 1e6)      # offered queries/s
+# offered queries/s: 10^4 to 10^6 in half decades
+SERVE_RATES = (1e4, 10 ** 4.5, 1e5, 10 ** 5.5, 1e6)
 SERVE_P99_TARGET_MS = 50.0
 SERVE_CANDIDATES = ((1024, 2), (4096, 2), (4096, 4), (16384, 2))
 
@@ -457,6 +524,42 @@ def copy_probe(mib: int) -> int:
     return 0
 
 
+def form_adc(T, codes, table):
+    """The distance the search ranks by under a table form, as FP64 values
+    comparable with the exact ADC, for rows `codes` [P][m] of one query's
+    FP32 table T [m][256] (from bang_build_pq_tables).  The forms follow
+    their definitions in include/bang.h: FP32, the sum in subspace order;
+    F16, entries times 2^-k rounded to half, summed in FP32, times 2^k; U8,
+    entries rint((T - lo_j) * 255 / max range) as integers, summed, then
+    divided by the scale with the offsets added back."""
+    m = T.shape[0]
+    f32 = np.float32
+    if table == "f32":
+        acc = np.zeros(len(codes), dtype=f32)
+        for j in range(m):
+            acc = (acc + T[j, codes[:, j]]).astype(f32)
+        return acc.astype(np.float64)
+    if table == "f16":
+        mx, mul = f32(T.max()), f32(1.0)
+        while f32(mx * mul) > f32(65504.0):
+            mul = f32(mul * f32(0.5))
+        H = (T * mul).astype(f32).astype(np.float16).astype(f32)
+        acc = np.zeros(len(codes), dtype=f32)
+        for j in range(m):
+            acc = (acc + H[j, codes[:, j]]).astype(f32)
+        return acc.astype(np.float64) / float(mul)
+    lo = T.min(1)
+    rng = (T.max(1) - lo).astype(f32)
+    mx = f32(rng.max())
+    inv = f32(f32(255.0) / mx) if mx > 0 else f32(0.0)
+    Q = np.minimum(np.rint(((T - lo[:, None]).astype(f32) * inv).astype(f32)),
+                   255).astype(np.int64)
+    isum = np.zeros(len(codes), dtype=np.int64)
+    for j in range(m):
+        isum += Q[j, codes[:, j]]
+    return isum / float(inv) + float(lo.astype(np.float64).sum())
+
+
 class Runner:
     """One workload's index on the GPU, its recall sweep over L and the
     timed measurement of one table form at one L."""
@@ -471,6 +574,7 @@ class Runner:
         self.dev = torch.device("cuda:0")
         self.q = torch.from_numpy(d["queries"]).to(self.dev)
         self.gt = d["gt_ids"]
+        self.adj = d["adj"]
         self.adj_deg = (d["adj"] != 0xFFFFFFFF).sum(1)
         self.elem = 1 if w.dtype in ("u8", "i8") else 4
         self.rows = []
@@ -507,6 +611,33 @@ class Runner:
         rows = [s for s in self.rows if s["table"] == table]
         ok = [s for s in rows if s["recall10"] >= TARGET_RECALL]
         return ok[0]["L"] if ok else max(rows, key=lambda s: s["recall10"])["L"]
+
+    def adc_error(self, table, cand, iters, nq=100, per_q=256):
+        """Relative error of the distance the search ranks by under a table
+        form, against the ADC in FP64 (the same codes, the codebooks and
+        query in FP64), over the first nq queries and up to per_q of each
+        one's expanded nodes (the nodes the search ranked)."""
+        torch = self.torch
+        d, m = self.d, self.w.m
+        ds = self.w.d // m
+        T = self.gi.build_pq_tables(self.q[:nq])
+        torch.cuda.synchronize()
+        T = T.cpu().numpy().reshape(nq, m, 256)
+        cb = d["codebooks"].astype(np.float64)  # [m][256][ds]
+        qn = d["queries"][:nq].astype(np.float64)
+        errs = []
+        for i in range(nq):
+            ex = cand[i, :min(int(iters[i]), per_q)]
+            codes = d["codes"][ex].astype(np.int64)
+            qs = qn[i].reshape(m, 1, ds)
+            T64 = ((qs - cb) ** 2).sum(-1)  # [m][256]
+            ref = T64[np.arange(m)[None, :], codes].sum(1)
+            got = form_adc(T[i], codes, table)
+            errs.append(np.abs(got - ref) / np.maximum(ref, 1e-30))
+        e = np.concatenate(errs)
+        return {"pairs": int(e.size), "max": float(e.max()),
+                "mean": float(e.mean()),
+                "p99": float(np.percentile(e, 99))}
 
     def measure(self, table, L, index=None, filter="exact"):
         """K timed steps of one form; returns its record."""
@@ -546,32 +677,62 @@ class Runner:
                                            filter=filter)
         torch.cuda.synchronize()
         cand = cand.cpu().numpy().view(np.uint32)
-        iters = cnt.cpu().numpy()[:, 0]
+        cnt = cnt.cpu().numpy()
+        iters, status = cnt[:, 0], cnt[:, 1]
         t = times.cpu().numpy().astype(np.float64)
         # completion time of each query after the batch began, scaled so
         # that the span of the device clock equals the measured kernel time
         span = max(1.0, t[:, 1].max() - t[:, 0].min())
         kern_ms = float(per.mean())
         lat_ms = (t[:, 1] - t[:, 0].min()) / span * kern_ms
-        B = algorithmic_bytes(self.adj_deg, w.R, w.m, w.d, self.elem, k,
-                              iters, cand, 4 * L, exact=table == "exact")
+        exact = table == "exact"
+        if filter == "exact":
+            # |N'| counted on every NPRIME_EVERY-th query (a fixed sample),
+            # scaled to the batch by expansions
+            sel = np.arange(0, nq, NPRIME_EVERY)
+            ns = unseen_neighbours(self.adj, int(self.d["medoid"]),
+                                   iters[sel], cand[sel])
+            per_exp = ns.sum() / max(1, iters[sel].astype(np.int64).sum())
+            nprime = per_exp * iters.astype(np.float64)
+        else:
+            nprime = None  # a lossy filter: |N'| is not the exact set's
+        design = packed_row_bytes(self.adj_deg, w.R, w.m, w.d, self.elem, k,
+                                  iters, cand, 4 * L, exact=exact)
         ms_step = wall * 1e3 / a.steps
-        return {"table": table, "L": L, "filter": filter,
+        recd = {"table": table, "L": L, "filter": filter,
                 "recall10": round(rec, 4),
                 "adjacency_bytes_per_launch": int(iters.astype(np.int64).sum()
                                                   * 4 * w.R),
                 "qps": round(nq / (ms_step / 1e3), 1),
                 "ms_per_step": round(ms_step, 4),
+                "latency": "per-query completion time after the launch "
+                           f"began, within one batch of {nq} queries",
                 "p50_ms": round(float(np.percentile(lat_ms, 50)), 4),
                 "p99_ms": round(float(np.percentile(lat_ms, 99)), 4),
                 "mean_iterations": round(float(iters.mean()), 2),
+                "iteration_capped_queries": int((status == 1).sum()),
                 "lambda_pct": round(iteration_overhead(float(iters.mean()),
                                                        L), 2),
                 "kernel_ms_mean": round(kern_ms, 4),
-                "algorithmic_bytes_per_launch": B,
-                "achieved_gbs": round(B / (kern_ms / 1e3) / 1e9, 2),
-                "max_rel_dist_err_vs_fp64": float(rel.max()) if rel.size
+                "packed_row_bytes_per_launch": design,
+                "packed_row_gbs": round(design / (kern_ms / 1e3) / 1e9, 2),
+                "result_rel_dist_err_vs_fp64": float(rel.max()) if rel.size
                 else 0.0}
+        if not exact:
+            recd["adc_rel_err_vs_fp64"] = self.adc_error(table, cand, iters)
+        if nprime is not None:
+            B, parts = method_bytes(nprime, w.R, w.m, w.d, self.elem, k,
+                                    iters, 4 * L, exact=exact)
+            recd.update({
+                "mean_unseen_per_expansion": round(float(per_exp), 3),
+                "unseen_sample": f"every {NPRIME_EVERY}th query "
+                                 f"({len(sel)} of {nq})",
+                "expansions": int(iters.astype(np.int64).sum()),
+                "method_bytes_per_launch": B,
+                "method_bytes_parts": parts,
+                "achieved_gbs": round(B / (kern_ms / 1e3) / 1e9, 2),
+                "packed_row_over_method": round(design / B, 3)})
+        return recd
 
 
 def main(argv=None):
@@ -701,8 +862,20 @@ def main(argv=None):
             "unit": "GB/s",
             "frac": round(plain["achieved_gbs"] / HBM_PEAK_GBS, 5),
             "traffic": traffic,
-            "algorithmic_bytes_per_launch":
-                plain["algorithmic_bytes_per_launch"],
+            "bytes": "the method's bytes per launch: per expansion the "
+                     "adjacency row (4R), visited-set probes (8R) and the "
+                     "codes of the unseen neighbours (m each); re-ranked "
+                     "base rows, queries and results",
+            "method_bytes_per_launch": plain["method_bytes_per_launch"],
+            "method_bytes_parts": plain["method_bytes_parts"],
+            "mean_unseen_per_expansion":
+                plain["mean_unseen_per_expansion"],
+            "packed_row_bytes_per_launch":
+                plain["packed_row_bytes_per_launch"],
+            "packed_row_over_method": plain["packed_row_over_method"],
+            "traffic_over_method": (round(traffic /
+                                          plain["method_bytes_per_launch"], 3)
+                                    if traffic else None),
             "kernel_ms_mean": plain["kernel_ms_mean"],
             "random_row_probe": probe,
         },
