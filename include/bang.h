@@ -49,7 +49,8 @@ extern "C" {
 #define BANG_ENOMEM (-2)       /* allocation failed / over the memory budget */
 #define BANG_EDEVICE (-3)      /* HIP runtime error or no usable GPU */
 #define BANG_EUNSUPPORTED (-4) /* valid but not supported by this build */
-#define BANG_EABORTED (-5)     /* reserved */
+#define BANG_EABORTED (-5)     /* stopped by a stop request, or a wait
+                                  that timed out */
 
 #define BANG_NONE 0xFFFFFFFFu  /* empty adjacency slot / padded result id */
 #define BANG_MAX_L 1024u       /* largest worklist (the paper's t) */
@@ -58,6 +59,7 @@ extern "C" {
 typedef enum { BANG_F32 = 0, BANG_U8 = 1, BANG_I8 = 2 } bang_dtype;
 
 typedef struct bang_index bang_index; /* opaque */
+typedef struct bang_abort bang_abort; /* opaque: a stop request */
 
 /* Index description; every pointer is HOST memory, read during
  * bang_index_create only. */
@@ -97,7 +99,9 @@ typedef struct {
   uint32_t* out_cand;       /* device [nq][cand_stride]: expanded node ids in
                                expansion order, BANG_NONE padded */
   uint32_t cand_stride;
-  uint32_t* out_counters;   /* device [nq][4]: {iterations, status, 0, 0} */
+  uint32_t* out_counters;   /* device [nq][4]: {iterations, status, 0, 0};
+                               status 0 converged, 1 stopped at iter_cap,
+                               2 stopped by the stop request (abort) */
   uint64_t* out_times;      /* device [nq][2]: device wall-clock ticks when
                                the query's work began and when its results
                                were written (hipDeviceAttributeWallClockRate
@@ -130,6 +134,14 @@ typedef struct {
                                search (same results, somewhat slower);
                                device-resident adjacency and the exact
                                filter only (EUNSUPPORTED otherwise). */
+  const bang_abort* abort;  /* NULL, or a stop request (bang_abort_create)
+                               this search obeys: once it is set, each wave
+                               finishes the expansion it is in, writes its
+                               query's row as padding (BANG_NONE, +inf) with
+                               status 2 in out_counters, and every query not
+                               yet started is written the same way without
+                               being searched.  Queries that finished before
+                               keep their results. */
 } bang_search_opts;
 
 /* Visited filters.
@@ -226,6 +238,30 @@ int bang_rerank(bang_index* index, const void* queries, uint64_t nq,
  * the kernel may write.  Errors: EINVAL, EDEVICE. */
 int bang_index_probe(bang_index* index, uint64_t nreads, uint64_t seed,
                      uint64_t* sink, uint32_t* row_bytes_out, void* stream);
+
+/* Stop requests.  The paper's search is one long batched launch (10,000
+ * queries, and the persistent launch of a large mixed batch runs for
+ * seconds); a stop request lets the host end such a launch early without
+ * losing the device: every wave of a search that carries it
+ * (bang_search_opts.abort) reads it at each query's start and once every
+ * 64 expansions, and leaves normally once it is set, so the stream and the
+ * index stay usable.  The request is a word of page-locked host memory
+ * mapped for the device (a read crosses the host link); bang_abort_set is
+ * a plain host store and may be called from any thread while the search
+ * runs.
+ *  - create: allocates the request, cleared.  Errors: ENOMEM, EDEVICE.
+ *  - destroy: frees it (NULL is a no-op); no search carrying it may still
+ *    be running.
+ *  - set: asks every search carrying it to stop.
+ *  - clear: withdraws the request and forgets that a search stopped.
+ *  - status: after the caller has synchronised the search's stream,
+ *    BANG_EABORTED if a search carrying the request stopped a query
+ *    because of it since the last clear, else BANG_OK (EINVAL for NULL). */
+int bang_abort_create(bang_abort** out);
+int bang_abort_destroy(bang_abort* ab);
+int bang_abort_set(bang_abort* ab);
+int bang_abort_clear(bang_abort* ab);
+int bang_abort_status(const bang_abort* ab);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char* bang_last_error(void);

@@ -31,7 +31,9 @@ EXPORTS = ("bang_index_create", "bang_index_destroy", "bang_build_pq_tables",
            "bang_search", "bang_rerank", "bang_index_probe",
            "bang_server_create",
            "bang_server_destroy", "bang_server_submit", "bang_server_wait",
-           "bang_server_replay", "bang_server_stats", "bang_last_error")
+           "bang_server_replay", "bang_server_stats", "bang_abort_create",
+           "bang_abort_destroy", "bang_abort_set", "bang_abort_clear",
+           "bang_abort_status", "bang_last_error")
 
 
 class BangError(RuntimeError):
@@ -56,7 +58,8 @@ class SearchOpts(ctypes.Structure):
                 ("out_times", ctypes.c_void_p),
                 ("table", ctypes.c_uint32), ("flags", ctypes.c_uint32),
                 ("query_L", ctypes.c_void_p), ("query_k", ctypes.c_void_p),
-                ("filter", ctypes.c_uint32), ("out_phases", ctypes.c_void_p)]
+                ("filter", ctypes.c_uint32), ("out_phases", ctypes.c_void_p),
+                ("abort", ctypes.c_void_p)]
 
 
 class ServerOpts(ctypes.Structure):
@@ -95,6 +98,10 @@ def lib():
         L.bang_server_wait.argtypes = [P, u64, P, P, ctypes.c_int]
         L.bang_server_replay.argtypes = [P, P, u32, P, P, P, P, u32, P, P, P]
         L.bang_server_stats.argtypes = [P, P, u32]
+        L.bang_abort_create.argtypes = [ctypes.POINTER(P)]
+        for f in ("bang_abort_destroy", "bang_abort_set", "bang_abort_clear",
+                  "bang_abort_status"):
+            getattr(L, f).argtypes = [P]
         for f in EXPORTS[:-1]:
             getattr(L, f).restype = ctypes.c_int
         L.bang_last_error.argtypes = []
@@ -214,7 +221,7 @@ class Index:
                want_times: bool = False, table: str = "f32",
                rerank_global: bool = False, query_L=None, query_k=None,
                filter: str = "exact", want_phases: bool = False, out=None,
-               stream=None):
+               abort=None, stream=None):
         """Stages 1-3.  Returns (ids uint32-as-int32 [nq][k], dists
         float32 [nq][k]) and, on request, the expanded nodes [nq][want_cand]
         `table` is the PQ table storage the search ranks by: "f32", the
@@ -227,7 +234,8 @@ class Index:
         "exact" (set union, the default) or "bloom" (the paper's Bloom
         filter, BANG_FILTER_BLOOM).  want_phases adds per-query cycles of
         the search's seven phases [nq][7] (bang_search_opts.out_phases;
-        a timed copy of the search)."""
+        a timed copy of the search).  abort: a StopRequest the search
+        obeys (bang_search_opts.abort)."""
         import torch
         qp = self._queries(q)
         nq = q.shape[0]
@@ -240,6 +248,8 @@ class Index:
         opts = SearchOpts(c_max, iter_cap, None, 0, None, None, TABLES[table],
                           1 if rerank_global else 0)
         opts.filter = FILTERS[filter]
+        if abort is not None:
+            opts.abort = abort._h.value
         for t, nm in ((query_L, "query_L"), (query_k, "query_k")):
             if t is not None:
                 if tuple(t.shape) != (nq,):
@@ -312,6 +322,44 @@ class Index:
             cand.shape[1], k, _dev_ptr(ids, torch.int32, "ids"),
             _dev_ptr(dists, torch.float32, "dists"), _stream(stream)))
         return ids, dists
+
+
+class StopRequest:
+    """A stop request (bang_abort_*): set() asks every search that carries
+    it to stop soon (each wave leaves after its current expansion; rows of
+    stopped or unstarted queries are padding with status 2); stopped()
+    tells, after the search's stream has been synchronised, whether a
+    search stopped a query because of it; clear() re-arms it."""
+
+    def __init__(self):
+        self._h = None
+        h = ctypes.c_void_p()
+        _check(lib().bang_abort_create(ctypes.byref(h)))
+        self._h = h
+
+    def set(self):
+        _check(lib().bang_abort_set(self._h))
+
+    def clear(self):
+        _check(lib().bang_abort_clear(self._h))
+
+    def stopped(self) -> bool:
+        rc = lib().bang_abort_status(self._h)
+        if rc == -5:
+            return True
+        _check(rc)
+        return False
+
+    def close(self):
+        if self._h is not None and _lib is not None:
+            lib().bang_abort_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Server:

@@ -39,6 +39,14 @@ const char* last_error();
 
 }  // namespace bang
 
+// A stop request: two words of coherent, mapped, page-locked host memory,
+// [0] the request (host writes, device reads) and [1] set by the device
+// when a query stopped because of it.
+struct bang_abort {
+  uint32_t* host = nullptr;
+  uint32_t* dev = nullptr;  // the same words as the device addresses them
+};
+
 struct bang_index {
   int device = 0;
   bang::DeviceIndex dev{};

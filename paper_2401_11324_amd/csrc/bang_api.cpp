@@ -425,6 +425,10 @@ int search_with(bang_index* ix, Workspace* ws, bool grow, const void* queries,
   l.qcounter = ws->qcounter;
   l.bloom = filter == BANG_FILTER_BLOOM ? ws->bloom : nullptr;
   l.bloom_epoch = filter == BANG_FILTER_BLOOM ? ws->bloom_epoch : nullptr;
+  if (o && o->abort) {
+    l.abort_flag = o->abort->dev;
+    l.abort_fired = o->abort->dev + 1;
+  }
   l.grid = (uint32_t)grid;
   hipError_t e = bang::launch_search(ix->dev, l, s);
   if (e != hipSuccess) return hip_fail(e, "search launch");
@@ -530,6 +534,66 @@ int bang_index_probe(bang_index* ix, uint64_t nreads, uint64_t seed,
   } catch (...) {
     return fail(BANG_ENOMEM, "exception");
   }
+}
+
+int bang_abort_create(bang_abort** out) {
+  try {
+    if (!out) return fail(BANG_EINVAL, "null argument");
+    *out = nullptr;
+    auto* ab = new (std::nothrow) bang_abort();
+    if (!ab) return fail(BANG_ENOMEM, "host allocation");
+    // coherent: the device's reads and writes bypass its caches, so a host
+    // store is seen by the next reading and the device's store by the host
+    hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&ab->host),
+                                 2 * sizeof(uint32_t),
+                                 hipHostMallocMapped | hipHostMallocCoherent);
+    if (e != hipSuccess) {
+      delete ab;
+      return fail(BANG_ENOMEM, std::string("stop request: ") +
+                                   hipGetErrorString(e));
+    }
+    __atomic_store_n(&ab->host[0], 0u, __ATOMIC_SEQ_CST);
+    __atomic_store_n(&ab->host[1], 0u, __ATOMIC_SEQ_CST);
+    void* dptr = nullptr;
+    e = hipHostGetDevicePointer(&dptr, ab->host, 0);
+    if (e != hipSuccess) {
+      (void)hipHostFree(ab->host);
+      delete ab;
+      return hip_fail(e, "hipHostGetDevicePointer");
+    }
+    ab->dev = static_cast<uint32_t*>(dptr);
+    *out = ab;
+    return BANG_OK;
+  } catch (...) {
+    return fail(BANG_ENOMEM, "exception");
+  }
+}
+
+int bang_abort_destroy(bang_abort* ab) {
+  if (!ab) return BANG_OK;
+  (void)hipHostFree(ab->host);
+  delete ab;
+  return BANG_OK;
+}
+
+int bang_abort_set(bang_abort* ab) {
+  if (!ab) return fail(BANG_EINVAL, "null stop request");
+  __atomic_store_n(&ab->host[0], 1u, __ATOMIC_SEQ_CST);
+  return BANG_OK;
+}
+
+int bang_abort_clear(bang_abort* ab) {
+  if (!ab) return fail(BANG_EINVAL, "null stop request");
+  __atomic_store_n(&ab->host[0], 0u, __ATOMIC_SEQ_CST);
+  __atomic_store_n(&ab->host[1], 0u, __ATOMIC_SEQ_CST);
+  return BANG_OK;
+}
+
+int bang_abort_status(const bang_abort* ab) {
+  if (!ab) return fail(BANG_EINVAL, "null stop request");
+  if (__atomic_load_n(&ab->host[1], __ATOMIC_SEQ_CST))
+    return fail(BANG_EABORTED, "a search stopped on the stop request");
+  return BANG_OK;
 }
 
 const char* bang_last_error(void) { return bang::last_error(); }

@@ -256,6 +256,8 @@ hipError_t launch_search(const DeviceIndex& ix, const SearchLaunch& l,
   a.cscratch = l.cscratch;
   a.bloom = l.bloom;
   a.bloom_epoch = l.bloom_epoch;
+  a.abort_flag = l.abort_flag;
+  a.abort_fired = l.abort_fired;
   a.qcounter = l.qcounter;
   const int dt = ix.dtype;
   const uint32_t m = ix.m, ds = ix.d / ix.m;

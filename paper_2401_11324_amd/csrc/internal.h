@@ -42,6 +42,8 @@ struct SearchLaunch {
   uint32_t* out_phases;  // [nq][7] per-phase cycles (timed variant) or null
   uint32_t* bloom;       // null (exact filter) or [grid][BANG_BLOOM_Z]
   uint32_t* bloom_epoch; // [grid] query epoch of each wave's filter
+  const uint32_t* abort_flag;  // device view of a bang_abort, or null
+  uint32_t* abort_fired;
   uint32_t grid;         // workgroups (one wave each)
 };
 

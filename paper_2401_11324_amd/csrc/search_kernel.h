@@ -823,6 +823,11 @@ struct SearchArgs {
   uint32_t* qcounter;
   uint32_t* bloom;        // null, or [grid][kBloomZ] filter entries
   uint32_t* bloom_epoch;  // [grid]
+  // null, or a stop request in host memory (coherent, mapped): polled at
+  // every query's start and every kAbortPoll expansions; abort_fired is
+  // set when a query is cut short or skipped because of it
+  const uint32_t* abort_flag;
+  uint32_t* abort_fired;
 };
 
 namespace {
@@ -831,6 +836,24 @@ namespace {
 // capped at kPer; inside one, lane l owns the B entries
 // [base + B*l, base + B*l + B).  L <= 256 is a single super-row.
 constexpr int kPer = 4;
+
+// Expansions between two readings of the stop request: a reading crosses
+// the host link, so it is rare and issued well before it is needed.
+constexpr uint32_t kAbortPoll = 64;
+
+// The host's stop request, read past every cache; the same word on every
+// lane, returned wave-uniform.
+__device__ __forceinline__ uint32_t abort_requested(const uint32_t* flag) {
+  const uint32_t v =
+      __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  return __builtin_amdgcn_readfirstlane(v);
+}
+
+// Records on the host that a query stopped because of the request.
+__device__ __forceinline__ void abort_record(uint32_t* fired, int lane) {
+  if (lane == 0)
+    __hip_atomic_store(fired, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
 
 // Adjacency row of node u and, in the same row, the codes of its
 // neighbours: one coalesced load per lane, no dependent gather.  With a
@@ -1014,8 +1037,28 @@ void search_kernel(SearchArgs a) {
       }
       break;
     }
-    const unsigned char* q = a.queries + (size_t)qi * D * Elem<DT>::size;
     const uint64_t t_begin = a.out_times ? wall_clock64() : 0;
+    if (a.abort_flag && abort_requested(a.abort_flag)) {
+      // stopped: this query is not searched; its row is padding, status 2
+      uint32_t* oid = a.out_ids + (size_t)qi * a.k;
+      float* od = a.out_dists + (size_t)qi * a.k;
+      for (uint32_t i = lane; i < a.k; i += kWave) {
+        oid[i] = kNone;
+        od[i] = __uint_as_float(0x7F800000u);
+      }
+      if (a.out_counters && lane < 4)
+        a.out_counters[qi * 4 + lane] = lane == 1 ? 2u : 0u;
+      if (a.out_cand)
+        for (uint32_t i = lane; i < a.cand_stride; i += kWave)
+          a.out_cand[(size_t)qi * a.cand_stride + i] = kNone;
+      if (a.out_times && lane == 0) {
+        a.out_times[qi * 2] = t_begin;
+        a.out_times[qi * 2 + 1] = wall_clock64();
+      }
+      abort_record(a.abort_fired, lane);
+      continue;
+    }
+    const unsigned char* q = a.queries + (size_t)qi * D * Elem<DT>::size;
     uint64_t ph[kPhases] = {0, 0, 0, 0, 0, 0, 0};
     uint64_t tp = PHASES ? phase_clock() : 0, t4 = 0;
     // this query's worklist size, result count, iteration cap and c_max
@@ -1098,6 +1141,9 @@ void search_kernel(SearchArgs a) {
     // the expanded keys, written to C 64 at a time: lane e holds that of
     // expansion e mod 64 until its group of 64 is stored
     uint64_t ckey = 0;
+    // the last reading of the stop request (taken every kAbortPoll
+    // expansions, used one expansion later)
+    uint32_t abw = 0;
     __syncthreads();
 
     if constexpr (PHASES) {
@@ -1107,6 +1153,10 @@ void search_kernel(SearchArgs a) {
     while (cur != kNone) {
       if (iters == capq) {
         status = 1;
+        break;
+      }
+      if (abw) {
+        status = 2;
         break;
       }
       if constexpr (PHASES) tp = phase_clock();
@@ -1133,6 +1183,10 @@ void search_kernel(SearchArgs a) {
       // distances of the neighbours (row of u*, loaded earlier)
       nb = row_mask(a, lane, nb);
       keep_alive(touched);
+      // read the stop request now and then; the reading is complete by the
+      // time the next row is, where the loop looks at it
+      if (a.abort_flag && (iters & (kAbortPoll - 1)) == 1)
+        abw = abort_requested(a.abort_flag);
       if constexpr (PHASES) {
         keep_alive(nb);
         const uint64_t t = phase_clock();
@@ -1420,7 +1474,14 @@ void search_kernel(SearchArgs a) {
     uint32_t nc = iters;
     uint32_t* oid = a.out_ids + (size_t)qi * a.k;
     float* od = a.out_dists + (size_t)qi * a.k;
-    if constexpr (kExact) {
+    if (status == 2) {
+      // cut short by the stop request: no re-rank, the row is padding
+      for (uint32_t i = lane; i < kq; i += kWave) {
+        oid[i] = kNone;
+        od[i] = __uint_as_float(0x7F800000u);
+      }
+      abort_record(a.abort_fired, lane);
+    } else if constexpr (kExact) {
       // no re-rank: the worklist already ranks by exact distance
       for (uint32_t i = lane; i < kq; i += kWave) {
         const uint64_t key = i < Llen ? Lc[i] : kInf;

@@ -929,3 +929,152 @@ def test_bloom_filter_equals_exact_filter_without_collisions(small_indexes,
         torch.cuda.synchronize()
         for x, y in zip(a, b):
             assert np.array_equal(x.cpu().numpy(), y.cpu().numpy()), (k, L)
+
+
+# --------------------------------------------------------------------------
+# stop requests and bounded waits
+# --------------------------------------------------------------------------
+def test_stop_request_set_before_the_launch_pads_every_query(small_indexes):
+    """A search carrying a stop request that is already set searches
+    nothing: every row is padding with status 2, the request reports that
+    it stopped the search, and once cleared the same index searches
+    normally (the persistent launch left its counters at zero)."""
+    ix, q, gi = small_indexes["u8-d128-m32"]
+    bang = bang_mod()
+    ab = bang.StopRequest()
+    assert not ab.stopped()
+    ab.set()
+    ids, d, cand, cnt = gi.search(to_dev(q), 10, 64, want_cand=8,
+                                  want_counters=True, abort=ab)
+    torch.cuda.synchronize()
+    assert (u32(ids) == NONE).all() and np.isinf(d.cpu().numpy()).all()
+    assert (u32(cand) == NONE).all()
+    c = u32(cnt)
+    assert (c[:, 0] == 0).all() and (c[:, 1] == 2).all()
+    assert ab.stopped()
+    ab.clear()
+    assert not ab.stopped()
+    run_and_compare(ix, gi, q, 10, 64, label="after a stopped launch")
+    ab.close()
+
+
+def test_stop_request_ends_a_long_launch_early(small_indexes):
+    """Set from the host while a long persistent launch runs: the launch
+    ends early, every query is either finished (status 0, the result of a
+    search without the request) or stopped (status 2, padding), and the
+    index searches normally afterwards."""
+    import time
+    ix, q, gi = small_indexes["u8-d128-m32"]
+    bang = bang_mod()
+    k, L, reps = 10, 1024, 1500
+    qrep = to_dev(np.tile(q, (reps, 1)))
+    nq = qrep.shape[0]
+    ref_ids, ref_d = _alone(gi, q, k, L, "f32")
+    ab = bang.StopRequest()
+    ids, d, cnt = gi.search(qrep, k, L, want_counters=True, abort=ab)
+    torch.cuda.synchronize()          # warm: the workspace has grown
+    t0 = time.perf_counter()
+    gi.search(qrep, k, L, want_counters=True, abort=ab, out=(ids, d))
+    torch.cuda.synchronize()
+    full = time.perf_counter() - t0
+    assert not ab.stopped()
+    assert (u32(cnt)[:, 1] == 0).all()
+    print(f"full launch: {nq} queries in {full * 1e3:.1f} ms", flush=True)
+    t0 = time.perf_counter()
+    _, _, cnt = gi.search(qrep, k, L, want_counters=True, abort=ab,
+                          out=(ids, d))
+    time.sleep(full * 0.2)
+    ab.set()
+    torch.cuda.synchronize()
+    cut = time.perf_counter() - t0
+    st = u32(cnt)[:, 1]
+    got_ids, got_d = u32(ids), d.cpu().numpy()
+    print(f"stopped launch: {cut * 1e3:.1f} ms, {int((st == 0).sum())} "
+          f"finished, {int((st == 2).sum())} stopped", flush=True)
+    assert set(np.unique(st).tolist()) <= {0, 2}
+    assert (st == 2).any() and ab.stopped()
+    assert cut < 0.8 * full
+    fin = np.where(st == 0)[0]
+    assert np.array_equal(got_ids[fin], ref_ids[fin % len(q)])
+    assert np.array_equal(f32bits(got_d[fin]), f32bits(ref_d[fin % len(q)]))
+    stop = np.where(st == 2)[0]
+    assert (got_ids[stop] == NONE).all() and np.isinf(got_d[stop]).all()
+    ab.clear()
+    run_and_compare(ix, gi, q, 10, 64, label="after an interrupted launch")
+    ab.close()
+
+
+def test_server_wait_with_zero_timeout_keeps_the_ticket(small_indexes):
+    """A wait that times out (timeout_ms = 0 on a request still queued
+    behind a long one on the only slot) returns EABORTED and leaves the
+    ticket valid: a later wait collects the request's results."""
+    ix, q, gi = small_indexes["u8-d128-m32"]
+    bang = bang_mod()
+    big = np.tile(q, (200, 1))
+    sv = bang.Server(gi, max_batch=len(big), slots=1, max_k=10, max_L=1024)
+    t1 = sv.submit(big, 10, 1024)
+    t2 = sv.submit(q[:5], 10, 64)
+    with pytest.raises(bang.BangError) as e:
+        sv.wait(t2, timeout_ms=0)
+    assert e.value.code == -5
+    ids2, d2 = sv.wait(t2)
+    a_ids, a_d = _alone(gi, q[:5], 10, 64, "f32")
+    assert np.array_equal(ids2, a_ids)
+    assert np.array_equal(f32bits(d2), f32bits(a_d))
+    ids1, _ = sv.wait(t1, timeout_ms=60000)
+    b_ids, _ = _alone(gi, q, 10, 1024, "f32")
+    assert np.array_equal(ids1, np.tile(b_ids, (200, 1)))
+    sv.close()
+
+
+def test_server_many_tickets_and_concurrent_waits(small_indexes):
+    """Threads hold many tickets at once (the server's ticket table grows
+    while others wait on it), and two threads waiting on one ticket: one
+    collects it, the other is told it was already collected."""
+    import threading
+    ix, q, gi = small_indexes["u8-d64-m16"]
+    bang = bang_mod()
+    sv = bang.Server(gi, max_batch=32, slots=2, max_k=10, max_L=64)
+    ref_ids, _ = _alone(gi, q, 10, 64, "f32")
+    errors = []
+
+    def worker(seed):
+        r = np.random.default_rng(seed)
+        try:
+            pend = []
+            for _ in range(40):
+                sel = r.integers(0, len(q), int(r.integers(1, 4)))
+                pend.append((sv.submit(q[sel], 10, 64), sel))
+            for t, sel in reversed(pend):
+                got, _ = sv.wait(t)
+                if not np.array_equal(got, ref_ids[sel]):
+                    errors.append((seed, t))
+        except Exception as ex:  # surfaced below
+            errors.append(repr(ex))
+
+    th = [threading.Thread(target=worker, args=(s,)) for s in range(6)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    assert not errors, errors
+    t = sv.submit(q[:3], 10, 64)
+    outcome = []
+
+    def waiter():
+        try:
+            outcome.append(("ok", sv.wait(t)[0]))
+        except bang.BangError as ex:
+            outcome.append(("err", ex.code))
+
+    ws = [threading.Thread(target=waiter) for _ in range(2)]
+    for w in ws:
+        w.start()
+    for w in ws:
+        w.join()
+    kinds = sorted(o[0] for o in outcome)
+    assert kinds == ["err", "ok"], outcome
+    assert [o[1] for o in outcome if o[0] == "err"] == [-1]
+    got = [o[1] for o in outcome if o[0] == "ok"][0]
+    assert np.array_equal(got, ref_ids[:3])
+    sv.close()
