@@ -220,7 +220,7 @@ def deep_section(a, bang, torch):
         return {"skipped": f"index files for {w.name} are missing; write "
                            f"them with `python -m oracle.build_index "
                            f"{w.name}`"}
-    run = Runner(w, a, bang, torch)
+    run = Runner(w, a, bang, torch, bf16_base=True)
     forms = TABLES + ("exact",)
     rows = run.sweep(forms)
     by = {(r["table"], r["L"]): r["recall10"] for r in rows}
@@ -234,8 +234,14 @@ def deep_section(a, bang, torch):
             rec["recall_lost_vs_f32_same_L"] = round(
                 by[("f32", rec["L"])] - by[(t, rec["L"])], 4)
         out["forms"][t] = rec
+    # the BF16 re-rank with the FP32 recheck, at each PQ form's point
+    for t in TABLES:
+        rec = run.measure(t, out["forms"][t]["L"], rerank="bf16")
+        rec["recall_equal_to_exact_rerank"] = rec["recall10"] == \
+            out["forms"][t]["recall10"]
+        out["forms"][t + "+bf16_rerank"] = rec
     base = out["forms"]["f32"]["qps"]
-    for t in forms:
+    for t in out["forms"]:
         out["forms"][t]["speedup_vs_f32"] = round(
             out["forms"][t]["qps"] / base, 3)
     run.gi.close()
@@ -564,13 +570,13 @@ class Runner:
     """One workload's index on the GPU, its recall sweep over L and the
     timed measurement of one table form at one L."""
 
-    def __init__(self, w, a, bang, torch):
+    def __init__(self, w, a, bang, torch, bf16_base=False):
         from synth import store
         self.w, self.a, self.torch = w, a, torch
         self.d = store.load(w)
         d = self.d
         self.gi = bang.Index(d["base"], d["adj"], d["medoid"],
-                             d["codebooks"], d["codes"])
+                             d["codebooks"], d["codes"], bf16_base=bf16_base)
         self.dev = torch.device("cuda:0")
         self.q = torch.from_numpy(d["queries"]).to(self.dev)
         self.gt = d["gt_ids"]
@@ -639,7 +645,35 @@ class Runner:
                 "mean": float(e.mean()),
                 "p99": float(np.percentile(e, 99))}
 
-    def measure(self, table, L, index=None, filter="exact"):
+    def bf16_error(self, cand, iters, nq=100, per_q=128):
+        """Relative error against FP64 of the distances the BF16 re-rank
+        sums first (bfloat16 rows, FP32 sums in coordinate order) and of
+        the canonical FP32 distances, over the first nq queries and up to
+        per_q of each one's expanded nodes."""
+        base, qs = self.d["base"], self.d["queries"]
+        e16, e32 = [], []
+        for i in range(nq):
+            ex = cand[i, :min(int(iters[i]), per_q)]
+            x = base[ex]
+            b = x.view(np.uint32).astype(np.uint64)
+            b = ((b + 0x7FFF + ((b >> 16) & 1)) >> 16) << 16
+            xb = b.astype(np.uint32).view(np.float32)
+            q = qs[i]
+            ref = ((x.astype(np.float64) - q.astype(np.float64)) ** 2).sum(1)
+            acc16 = np.zeros(len(ex), dtype=np.float32)
+            acc32 = np.zeros(len(ex), dtype=np.float32)
+            for t in range(x.shape[1]):
+                acc16 = acc16 + (xb[:, t] - q[t]) * (xb[:, t] - q[t])
+                acc32 = acc32 + (x[:, t] - q[t]) * (x[:, t] - q[t])
+            den = np.maximum(ref, 1e-30)
+            e16.append(np.abs(acc16 - ref) / den)
+            e32.append(np.abs(acc32 - ref) / den)
+        e16, e32 = np.concatenate(e16), np.concatenate(e32)
+        return {"pairs": int(e16.size), "bf16_max": float(e16.max()),
+                "bf16_mean": float(e16.mean()),
+                "fp32_max": float(e32.max()), "fp32_mean": float(e32.mean())}
+
+    def measure(self, table, L, index=None, filter="exact", rerank="exact"):
         """K timed steps of one form; returns its record."""
         torch, w, a = self.torch, self.w, self.a
         gi_ = index or self.gi
@@ -649,14 +683,16 @@ class Runner:
         ids = torch.empty((nq, k), dtype=torch.int32, device=dev)
         dist = torch.empty((nq, k), dtype=torch.float32, device=dev)
         for _ in range(a.warmup):
-            gi_.search(q, k, L, out=(ids, dist), table=table, filter=filter)
+            gi_.search(q, k, L, out=(ids, dist), table=table, filter=filter,
+                       rerank=rerank)
         torch.cuda.synchronize()
         ev = [(torch.cuda.Event(enable_timing=True),
                torch.cuda.Event(enable_timing=True)) for _ in range(a.steps)]
         wall0 = time.perf_counter()
         for e0, e1 in ev:
             e0.record(stream)
-            gi_.search(q, k, L, out=(ids, dist), table=table, filter=filter)
+            gi_.search(q, k, L, out=(ids, dist), table=table, filter=filter,
+                       rerank=rerank)
             e1.record(stream)
         torch.cuda.synchronize()
         wall = time.perf_counter() - wall0
@@ -674,7 +710,7 @@ class Runner:
         _, _, cand, cnt, times = gi_.search(q, k, L, want_cand=cap,
                                            want_counters=True,
                                            want_times=True, table=table,
-                                           filter=filter)
+                                           filter=filter, rerank=rerank)
         torch.cuda.synchronize()
         cand = cand.cpu().numpy().view(np.uint32)
         cnt = cnt.cpu().numpy()
@@ -699,7 +735,7 @@ class Runner:
         design = packed_row_bytes(self.adj_deg, w.R, w.m, w.d, self.elem, k,
                                   iters, cand, 4 * L, exact=exact)
         ms_step = wall * 1e3 / a.steps
-        recd = {"table": table, "L": L, "filter": filter,
+        recd = {"table": table, "L": L, "filter": filter, "rerank": rerank,
                 "recall10": round(rec, 4),
                 "adjacency_bytes_per_launch": int(iters.astype(np.int64).sum()
                                                   * 4 * w.R),
@@ -720,6 +756,14 @@ class Runner:
                 else 0.0}
         if not exact:
             recd["adc_rel_err_vs_fp64"] = self.adc_error(table, cand, iters)
+        if rerank == "bf16":
+            ncand = np.minimum(iters.astype(np.int64), 4 * L)
+            recd["bf16_rerank"] = {
+                "rechecked_fp32": int(cnt[:, 2].astype(np.int64).sum()),
+                "candidates": int(ncand.sum()),
+                "rechecked_frac": round(float(cnt[:, 2].astype(np.int64).sum()
+                                              / max(1, ncand.sum())), 4),
+                "bf16_dist_rel_err_vs_fp64": self.bf16_error(cand, iters)}
         if nprime is not None:
             B, parts = method_bytes(nprime, w.R, w.m, w.d, self.elem, k,
                                     iters, 4 * L, exact=exact)

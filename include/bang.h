@@ -75,7 +75,7 @@ typedef struct {
   uint32_t m;               /* PQ subspaces; m divides d */
   const float* codebooks;   /* [m][256][d/m] FP32 centroids */
   const uint8_t* codes;     /* [n][m] centroid ids */
-  uint32_t flags;           /* 0 or BANG_INDEX_HOST_ADJ */
+  uint32_t flags;           /* 0, BANG_INDEX_HOST_ADJ, BANG_INDEX_BF16_BASE */
 } bang_index_desc;
 
 /* Index flag: keep the adjacency in pinned host memory instead of device
@@ -89,6 +89,13 @@ typedef struct {
  * same as with a device-resident graph. */
 #define BANG_INDEX_HOST_ADJ 1u
 
+/* Index flag, float data with d a multiple of 8: also keep the base rounded
+ * to bfloat16 (nearest, ties to even; 2 bytes a coordinate) and the sum of
+ * squares of each rounded row (FP32, coordinates in order), for the
+ * precision form's re-rank (bang_search_opts.rerank = BANG_RERANK_BF16).
+ * Device memory: n*d*2 + n*4 bytes more. */
+#define BANG_INDEX_BF16_BASE 2u
+
 /* Optional search outputs for inspection; NULL pointers are skipped. */
 typedef struct {
   uint32_t c_max;           /* re-rank candidates kept (0 = 4*L): when more
@@ -99,9 +106,11 @@ typedef struct {
   uint32_t* out_cand;       /* device [nq][cand_stride]: expanded node ids in
                                expansion order, BANG_NONE padded */
   uint32_t cand_stride;
-  uint32_t* out_counters;   /* device [nq][4]: {iterations, status, 0, 0};
-                               status 0 converged, 1 stopped at iter_cap,
-                               2 stopped by the stop request (abort) */
+  uint32_t* out_counters;   /* device [nq][4]: {iterations, status,
+                               rechecked, 0}; status 0 converged, 1 stopped
+                               at iter_cap, 2 stopped by the stop request
+                               (abort); rechecked: with BANG_RERANK_BF16 the
+                               candidates given an FP32 distance, else 0 */
   uint64_t* out_times;      /* device [nq][2]: device wall-clock ticks when
                                the query's work began and when its results
                                were written (hipDeviceAttributeWallClockRate
@@ -142,7 +151,25 @@ typedef struct {
                                yet started is written the same way without
                                being searched.  Queries that finished before
                                keep their results. */
+  uint32_t rerank;          /* BANG_RERANK_EXACT (default) or
+                               BANG_RERANK_BF16 */
 } bang_search_opts;
+
+/* Re-rank forms (float data; integer data is always re-ranked exactly).
+ *  - EXACT: the canonical FP32 distance of every candidate.
+ *  - BF16: the precision form's re-rank, same answer.  Each candidate's
+ *    distance D~ is first summed in FP32 from its bfloat16 row (half the
+ *    bytes); with B its row's sum of squares, E = 2^-6 sqrt(B D~) +
+ *    2^-15 B + 2^-12 D~ bounds the gap to its canonical FP32 distance
+ *    (d <= 1024).  Every candidate whose D~ - E is at most the k-th
+ *    smallest D~ + E, the only ones that can be among the k nearest, is
+ *    recomputed in FP32 from the float row, and the k nearest of those by
+ *    (FP32 distance, id) are returned: ids and distances equal EXACT's.
+ *    Needs an index created with BANG_INDEX_BF16_BASE and a PQ table form.
+ *    The re-rank falls back to EXACT when its arrays do not fit on chip
+ *    (about 8 bytes per candidate more than EXACT). */
+#define BANG_RERANK_EXACT 0u
+#define BANG_RERANK_BF16 1u
 
 /* Visited filters.
  *  - EXACT: set union into the worklist (Algorithm 1): a neighbour already

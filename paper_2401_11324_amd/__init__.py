@@ -23,6 +23,9 @@ MAX_R = 64
 DTYPES = {"f32": 0, "u8": 1, "i8": 2}
 TABLES = {"f32": 0, "f16": 1, "u8": 2, "exact": 3}
 INDEX_HOST_ADJ = 1
+INDEX_BF16_BASE = 2
+# re-rank forms (bang.h BANG_RERANK_*)
+RERANKS = {"exact": 0, "bf16": 1}
 # visited filters (bang.h BANG_FILTER_*)
 FILTERS = {"exact": 0, "bloom": 1}
 ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EUNSUPPORTED",
@@ -59,7 +62,7 @@ class SearchOpts(ctypes.Structure):
                 ("table", ctypes.c_uint32), ("flags", ctypes.c_uint32),
                 ("query_L", ctypes.c_void_p), ("query_k", ctypes.c_void_p),
                 ("filter", ctypes.c_uint32), ("out_phases", ctypes.c_void_p),
-                ("abort", ctypes.c_void_p)]
+                ("abort", ctypes.c_void_p), ("rerank", ctypes.c_uint32)]
 
 
 class ServerOpts(ctypes.Structure):
@@ -152,10 +155,12 @@ class Index:
     base [n][d] (float32 / uint8 / int8), adj [n][R] uint32 (BANG_NONE for
     empty slots), medoid, codebooks [m][256][d/m] float32, codes [n][m]
     uint8.  host_adj=True keeps the adjacency in pinned host memory, read
-    by the search across the host link (BANG_INDEX_HOST_ADJ)."""
+    by the search across the host link (BANG_INDEX_HOST_ADJ); bf16_base=True
+    (float data) also keeps the base in bfloat16 for the BF16 re-rank
+    (BANG_INDEX_BF16_BASE)."""
 
     def __init__(self, base, adj, medoid, codebooks, codes,
-                 host_adj: bool = False):
+                 host_adj: bool = False, bf16_base: bool = False):
         self._h = None
         self._sink = None  # device word the probe kernel may write
         base = np.ascontiguousarray(base)
@@ -175,7 +180,8 @@ class Index:
         desc = IndexDesc(n, d, DTYPES[dt], base.ctypes.data, adj.shape[1],
                          adj.ctypes.data, int(medoid), codes.shape[1],
                          cb.ctypes.data, codes.ctypes.data,
-                         INDEX_HOST_ADJ if host_adj else 0)
+                         (INDEX_HOST_ADJ if host_adj else 0) |
+                         (INDEX_BF16_BASE if bf16_base else 0))
         if adj.shape[0] != n or codes.shape[0] != n:
             raise ValueError("adj and codes need one row per base vector")
         if cb.shape != (self.m, 256, d // max(1, self.m)):
@@ -221,7 +227,7 @@ class Index:
                want_times: bool = False, table: str = "f32",
                rerank_global: bool = False, query_L=None, query_k=None,
                filter: str = "exact", want_phases: bool = False, out=None,
-               abort=None, stream=None):
+               abort=None, rerank: str = "exact", stream=None):
         """Stages 1-3.  Returns (ids uint32-as-int32 [nq][k], dists
         float32 [nq][k]) and, on request, the expanded nodes [nq][want_cand]
         `table` is the PQ table storage the search ranks by: "f32", the
@@ -235,7 +241,9 @@ class Index:
         filter, BANG_FILTER_BLOOM).  want_phases adds per-query cycles of
         the search's seven phases [nq][7] (bang_search_opts.out_phases;
         a timed copy of the search).  abort: a StopRequest the search
-        obeys (bang_search_opts.abort)."""
+        obeys (bang_search_opts.abort).  rerank: "exact" or "bf16" (float
+        data on an index with bf16_base; the same answer, counters[:, 2]
+        the candidates recomputed in FP32)."""
         import torch
         qp = self._queries(q)
         nq = q.shape[0]
@@ -250,6 +258,7 @@ class Index:
         opts.filter = FILTERS[filter]
         if abort is not None:
             opts.abort = abort._h.value
+        opts.rerank = RERANKS[rerank]
         for t, nm in ((query_L, "query_L"), (query_k, "query_k")):
             if t is not None:
                 if tuple(t.shape) != (nq,):

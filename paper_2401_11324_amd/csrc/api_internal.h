@@ -55,6 +55,8 @@ struct bang_index {
   uint32_t* h_adj = nullptr;  // pinned host adjacency (BANG_INDEX_HOST_ADJ)
   uint8_t* d_codes = nullptr;
   float* d_cb = nullptr;
+  uint16_t* d_base16 = nullptr;  // bfloat16 base (BANG_INDEX_BF16_BASE)
+  float* d_norm16 = nullptr;     // sums of squares of its rows
   bang::Workspace ws;         // used by bang_search; grown on demand
   int num_cus = 0;
   int max_lds = 64 * 1024;    // dynamic LDS bytes one workgroup may use

@@ -139,6 +139,8 @@ void free_index(bang_index* ix) {
   if (ix->h_adj) (void)hipHostFree(ix->h_adj);
   (void)hipFree(ix->d_codes);
   (void)hipFree(ix->d_cb);
+  (void)hipFree(ix->d_base16);
+  (void)hipFree(ix->d_norm16);
   bang::workspace_free(&ix->ws);
   delete ix;
 }
@@ -146,8 +148,13 @@ void free_index(bang_index* ix) {
 int create_impl(const bang_index_desc* d, bang_index** out) {
   if (!d || !out) return fail(BANG_EINVAL, "null argument");
   *out = nullptr;
-  if (d->flags & ~BANG_INDEX_HOST_ADJ)
+  if (d->flags & ~(BANG_INDEX_HOST_ADJ | BANG_INDEX_BF16_BASE))
     return fail(BANG_EINVAL, "unknown index flags");
+  if ((d->flags & BANG_INDEX_BF16_BASE) &&
+      (d->dtype != BANG_F32 || d->d % 8 != 0))
+    return fail(BANG_EUNSUPPORTED,
+                "BANG_INDEX_BF16_BASE needs float data with d a multiple "
+                "of 8");
   if (d->n == 0 || d->n >= (1ull << 31))
     return fail(BANG_EINVAL, "n must be in [1, 2^31)");
   if (d->dtype < BANG_F32 || d->dtype > BANG_I8)
@@ -251,6 +258,25 @@ int create_impl(const bang_index_desc* d, bang_index** out) {
   if (!host_adj) ix->dev.rows = ix->d_rows;
   ix->dev.codes = ix->d_codes;
   ix->dev.cb = ix->d_cb;
+  if (d->flags & BANG_INDEX_BF16_BASE) {
+    e = hipMalloc(reinterpret_cast<void**>(&ix->d_base16), nd * 2);
+    if (e == hipSuccess)
+      e = hipMalloc(reinterpret_cast<void**>(&ix->d_norm16), d->n * 4);
+    if (e != hipSuccess) {
+      free_index(ix);
+      return fail(BANG_ENOMEM, std::string("bfloat16 base: ") +
+                                   hipGetErrorString(e));
+    }
+    e = bang::launch_bf16_base(static_cast<const float*>(ix->d_base), d->n,
+                               d->d, ix->d_base16, ix->d_norm16, nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+      free_index(ix);
+      return hip_fail(e, "bfloat16 base");
+    }
+    ix->dev.base16 = ix->d_base16;
+    ix->dev.norm16 = ix->d_norm16;
+  }
   ix->dev.n = (uint32_t)d->n;
   ix->dev.d = d->d;
   ix->dev.R = d->R;
@@ -338,6 +364,15 @@ int search_with(bang_index* ix, Workspace* ws, bool grow, const void* queries,
   const uint32_t filter = o ? o->filter : BANG_FILTER_EXACT;
   if (filter > BANG_FILTER_BLOOM)
     return fail(BANG_EINVAL, "unknown visited filter");
+  const uint32_t rerank = o ? o->rerank : BANG_RERANK_EXACT;
+  if (rerank > BANG_RERANK_BF16) return fail(BANG_EINVAL, "unknown re-rank");
+  if (rerank == BANG_RERANK_BF16 && !ix->dev.base16)
+    return fail(BANG_EINVAL,
+                "BANG_RERANK_BF16 needs an index created with "
+                "BANG_INDEX_BF16_BASE");
+  if (rerank == BANG_RERANK_BF16 && table == BANG_TABLE_EXACT)
+    return fail(BANG_EINVAL,
+                "the exact-distance search has no re-rank to make BF16");
 
   size_t lds;
   uint64_t grid;
@@ -411,6 +446,7 @@ int search_with(bang_index* ix, Workspace* ws, bool grow, const void* queries,
   l.c_max = c_max;
   l.iter_cap = iter_cap;
   l.table = (int)table;
+  l.rerank_bf16 = rerank == BANG_RERANK_BF16;
   l.flags = flags;
   l.out_ids = out_ids;
   l.out_dists = out_dists;

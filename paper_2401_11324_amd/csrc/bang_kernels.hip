@@ -136,7 +136,54 @@ __global__ __launch_bounds__(256) void probe_kernel(
   if (acc == 0x2545F491u) sink[0] = wave;
 }
 
+// FP32 to bfloat16, to the nearest with ties to the even significand:
+// adding 0x7FFF plus the lowest kept bit carries into the kept bits exactly
+// when the dropped half is above the midpoint, or at it with an odd kept
+// part.  Finite inputs (the base is finite data).
+__device__ __forceinline__ uint16_t to_bf16(float x) {
+  const uint32_t b = __float_as_uint(x);
+  return (uint16_t)((b + 0x7FFFu + ((b >> 16) & 1u)) >> 16);
+}
+
+__global__ __launch_bounds__(256) void bf16_base_kernel(
+    const float* __restrict__ base, uint64_t total,
+    uint16_t* __restrict__ out) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+       i < total; i += (uint64_t)gridDim.x * blockDim.x)
+    out[i] = to_bf16(base[i]);
+}
+
+// Sum of squares of each bfloat16 row, coordinates in order, FP32.
+__global__ __launch_bounds__(256) void bf16_norm_kernel(
+    const uint16_t* __restrict__ b16, uint64_t n, uint32_t d,
+    float* __restrict__ norms) {
+  for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n;
+       r += (uint64_t)gridDim.x * blockDim.x) {
+    const uint16_t* x = b16 + r * d;
+    float acc = 0.0f;
+    for (uint32_t t = 0; t < d; ++t) {
+      const float v = __uint_as_float((uint32_t)x[t] << 16);
+      const float sq = v * v;
+      acc = acc + sq;
+    }
+    norms[r] = acc;
+  }
+}
+
 }  // namespace
+
+hipError_t launch_bf16_base(const float* base, uint64_t n, uint32_t d,
+                            uint16_t* out16, float* norms, hipStream_t s) {
+  const uint64_t total = n * d;
+  const uint32_t g1 =
+      (uint32_t)std::min<uint64_t>((total + 255) / 256, 65536);
+  hipLaunchKernelGGL(bf16_base_kernel, dim3(g1), dim3(256), 0, s, base, total,
+                     out16);
+  const uint32_t g2 = (uint32_t)std::min<uint64_t>((n + 255) / 256, 65536);
+  hipLaunchKernelGGL(bf16_norm_kernel, dim3(g2), dim3(256), 0, s, out16, n, d,
+                     norms);
+  return hipGetLastError();
+}
 
 uint32_t pow2ceil(uint32_t x) {
   uint32_t p = 1;
@@ -258,6 +305,8 @@ hipError_t launch_search(const DeviceIndex& ix, const SearchLaunch& l,
   a.bloom_epoch = l.bloom_epoch;
   a.abort_flag = l.abort_flag;
   a.abort_fired = l.abort_fired;
+  a.base16 = l.rerank_bf16 ? ix.base16 : nullptr;
+  a.norm16 = l.rerank_bf16 ? ix.norm16 : nullptr;
   a.qcounter = l.qcounter;
   const int dt = ix.dtype;
   const uint32_t m = ix.m, ds = ix.d / ix.m;

@@ -18,6 +18,9 @@ struct DeviceIndex {
   const uint32_t* hadj;       // [n][R] in pinned host memory, or null
   const uint8_t* codes;       // [n][m]
   const float* cb;            // [m][256][d/m]
+  const uint16_t* base16;     // [n][d] float base rounded to bfloat16, or
+                              // null (BANG_INDEX_BF16_BASE)
+  const float* norm16;        // [n] sum of squares of each bfloat16 row
   uint32_t n, d, R, m, medoid;
   int dtype;
 };
@@ -27,6 +30,7 @@ struct SearchLaunch {
   uint64_t nq;
   uint32_t k, L, c_max, iter_cap;
   int table;             // 0 FP32, 1 FP16, 2 U8 (bang_search_opts.table)
+  bool rerank_bf16;      // BANG_RERANK_BF16 (float data, base16 present)
   uint32_t flags;        // bang_search_opts.flags
   uint32_t* out_ids;
   float* out_dists;
@@ -82,5 +86,10 @@ hipError_t launch_rerank(const DeviceIndex& ix, const void* queries,
                          hipStream_t s);
 
 uint32_t pow2ceil(uint32_t x);
+
+// The float base rounded to bfloat16 (nearest, ties to even) and the sum of
+// squares of each rounded row (FP32, coordinates in order).
+hipError_t launch_bf16_base(const float* base, uint64_t n, uint32_t d,
+                            uint16_t* out16, float* norms, hipStream_t s);
 
 }  // namespace bang

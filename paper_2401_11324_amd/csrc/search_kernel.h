@@ -786,6 +786,153 @@ __device__ void global_select(uint64_t* C, uint32_t n, uint32_t kk, int lane) {
   }
 }
 
+// The kq-th smallest of the distinct keys S[i], i < cnt (kq <= cnt), by kq
+// rounds of a wave minimum over per-lane minima (best/at as in
+// select_and_emit); the keys taken are overwritten with kInf.
+__device__ uint64_t kth_key(uint64_t* S, uint32_t cnt, uint32_t kq,
+                            uint64_t best, uint32_t at, int lane) {
+  uint64_t m = kInf;
+  for (uint32_t r = 0; r < kq; ++r) {
+    m = wave_min64(best);
+    if (m == kInf) break;
+    if (best == m) {
+      S[at] = kInf;
+      best = kInf;
+      at = kNone;
+      for (uint32_t i = lane; i < cnt; i += kWave) {
+        const uint64_t v = S[i];
+        if (v < best) {
+          best = v;
+          at = i;
+        }
+      }
+    }
+  }
+  return m;
+}
+
+// Squared distance between a bfloat16 row and the FP32 query, summed in
+// FP32 over the coordinates in order (no FMA), the row read in one round
+// trip.
+template <int D>
+__device__ __forceinline__ float bf16_dist(const uint16_t* __restrict__ row,
+                                           const float* __restrict__ q) {
+  static_assert(D % 8 == 0, "bfloat16 rows are read 16 bytes at a time");
+  const uint4* x = reinterpret_cast<const uint4*>(row);
+  uint4 v[D / 8];
+#pragma unroll
+  for (int c = 0; c < D / 8; ++c) v[c] = x[c];
+  float acc = 0.0f;
+#pragma unroll
+  for (int c = 0; c < D / 8; ++c) {
+    const uint32_t w[4] = {v[c].x, v[c].y, v[c].z, v[c].w};
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const uint32_t h = (w[t >> 1] >> (16 * (t & 1))) & 0xFFFFu;
+      const float xb = __uint_as_float(h << 16);
+      const float diff = xb - q[8 * c + t];
+      const float sq = diff * diff;
+      acc = acc + sq;
+    }
+  }
+  return acc;
+}
+
+// The re-rank of float data from bfloat16 rows with an FP32 recheck (the
+// precision form's re-rank; the paper's is FP32, section "Re-ranking").
+// For each candidate, D~ = bf16_dist and B = its row's sum of squares give
+// the band E = 2^-6 sqrt(B D~) + 2^-15 B + 2^-12 D~, which bounds the gap
+// between D~ and the candidate's canonical FP32 distance (the rounding of
+// the row to bfloat16 moves the exact distance by at most
+// 2v sqrt(B D~) + v^2 B, v = 2^-8 / (1 - 2^-8), by Cauchy-Schwarz, and the
+// FP32 sums of d <= 1024 squares are within 6.2e-5 relative; every term of
+// E is twice that).  tau = the kq-th smallest upper bound D~ + E; only the
+// candidates whose lower bound D~ - E is <= tau can be among the kq nearest,
+// and those get their FP32 distance; the kq nearest of them by (distance,
+// id) are the FP32 re-rank's answer.  S holds the nc candidates' keys (id
+// in the low bits); it and the two arrays behind it (2 * pow2ceil(nc) keys
+// in all) are LDS.  Returns the number recomputed in FP32.  Out of line:
+// its registers stay out of the search loop's allocation.
+template <int D>
+__device__ __attribute__((noinline)) uint32_t rerank_bf16(
+    const float* __restrict__ base, const uint16_t* __restrict__ base16,
+    const float* __restrict__ norm16, uint64_t* S, uint32_t nc, uint32_t kq,
+    const float* q, uint32_t* oid, float* od, int lane) {
+  const uint32_t P = pow2ceil_dev(nc);
+  uint32_t* Id = reinterpret_cast<uint32_t*>(S + P);
+  float* Lo = reinterpret_cast<float*>(Id + P);
+  uint64_t best = kInf;
+  uint32_t at = kNone;
+#pragma unroll 1
+  for (uint32_t i = lane; i < nc; i += kWave) {
+    const uint32_t id = key_id(S[i]);
+    const float dt = bf16_dist<D>(base16 + (size_t)id * D, q);
+    const float nb = norm16[id];
+    const float e1 = __builtin_sqrtf(nb * dt) * 0.015625f;   // 2^-6
+    const float e2 = nb * 3.0517578125e-05f;                 // 2^-15
+    const float e3 = dt * 2.44140625e-04f;                   // 2^-12
+    const float E = (e1 + e2) + e3;
+    const float lo = dt - E;
+    const uint64_t key = make_key(dt + E, id);
+    Id[i] = id;
+    Lo[i] = lo > 0.0f ? lo : 0.0f;
+    S[i] = key;
+    if (key < best) {
+      best = key;
+      at = i;
+    }
+  }
+  __syncthreads();
+  float tau = __uint_as_float(0x7F800000u);
+  if (nc > kq) {
+    uint64_t tk;
+    if (kq <= kWave) {
+      tk = kth_key(S, nc, kq, best, at, lane);
+    } else {
+      for (uint32_t i = nc + lane; i < P; i += kWave) S[i] = kInf;
+      __syncthreads();
+      lds_sort(S, P, lane);
+      tk = S[kq - 1];
+    }
+    tau = key_dist(tk);
+  }
+  __syncthreads();
+  best = kInf;
+  at = kNone;
+  uint32_t cnt = 0;
+#pragma unroll 1
+  for (uint32_t i = lane; i < nc; i += kWave) {
+    uint64_t key = kInf;
+    if (Lo[i] <= tau) {
+      const uint32_t id = Id[i];
+      key = make_key(exact_dist<kF32, D, true>(base, id,
+                                                reinterpret_cast<const
+                                                unsigned char*>(q), 0),
+                     id);
+      ++cnt;
+    }
+    S[i] = key;
+    if (key < best) {
+      best = key;
+      at = i;
+    }
+  }
+  __syncthreads();
+  if (kq <= kWave)
+    select_and_emit(S, nc, kq, best, at, oid, od, lane);
+  else
+    sort_and_emit(S, nc, kq, oid, od, lane);
+  // the count, summed over the wave
+  uint32_t tot = cnt;
+  tot += dpp<0x111>(0u, tot);
+  tot += dpp<0x112>(0u, tot);
+  tot += dpp<0x114>(0u, tot);
+  tot += dpp<0x118>(0u, tot);
+  tot += dpp<0x142, 0xA>(0u, tot);
+  tot += dpp<0x143, 0xC>(0u, tot);
+  return __builtin_amdgcn_readlane(tot, kWave - 1);
+}
+
 }  // namespace
 
 // Arguments of one search launch (the same struct in every translation
@@ -828,6 +975,10 @@ struct SearchArgs {
   // set when a query is cut short or skipped because of it
   const uint32_t* abort_flag;
   uint32_t* abort_fired;
+  // float data only: base rows in bfloat16 and their sums of squares, for
+  // the re-rank with an FP32 recheck (null: the exact FP32 re-rank)
+  const uint16_t* base16;
+  const float* norm16;
 };
 
 namespace {
@@ -1472,6 +1623,7 @@ void search_kernel(SearchArgs a) {
         a.out_cand[(size_t)qi * a.cand_stride + i] =
             i < iters ? key_id(C[i]) : kNone;
     uint32_t nc = iters;
+    uint32_t rechecked = 0;  // FP32 distances of the bfloat16 re-rank
     uint32_t* oid = a.out_ids + (size_t)qi * a.k;
     float* od = a.out_dists + (size_t)qi * a.k;
     if (status == 2) {
@@ -1502,26 +1654,39 @@ void search_kernel(SearchArgs a) {
         for (uint32_t i = lane; i < nc; i += kWave) S[i] = C[i] & ~1ull;
       }
       __syncthreads();
-      // exact keys; each lane also keeps the smallest of its own
-      uint64_t best = kInf;
-      uint32_t at = kNone;
-#pragma unroll 1
-      for (uint32_t i = lane; i < nc; i += kWave) {
-        const uint32_t id = key_id(S[i]);
-        // the whole row in one round trip (the loop's registers are free)
-        const uint64_t key =
-            make_key(exact_dist<DT, D, true>(a.base, id, q, qq), id);
-        S[i] = key;
-        if (key < best) {
-          best = key;
-          at = i;
+      bool done = false;
+      if constexpr (DT == kF32) {
+        // bfloat16 rows with an FP32 recheck, when its arrays fit as well
+        if (a.base16 && 2u * pow2ceil_dev(nc) <= a.s_cap) {
+          rechecked = rerank_bf16<D>(
+              reinterpret_cast<const float*>(a.base), a.base16, a.norm16, S,
+              nc, kq, reinterpret_cast<const float*>(q), oid, od, lane);
+          done = true;
         }
       }
-      __syncthreads();
-      if (kq <= kWave)
-        select_and_emit(S, nc, kq, best, at, oid, od, lane);
-      else
-        sort_and_emit(S, nc, kq, oid, od, lane);
+      if (!done) {
+        // exact keys; each lane also keeps the smallest of its own
+        uint64_t best = kInf;
+        uint32_t at = kNone;
+#pragma unroll 1
+        for (uint32_t i = lane; i < nc; i += kWave) {
+          const uint32_t id = key_id(S[i]);
+          // the whole row in one round trip (the loop's registers are free)
+          const uint64_t key =
+              make_key(exact_dist<DT, D, true>(a.base, id, q, qq), id);
+          S[i] = key;
+          if (key < best) {
+            best = key;
+            at = i;
+          }
+        }
+        __syncthreads();
+        if (kq <= kWave)
+          select_and_emit(S, nc, kq, best, at, oid, od, lane);
+        else
+          sort_and_emit(S, nc, kq, oid, od, lane);
+        if (a.base16) rechecked = nc;
+      }
     } else {
       // too many to sort in LDS: select in the candidate buffer itself
       for (uint32_t i = lane; i < nc; i += kWave) C[i] &= ~1ull;
@@ -1538,6 +1703,7 @@ void search_kernel(SearchArgs a) {
       }
       __threadfence();
       __syncthreads();
+      if (a.base16) rechecked = nc;
       global_select(C, nc, kq, lane);
       for (uint32_t i = lane; i < kq; i += kWave) {
         const uint64_t key = i < nc ? C[i] : kInf;
@@ -1545,6 +1711,8 @@ void search_kernel(SearchArgs a) {
         od[i] = key == kInf ? __uint_as_float(0x7F800000u) : key_dist(key);
       }
     }
+    if (a.out_counters && a.base16 && lane == 0)
+      a.out_counters[qi * 4 + 2] = rechecked;
     // a row of a mixed batch holds k_q results, then padding
     for (uint32_t i = kq + lane; i < a.k; i += kWave) {
       oid[i] = kNone;

@@ -67,7 +67,8 @@ def _create(desc):
     (dict(m=5), -1, "m must divide d"),
     (dict(R=65, adj=np.zeros((100, 65))), -1, "R must be"),
     (dict(medoid=100), -1, "medoid"),
-    (dict(flags=2), -1, "flags"),            # only BANG_INDEX_HOST_ADJ is defined
+    (dict(flags=4), -1, "flags"),            # HOST_ADJ | BF16_BASE only
+    (dict(flags=2), -4, "BF16_BASE"),        # bfloat16 base: float data
     (dict(m=4), -4, "no kernel"),            # d/m = 8 not compiled
 ])
 def test_create_rejects_bad_descriptions(mutate, code, msg):

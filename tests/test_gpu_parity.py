@@ -82,13 +82,14 @@ def f32bits(a):
 
 
 def run_and_compare(ix, gi, q, k, L, c_max=0, iter_cap=0, label="",
-                    table="f32", rerank_global=False, filter="exact"):
+                    table="f32", rerank_global=False, filter="exact",
+                    rerank="exact"):
     cap = iter_cap or oracle.iter_cap_for(L)
     qt = to_dev(q)
     ids, d, cand, cnt = gi.search(qt, k, L, c_max=c_max, iter_cap=iter_cap,
                                   want_cand=cap, want_counters=True,
                                   table=table, rerank_global=rerank_global,
-                                  filter=filter)
+                                  filter=filter, rerank=rerank)
     torch.cuda.synchronize()
     ref = oracle.search(ix, q, k, L, c_max=c_max or None,
                         iter_cap=iter_cap or None, want_cand=True,
@@ -527,24 +528,28 @@ def test_deep1m_sampled_bit_exact():
     and the exact-distance search on the full batch; a seeded sample is
     recomputed by the oracle and compared bit for bit."""
     w, ix, d = load_workload("deep1m")
-    gi = bang_mod().Index(ix.base, ix.adj, ix.medoid, ix.codebooks, ix.codes)
+    gi = bang_mod().Index(ix.base, ix.adj, ix.medoid, ix.codebooks, ix.codes,
+                          bf16_base=True)
     q = d["queries"]
     qt = to_dev(q)
     sample = np.sort(np.random.default_rng(2027).choice(len(q), 96,
                                                         replace=False))
-    for L, table in [(128, "f32"), (256, "f32"), (256, "f16"), (256, "u8"),
-                     (128, "exact"), (512, "f32")]:
+    for L, table, rr in [(128, "f32", "exact"), (256, "f32", "exact"),
+                         (256, "f16", "exact"), (256, "u8", "exact"),
+                         (128, "exact", "exact"), (512, "f32", "exact"),
+                         (128, "f32", "bf16"), (256, "u8", "bf16")]:
         cap = oracle.iter_cap_for(L)
         ids, dist, cand, cnt = gi.search(qt, w.k, L, want_cand=cap,
-                                         want_counters=True, table=table)
+                                         want_counters=True, table=table,
+                                         rerank=rr)
         torch.cuda.synchronize()
         ref = oracle.search(ix, q[sample], w.k, L, want_cand=True,
                             table=table)
         assert np.array_equal(u32(cnt)[sample, 0], ref["iters"]), (L, table)
         assert np.array_equal(u32(cand)[sample], ref["cand"]), (L, table)
-        assert np.array_equal(u32(ids)[sample], ref["ids"]), (L, table)
+        assert np.array_equal(u32(ids)[sample], ref["ids"]), (L, table, rr)
         assert np.array_equal(f32bits(dist.cpu().numpy()[sample]),
-                              f32bits(ref["dists"])), (L, table)
+                              f32bits(ref["dists"])), (L, table, rr)
     gi.close()
 
 
@@ -1078,3 +1083,90 @@ def test_server_many_tickets_and_concurrent_waits(small_indexes):
     got = [o[1] for o in outcome if o[0] == "ok"][0]
     assert np.array_equal(got, ref_ids[:3])
     sv.close()
+
+
+# --------------------------------------------------------------------------
+# the precision form's re-rank of float data: bfloat16 rows, FP32 recheck
+# --------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def bf16_indexes(small_indexes):
+    out = {}
+    for name in ("f32-d32-m16", "f32-d128-m16"):
+        ix, q, _ = small_indexes[name]
+        out[name] = (ix, q, bang_mod().Index(ix.base, ix.adj, ix.medoid,
+                                             ix.codebooks, ix.codes,
+                                             bf16_base=True))
+    return out
+
+
+@pytest.mark.parametrize("name", ["f32-d32-m16", "f32-d128-m16"])
+@pytest.mark.parametrize("k,L,c_max,table", [(10, 64, 0, "f32"),
+                                             (1, 16, 0, "u8"),
+                                             (10, 128, 20, "f16"),
+                                             (100, 256, 0, "f32")])
+def test_bf16_rerank_equals_the_fp32_rerank(bf16_indexes, name, k, L, c_max,
+                                            table):
+    """The search with the BF16 re-rank returns the oracle's FP32 answer bit
+    for bit (ids, distances, expanded nodes, iterations), including the
+    c_max cut and k above 64 (the sorted path); fewer candidates than were
+    expanded get an FP32 distance."""
+    ix, q, gi = bf16_indexes[name]
+    run_and_compare(ix, gi, q, k, L, c_max=c_max, table=table, rerank="bf16",
+                    label=f"{name} k={k} L={L} bf16")
+    _, _, cnt = gi.search(to_dev(q), k, L, c_max=c_max, table=table,
+                          want_counters=True, rerank="bf16")
+    torch.cuda.synchronize()
+    c = u32(cnt)
+    nc = np.minimum(c[:, 0], c_max or 4 * L)
+    assert (c[:, 2] <= nc).all()
+    assert (c[:, 2] >= np.minimum(nc, k)).all()
+    if k == 10 and L >= 64:
+        assert c[:, 2].sum() < nc.sum()
+
+
+def test_bf16_rerank_global_fallback_equals_fp32(bf16_indexes):
+    ix, q, gi = bf16_indexes["f32-d32-m16"]
+    run_and_compare(ix, gi, q, 10, 64, rerank="bf16", rerank_global=True,
+                    label="bf16 global fallback")
+
+
+def test_bf16_rerank_near_ties():
+    """Rows that differ from each other by less than a bfloat16 step, so
+    that the BF16 sums alone misorder them: on a graph where every node is
+    expanded (L >= n), the answer still equals the oracle's FP32 re-rank."""
+    rng = np.random.default_rng(31)
+    n, d, m, R = 300, 32, 16, 24
+    base = rng.standard_normal((n, d)).astype(np.float32)
+    q = rng.standard_normal((8, d)).astype(np.float32)
+    anchor = q[0] + np.float32(0.2) * rng.standard_normal(d).astype(np.float32)
+    base[:60] = anchor + (rng.standard_normal((60, d)) * 1e-4).astype(
+        np.float32)
+    w = synth.small("f32", n=n, d=d, nq=8, m=m, R=R, seed_index=131)
+    rs = synth.streams(w)
+    cb = train_pq(base, m, 4, rs["pq_init"])
+    codes = pq_encode(base, cb)
+    s = oracle.medoid(base)
+    perm = rs["vamana_order"].permutation(n).astype(np.uint32)
+    adj, _ = build_graph(base, R, 32, 1.2, perm, s)
+    ix = oracle.Index(base, adj, s, cb, codes)
+    gi = bang_mod().Index(base, adj, s, cb, codes, bf16_base=True)
+    run_and_compare(ix, gi, q, 10, 512, rerank="bf16", label="near ties")
+    gi.close()
+
+
+def test_bf16_rerank_is_refused_where_it_does_not_apply(small_indexes,
+                                                       bf16_indexes):
+    bang = bang_mod()
+    _, q, gi = small_indexes["f32-d32-m16"]
+    with pytest.raises(bang.BangError) as e:
+        gi.search(to_dev(q), 10, 64, rerank="bf16")   # no bfloat16 base
+    assert e.value.code == -1
+    _, q, gb = bf16_indexes["f32-d32-m16"]
+    with pytest.raises(bang.BangError) as e:
+        gb.search(to_dev(q), 10, 64, rerank="bf16", table="exact")
+    assert e.value.code == -1
+    ix, _, _ = small_indexes["u8-d64-m16"]
+    with pytest.raises(bang.BangError) as e:
+        bang.Index(ix.base, ix.adj, ix.medoid, ix.codebooks, ix.codes,
+                   bf16_base=True)
+    assert e.value.code == -4
