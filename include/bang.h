@@ -119,7 +119,8 @@ typedef struct {
                                BANG_TABLE_F32 (default), the precision
                                form's BANG_TABLE_F16 / BANG_TABLE_U8, or
                                BANG_TABLE_EXACT (no table) */
-  uint32_t flags;           /* 0, or BANG_SEARCH_RERANK_GLOBAL */
+  uint32_t flags;           /* 0, or BANG_SEARCH_RERANK_GLOBAL |
+                               BANG_SEARCH_SEEN_LOG_SHORT */
   const uint32_t* query_L;  /* device [nq] or NULL: a mixed batch, query i
                                searched with worklist size L_i in [1, L]
                                and, with query_k, k_i results in
@@ -131,8 +132,8 @@ typedef struct {
                                Each query's result equals a search of that
                                query alone with (k_i, L_i). */
   const uint32_t* query_k;  /* device [nq] or NULL (every k_i = k) */
-  uint32_t filter;          /* visited filter: BANG_FILTER_EXACT (default)
-                               or BANG_FILTER_BLOOM */
+  uint32_t filter;          /* visited filter: BANG_FILTER_EXACT (default),
+                               BANG_FILTER_BLOOM or BANG_FILTER_SEEN */
   uint32_t* out_phases;     /* device [nq][7] or NULL: shader-clock cycles
                                (s_memtime) of each query's phases: table and
                                worklist start; then summed over expansions:
@@ -141,8 +142,8 @@ typedef struct {
                                next node and requesting its row, merging;
                                then the re-rank.  Runs a timed copy of the
                                search (same results, somewhat slower);
-                               device-resident adjacency and the exact
-                               filter only (EUNSUPPORTED otherwise). */
+                               device-resident adjacency and no Bloom
+                               filter (EUNSUPPORTED otherwise). */
   const bang_abort* abort;  /* NULL, or a stop request (bang_abort_create)
                                this search obeys: once it is set, each wave
                                finishes the expansion it is in, writes its
@@ -185,15 +186,32 @@ typedef struct {
  *    never seen, so results differ from EXACT.  Device memory: 4*z bytes
  *    per resident wave (entries are 32-bit tags ordered by query, row and
  *    neighbour, which resolve the in-row order in one round trip), taken
- *    with the search workspace the first time. */
+ *    with the search workspace the first time.
+ *  - SEEN: Algorithm 2's visited filter with no false positives: one bit
+ *    per node and resident wave, tested and set by one atomic per
+ *    neighbour while the neighbours are scored; a row whose neighbours
+ *    were all seen skips the worklist rank and merge.  A seen node can only
+ *    be in the worklist already or past its last entry (which never grows
+ *    once the worklist is full), so results equal EXACT's, ids and
+ *    distances.  Each query logs the ids it set (up to 8,192; past that it
+ *    only tests) and clears their words at its end.  Device memory per
+ *    resident wave: n/8 bytes (rounded up to 128) plus 32 KiB, taken with
+ *    the search workspace the first time. */
 #define BANG_FILTER_EXACT 0u
 #define BANG_FILTER_BLOOM 1u
+#define BANG_FILTER_SEEN 2u
 #define BANG_BLOOM_Z 399887u
 
 /* The re-rank sorts a query's expanded nodes in on-chip memory when they
  * fit there and otherwise selects them in device memory; this flag takes
  * the device-memory path always (same results; for testing it). */
 #define BANG_SEARCH_RERANK_GLOBAL 1u
+
+/* With BANG_FILTER_SEEN: each query stops setting bits once it has logged
+ * 64 ids or more (the medoid and its first row or two) and from then on
+ * only tests, as a query does once its log is full (same results; for
+ * testing that path). */
+#define BANG_SEARCH_SEEN_LOG_SHORT 2u
 
 /* Table storage forms.  Both reduced forms are computed from the FP32
  * entries of the PQ table section, so they are deterministic:

@@ -27,7 +27,7 @@ INDEX_BF16_BASE = 2
 # re-rank forms (bang.h BANG_RERANK_*)
 RERANKS = {"exact": 0, "bf16": 1}
 # visited filters (bang.h BANG_FILTER_*)
-FILTERS = {"exact": 0, "bloom": 1}
+FILTERS = {"exact": 0, "bloom": 1, "seen": 2}
 ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EUNSUPPORTED",
           -5: "EABORTED"}
 EXPORTS = ("bang_index_create", "bang_index_destroy", "bang_build_pq_tables",
@@ -227,7 +227,8 @@ class Index:
                want_times: bool = False, table: str = "f32",
                rerank_global: bool = False, query_L=None, query_k=None,
                filter: str = "exact", want_phases: bool = False, out=None,
-               abort=None, rerank: str = "exact", stream=None):
+               abort=None, rerank: str = "exact", stream=None,
+               seen_log_short: bool = False):
         """Stages 1-3.  Returns (ids uint32-as-int32 [nq][k], dists
         float32 [nq][k]) and, on request, the expanded nodes [nq][want_cand]
         `table` is the PQ table storage the search ranks by: "f32", the
@@ -237,13 +238,16 @@ class Index:
         k_i <= min(k, L_i), row i holding k_i results then padding.
         and counters [nq][4] (iterations, status) and device wall-clock
         ticks [nq][2] (begin, end).  `filter` is the visited filter:
-        "exact" (set union, the default) or "bloom" (the paper's Bloom
-        filter, BANG_FILTER_BLOOM).  want_phases adds per-query cycles of
+        "exact" (set union, the default), "bloom" (the paper's Bloom
+        filter, BANG_FILTER_BLOOM) or "seen" (an exact seen bitmap,
+        BANG_FILTER_SEEN: the same results as "exact").  want_phases adds per-query cycles of
         the search's seven phases [nq][7] (bang_search_opts.out_phases;
         a timed copy of the search).  abort: a StopRequest the search
         obeys (bang_search_opts.abort).  rerank: "exact" or "bf16" (float
         data on an index with bf16_base; the same answer, counters[:, 2]
-        the candidates recomputed in FP32)."""
+        the candidates recomputed in FP32).  seen_log_short: with the
+        "seen" filter, stop setting bits after 64 logged ids and only test
+        from then on (BANG_SEARCH_SEEN_LOG_SHORT; for testing)."""
         import torch
         qp = self._queries(q)
         nq = q.shape[0]
@@ -254,7 +258,8 @@ class Index:
             ids, dists = out
             _check_out(ids, dists, nq, k, q.device)
         opts = SearchOpts(c_max, iter_cap, None, 0, None, None, TABLES[table],
-                          1 if rerank_global else 0)
+                          (1 if rerank_global else 0)
+                          | (2 if seen_log_short else 0))
         opts.filter = FILTERS[filter]
         if abort is not None:
             opts.abort = abort._h.value

@@ -17,10 +17,12 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "_bang.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # (source, extra defines): the search variants are host-resident adjacency
-# (bit 0) x Bloom filter (bit 1), and 4 the timed copy of variant 0
+# (bit 0) | visited filter << 1 (none, Bloom, seen bitmap) | timed << 3 (the
+# timed copies of the device-resident forms without the Bloom filter)
+VARIANTS = (0, 1, 2, 3, 4, 5, 8, 12)
 UNITS = ([("bang_kernels.hip", []), ("bang_api.cpp", []),
           ("bang_server.cpp", [])] +
-         [("search_variants.hip", [f"-DBANG_VARIANT={v}"]) for v in range(5)])
+         [("search_variants.hip", [f"-DBANG_VARIANT={v}"]) for v in VARIANTS])
 SOURCES = sorted({os.path.join(CSRC, f) for f, _ in UNITS} |
                  {os.path.join(CSRC, f) for f in
                   ("search_kernel.h", "internal.h", "api_internal.h")})

@@ -27,6 +27,13 @@ struct Workspace {
   uint32_t* bloom = nullptr;
   uint32_t* bloom_epoch = nullptr;
   uint64_t bloom_waves = 0;
+  // seen bitmaps (BANG_FILTER_SEEN): per resident wave seen_words words
+  // (zero between queries) and a log of seen_log_entries() ids, for
+  // seen_waves waves
+  uint32_t* seen = nullptr;
+  uint32_t* seen_log = nullptr;
+  uint32_t seen_words = 0;
+  uint64_t seen_waves = 0;
 };
 
 int workspace_init(Workspace* ws, size_t cscratch_bytes);
@@ -68,6 +75,11 @@ namespace bang {
 // keys); 0 with an error set if the launch cannot run at all.
 size_t search_workspace_bytes(bang_index* ix, uint64_t nq, uint32_t L,
                               uint32_t iter_cap, uint32_t table);
+
+// Seen bitmaps for `grid` resident waves in ws (BANG_FILTER_SEEN),
+// allocated and cleared when missing or too small; grow = false makes that
+// an error instead.
+int seen_reserve(bang_index* ix, Workspace* ws, bool grow, uint64_t grid);
 
 // bang_search on an explicit workspace.  grow = false: a workspace that is
 // too small is an error instead of being reallocated (reallocation

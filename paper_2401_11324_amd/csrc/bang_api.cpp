@@ -60,8 +60,8 @@ void workspace_free(Workspace* ws) {
   (void)hipFree(ws->qcounter);
   (void)hipFree(ws->bloom);
   (void)hipFree(ws->bloom_epoch);
-  ws->bloom = ws->bloom_epoch = nullptr;
-  ws->bloom_waves = 0;
+  (void)hipFree(ws->seen);
+  (void)hipFree(ws->seen_log);
   *ws = Workspace{};
 }
 
@@ -297,7 +297,7 @@ int check_queries(const bang_index* ix, const void* queries) {
 
 // Launch geometry of a search: LDS bytes and resident workgroups.
 int search_geometry(bang_index* ix, uint64_t nq, uint32_t L, uint32_t iter_cap,
-                    uint32_t table, bool bloom, bool phases, size_t* lds,
+                    uint32_t table, int filter, bool phases, size_t* lds,
                     uint64_t* grid) {
   *lds = bang::search_lds_bytes(ix->dev.m, L, iter_cap, (int)table);
   hipError_t e = hipSetDevice(ix->device);
@@ -308,7 +308,7 @@ int search_geometry(bang_index* ix, uint64_t nq, uint32_t L, uint32_t iter_cap,
                     " bytes of LDS, the device allows " +
                     std::to_string(ix->max_lds) + " (lower L or iter_cap)");
   int per_cu = 0;
-  e = bang::search_occupancy(ix->dev, (int)table, bloom, phases, *lds,
+  e = bang::search_occupancy(ix->dev, (int)table, filter, phases, *lds,
                              &per_cu);
   if (e != hipSuccess) return hip_fail(e, "occupancy query");
   if (per_cu < 1) return fail(BANG_EUNSUPPORTED, "search kernel cannot be resident");
@@ -324,9 +324,47 @@ size_t search_workspace_bytes(bang_index* ix, uint64_t nq, uint32_t L,
                               uint32_t iter_cap, uint32_t table) {
   size_t lds;
   uint64_t grid;
-  if (search_geometry(ix, nq, L, iter_cap, table, false, false, &lds, &grid))
+  if (search_geometry(ix, nq, L, iter_cap, table, kFilterUnion, false, &lds,
+                      &grid))
     return 0;
   return (size_t)grid * iter_cap * sizeof(uint64_t);
+}
+
+// Seen bitmaps and logs for `grid` waves in ws, allocated (and cleared)
+// the first time or when a launch needs more waves (grow only).
+int seen_reserve(bang_index* ix, Workspace* ws, bool grow, uint64_t grid) {
+  const uint32_t words = seen_words_for(ix->dev.n);
+  if (grid <= ws->seen_waves && ws->seen_words >= words) return BANG_OK;
+  if (!grow)
+    return fail(BANG_ENOMEM, "seen bitmaps for " +
+                                 std::to_string(ws->seen_waves) +
+                                 " waves, the launch needs " +
+                                 std::to_string(grid));
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+  (void)hipFree(ws->seen);
+  (void)hipFree(ws->seen_log);
+  ws->seen = ws->seen_log = nullptr;
+  ws->seen_waves = 0;
+  ws->seen_words = 0;
+  const size_t bb = (size_t)grid * words * sizeof(uint32_t);
+  const size_t lb = (size_t)grid * seen_log_entries() * sizeof(uint32_t);
+  e = hipMalloc(reinterpret_cast<void**>(&ws->seen), bb);
+  if (e == hipSuccess)
+    e = hipMalloc(reinterpret_cast<void**>(&ws->seen_log), lb);
+  if (e != hipSuccess) {
+    (void)hipFree(ws->seen);
+    ws->seen = nullptr;
+    return fail(BANG_ENOMEM,
+                std::string("seen bitmaps: ") + hipGetErrorString(e));
+  }
+  // every bit clear; each query leaves the bits it set clear again
+  e = hipMemset(ws->seen, 0, bb);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(e, "seen bitmap init");
+  ws->seen_waves = grid;
+  ws->seen_words = words;
+  return BANG_OK;
 }
 
 int search_with(bang_index* ix, Workspace* ws, bool grow, const void* queries,
@@ -359,11 +397,15 @@ int search_with(bang_index* ix, Workspace* ws, bool grow, const void* queries,
   if (o && o->out_cand && o->cand_stride == 0)
     return fail(BANG_EINVAL, "cand_stride must be > 0 with out_cand");
   const uint32_t flags = o ? o->flags : 0u;
-  if (flags & ~BANG_SEARCH_RERANK_GLOBAL)
+  if (flags & ~(BANG_SEARCH_RERANK_GLOBAL | BANG_SEARCH_SEEN_LOG_SHORT))
     return fail(BANG_EINVAL, "unknown search flags");
   const uint32_t filter = o ? o->filter : BANG_FILTER_EXACT;
-  if (filter > BANG_FILTER_BLOOM)
+  if (filter > BANG_FILTER_SEEN)
     return fail(BANG_EINVAL, "unknown visited filter");
+  const int fkind = filter == BANG_FILTER_BLOOM
+                        ? bang::kFilterBloom
+                        : (filter == BANG_FILTER_SEEN ? bang::kFilterSeen
+                                                      : bang::kFilterUnion);
   const uint32_t rerank = o ? o->rerank : BANG_RERANK_EXACT;
   if (rerank > BANG_RERANK_BF16) return fail(BANG_EINVAL, "unknown re-rank");
   if (rerank == BANG_RERANK_BF16 && !ix->dev.base16)
@@ -380,12 +422,11 @@ int search_with(bang_index* ix, Workspace* ws, bool grow, const void* queries,
   if (phases && (ix->dev.hadj || filter == BANG_FILTER_BLOOM))
     return fail(BANG_EUNSUPPORTED,
                 "out_phases: the timed search has the device-resident "
-                "adjacency and the exact filter only");
+                "adjacency and no Bloom filter");
   if (phases && !aligned(phases, 4))
     return fail(BANG_EINVAL, "out_phases not 4-byte aligned");
-  rc = search_geometry(ix, nq, L, iter_cap, table,
-                       filter == BANG_FILTER_BLOOM, phases != nullptr, &lds,
-                       &grid);
+  rc = search_geometry(ix, nq, L, iter_cap, table, fkind, phases != nullptr,
+                       &lds, &grid);
   if (rc) return rc;
   size_t need = (size_t)grid * iter_cap * sizeof(uint64_t);
   if (need > ws->cscratch_bytes) {
@@ -437,6 +478,10 @@ int search_with(bang_index* ix, Workspace* ws, bool grow, const void* queries,
     if (e != hipSuccess) return hip_fail(e, "Bloom filter init");
     ws->bloom_waves = grid;
   }
+  if (filter == BANG_FILTER_SEEN) {
+    rc = seen_reserve(ix, ws, grow, grid);
+    if (rc) return rc;
+  }
 
   bang::SearchLaunch l{};
   l.queries = queries;
@@ -461,6 +506,13 @@ int search_with(bang_index* ix, Workspace* ws, bool grow, const void* queries,
   l.qcounter = ws->qcounter;
   l.bloom = filter == BANG_FILTER_BLOOM ? ws->bloom : nullptr;
   l.bloom_epoch = filter == BANG_FILTER_BLOOM ? ws->bloom_epoch : nullptr;
+  if (filter == BANG_FILTER_SEEN) {
+    l.seen = ws->seen;
+    l.seen_log = ws->seen_log;
+    l.seen_words = ws->seen_words;
+    l.seen_cap = (flags & BANG_SEARCH_SEEN_LOG_SHORT) ? 2u * 64u
+                                                      : bang::seen_log_entries();
+  }
   if (o && o->abort) {
     l.abort_flag = o->abort->dev;
     l.abort_fired = o->abort->dev + 1;

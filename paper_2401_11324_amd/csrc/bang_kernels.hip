@@ -248,16 +248,30 @@ hipError_t launch_pack(const uint32_t* adj, const uint8_t* codes, uint32_t n,
   return hipGetLastError();
 }
 
-hipError_t search_occupancy(const DeviceIndex& ix, int table, bool bloom,
+uint32_t seen_words_for(uint32_t n) { return (n + 1023u) / 1024u * 32u; }
+
+uint32_t seen_log_entries() { return kSeenLog; }
+
+// Variant number of a search: host-resident adjacency (bit 0) | filter << 1
+// | timed << 3 (search_variants.hip).
+static int variant_of(bool host, int filter, bool phases) {
+  return (host ? 1 : 0) | (filter << 1) | (phases ? 8 : 0);
+}
+
+hipError_t search_occupancy(const DeviceIndex& ix, int table, int filter,
                             bool phases, size_t lds, int* per_cu) {
   const int dt = ix.dtype;
   const uint32_t m = ix.m, ds = ix.d / ix.m;
-  if (phases) return search_occupancy_v4(dt, m, ds, table, lds, per_cu);
-  switch ((ix.hadj ? 1 : 0) | (bloom ? 2 : 0)) {
+  switch (variant_of(ix.hadj != nullptr, filter, phases)) {
     case 0: return search_occupancy_v0(dt, m, ds, table, lds, per_cu);
     case 1: return search_occupancy_v1(dt, m, ds, table, lds, per_cu);
     case 2: return search_occupancy_v2(dt, m, ds, table, lds, per_cu);
-    default: return search_occupancy_v3(dt, m, ds, table, lds, per_cu);
+    case 3: return search_occupancy_v3(dt, m, ds, table, lds, per_cu);
+    case 4: return search_occupancy_v4(dt, m, ds, table, lds, per_cu);
+    case 5: return search_occupancy_v5(dt, m, ds, table, lds, per_cu);
+    case 8: return search_occupancy_v8(dt, m, ds, table, lds, per_cu);
+    case 12: return search_occupancy_v12(dt, m, ds, table, lds, per_cu);
+    default: return hipErrorInvalidValue;
   }
 }
 
@@ -307,16 +321,27 @@ hipError_t launch_search(const DeviceIndex& ix, const SearchLaunch& l,
   a.abort_fired = l.abort_fired;
   a.base16 = l.rerank_bf16 ? ix.base16 : nullptr;
   a.norm16 = l.rerank_bf16 ? ix.norm16 : nullptr;
+  a.seen = l.seen;
+  a.seen_log = l.seen_log;
+  a.seen_words = l.seen_words;
+  a.seen_cap = std::min(l.seen_cap, kSeenLog);
   a.qcounter = l.qcounter;
   const int dt = ix.dtype;
   const uint32_t m = ix.m, ds = ix.d / ix.m;
-  if (a.out_phases)
-    return search_launch_v4(a, dt, m, ds, l.table, l.grid, lds, s);
-  switch ((a.hadj ? 1 : 0) | (a.bloom ? 2 : 0)) {
+  const int filter =
+      a.bloom ? kFilterBloom : (a.seen ? kFilterSeen : kFilterUnion);
+  if (a.seen && (!a.seen_log || a.seen_words < seen_words_for(ix.n)))
+    return hipErrorInvalidValue;
+  switch (variant_of(a.hadj != nullptr, filter, a.out_phases != nullptr)) {
     case 0: return search_launch_v0(a, dt, m, ds, l.table, l.grid, lds, s);
     case 1: return search_launch_v1(a, dt, m, ds, l.table, l.grid, lds, s);
     case 2: return search_launch_v2(a, dt, m, ds, l.table, l.grid, lds, s);
-    default: return search_launch_v3(a, dt, m, ds, l.table, l.grid, lds, s);
+    case 3: return search_launch_v3(a, dt, m, ds, l.table, l.grid, lds, s);
+    case 4: return search_launch_v4(a, dt, m, ds, l.table, l.grid, lds, s);
+    case 5: return search_launch_v5(a, dt, m, ds, l.table, l.grid, lds, s);
+    case 8: return search_launch_v8(a, dt, m, ds, l.table, l.grid, lds, s);
+    case 12: return search_launch_v12(a, dt, m, ds, l.table, l.grid, lds, s);
+    default: return hipErrorInvalidValue;
   }
 }
 

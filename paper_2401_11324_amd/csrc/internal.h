@@ -46,6 +46,11 @@ struct SearchLaunch {
   uint32_t* out_phases;  // [nq][7] per-phase cycles (timed variant) or null
   uint32_t* bloom;       // null (exact filter) or [grid][BANG_BLOOM_Z]
   uint32_t* bloom_epoch; // [grid] query epoch of each wave's filter
+  uint32_t* seen;        // null, or [grid][seen_words] seen bitmaps (zero
+                         // between queries; BANG_FILTER_SEEN)
+  uint32_t* seen_log;    // [grid][seen_log_entries()] ids set per query
+  uint32_t seen_words;
+  uint32_t seen_cap;     // ids a query may log (<= seen_log_entries())
   const uint32_t* abort_flag;  // device view of a bang_abort, or null
   uint32_t* abort_fired;
   uint32_t grid;         // workgroups (one wave each)
@@ -65,9 +70,18 @@ hipError_t launch_pack(const uint32_t* adj, const uint8_t* codes, uint32_t n,
                        uint32_t R, uint32_t m, unsigned char* rows,
                        hipStream_t s);
 
+// Visited filter of a search variant: none (set union in the worklist),
+// the paper's Bloom filter, or the exact seen bitmap.
+enum FilterKind : int { kFilterUnion = 0, kFilterBloom = 1, kFilterSeen = 2 };
+
+// Seen-bitmap words per resident wave for n nodes (one bit each, a whole
+// number of 128-byte lines) and logged ids per wave.
+uint32_t seen_words_for(uint32_t n);
+uint32_t seen_log_entries();
+
 // Resident workgroups per CU for the search kernel variant (adjacency
 // placement of ix, visited filter, timed) at this LDS size.
-hipError_t search_occupancy(const DeviceIndex& ix, int table, bool bloom,
+hipError_t search_occupancy(const DeviceIndex& ix, int table, int filter,
                             bool phases, size_t lds, int* per_cu);
 
 hipError_t launch_tables(const DeviceIndex& ix, const void* queries,

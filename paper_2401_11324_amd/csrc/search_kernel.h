@@ -979,6 +979,13 @@ struct SearchArgs {
   // the re-rank with an FP32 recheck (null: the exact FP32 re-rank)
   const uint16_t* base16;
   const float* norm16;
+  // exact seen-set (the seen-bitmap variant only): per resident wave one
+  // bit per node, seen_words words, all zero between queries; and a log of
+  // the ids whose bits the current query set, kSeenLog entries per wave
+  uint32_t* seen;
+  uint32_t* seen_log;
+  uint32_t seen_words;
+  uint32_t seen_cap;  // ids a query may log, <= kSeenLog
 };
 
 namespace {
@@ -1093,6 +1100,27 @@ __device__ __forceinline__ void bloom_update(uint32_t* bf, uint32_t btop,
   }
 }
 
+// Exact seen-set (Algorithm 2's visited filter without false positives):
+// one bit per node in the wave's bitmap.  Each neighbour of an expanded row
+// takes one atomicOr with its bit, which sets it and returns the word as it
+// was: a clear bit means the neighbour is new to the query.  While the log
+// has room for a whole row the bit is set and new ids are logged; after
+// that the word is only read (atomicOr with 0), so a new neighbour counts
+// as unseen again later, which the set union in the worklist resolves.  A
+// set bit is therefore always a node seen before, and dropping it changes
+// nothing: it is in the worklist already, or its key lies past the last
+// entry, which never grows once the worklist is full.  At the query's end
+// the logged words are stored as zero, which leaves the bitmap clear.
+constexpr uint32_t kSeenLog = 8192u;  // logged ids per wave
+
+enum Filter : int { kFiltUnion = 0, kFiltBloom = 1, kFiltSeen = 2 };
+
+__device__ __forceinline__ uint32_t seen_update(uint32_t* sb, uint32_t nb,
+                                                bool set) {
+  if (nb == kNone) return ~0u;  // an empty slot reads as seen
+  return atomicOr(sb + (nb >> 5), set ? 1u << (nb & 31u) : 0u);
+}
+
 template <int M, bool CODES, bool HOST>
 __device__ __forceinline__ void touch_row(const SearchArgs& a, uint32_t u,
                                           int lane, uint32_t& touched) {
@@ -1143,16 +1171,20 @@ __device__ __forceinline__ uint64_t phase_clock() {
 }
 
 // HOST: adjacency rows in pinned host memory (a.hadj), the codes gathered
-// from device memory.  BLOOM: the paper's Bloom filter as the visited test
-// (a.bloom) in addition to the set union.  Each is its own instantiation,
-// so that no form's extra loads and atomics change where the others wait
-// for memory.  PHASES: the timed variant, which adds up shader-clock cycles
-// per phase of each query (out_phases) and is otherwise the same search.
-template <int DT, int M, int DS, int TT, bool HOST, bool BLOOM, bool PHASES>
+// from device memory.  FILT: the visited test besides the set union in the
+// worklist: none, the paper's Bloom filter (a.bloom), or the exact seen
+// bitmap (a.seen), which skips the worklist rank of a row whose neighbours
+// were all seen.  Each is its own instantiation, so that no form's extra
+// loads and atomics change where the others wait for memory.  PHASES: the
+// timed variant, which adds up shader-clock cycles per phase of each query
+// (out_phases) and is otherwise the same search.
+template <int DT, int M, int DS, int TT, bool HOST, int FILT, bool PHASES>
 __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(
     1, max_waves_per_simd(table_bytes<TT>(M)))))
 void search_kernel(SearchArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
+  constexpr bool BLOOM = FILT == kFiltBloom;
+  constexpr bool SEEN = FILT == kFiltSeen;
   constexpr int D = M * DS;
   constexpr int kTableBytes = table_bytes<TT>(M);
   constexpr bool kExact = TT == kTabExact;
@@ -1248,6 +1280,21 @@ void search_kernel(SearchArgs a) {
       // clears and the medoid's tags are in place before any row's update
       __builtin_amdgcn_s_waitcnt(kWaitVmem0);
       __threadfence_block();
+    }
+    // seen bitmap: the previous query's clearing stores are complete, then
+    // the medoid is the first id seen and logged
+    uint32_t* const sb =
+        SEEN ? a.seen + (size_t)blockIdx.x * a.seen_words : nullptr;
+    uint32_t* const slog =
+        SEEN ? a.seen_log + (size_t)blockIdx.x * kSeenLog : nullptr;
+    uint32_t nlog = 0;
+    if constexpr (SEEN) {
+      __builtin_amdgcn_s_waitcnt(kWaitVmem0);
+      if (lane == 0) {
+        atomicOr(sb + (s >> 5), 1u << (s & 31u));
+        slog[0] = s;
+      }
+      nlog = 1;
     }
     // constant term of integer exact distances (the PQ forms compute it
     // after the search, so the query is not held through the loop)
@@ -1348,14 +1395,20 @@ void search_kernel(SearchArgs a) {
       // lane's tag below (after any code gather, so that the scoring waits
       // for neither); the previous values are used after the scoring
       uint32_t b1 = 0, b2 = 0, btag = 0, bo1 = ~0u, bo2 = ~0u;
+      // seen bitmap: each neighbour's word as it was before this row set
+      // its bit, back during the scoring (set only while the log has room)
+      uint32_t sold = 0;
+      const bool sset = nlog + kWave <= a.seen_cap;
       uint64_t key = kInf;
       if constexpr (kExact && DT != kF32) {
         bloom_update(bf, btop, iters, lane, nb, b1, b2, btag, bo1, bo2);
+        if constexpr (SEEN) sold = seen_update(sb, nb, sset);
         touch_row<M, false, HOST>(a, key_id(nx), lane, touched);
         const float dq = coop_dist<DT, D>(a.base, nb, qc, qq, lane);
         key = nb != kNone ? make_key(dq, nb) : kInf;
       } else if constexpr (kExact) {
         bloom_update(bf, btop, iters, lane, nb, b1, b2, btag, bo1, bo2);
+        if constexpr (SEEN) sold = seen_update(sb, nb, sset);
         touch_row<M, false, HOST>(a, key_id(nx), lane, touched);
         if (nb != kNone)
           key = make_key(exact_dist<DT, D, true>(a.base, nb, q, qq), nb);
@@ -1370,11 +1423,27 @@ void search_kernel(SearchArgs a) {
                 keep_alive(code[i].z), keep_alive(code[i].w);
         }
         bloom_update(bf, btop, iters, lane, nb, b1, b2, btag, bo1, bo2);
+        if constexpr (SEEN) sold = seen_update(sb, nb, sset);
         touch_row<M, true, HOST>(a, key_id(nx), lane, touched);
         // every lane sums (no branch): an empty slot has zero codes, a lane
         // past R reads table entries it then discards
         const uint64_t k2 = make_key(adc_codes<M, TT>(code), nb);
         key = nb != kNone ? k2 : kInf;
+      }
+      // a neighbour whose bit was set is dropped before the worklist rank;
+      // new ones are logged (in row order) for the clearing at the end
+      uint64_t fresh_mask = ~0ull;
+      if constexpr (SEEN) {
+        const bool fresh = !((sold >> (nb & 31u)) & 1u);
+        fresh_mask = __ballot(fresh);
+        if (!fresh) key = kInf;
+        if (sset) {
+          const uint32_t at = __builtin_amdgcn_mbcnt_hi(
+              (uint32_t)(fresh_mask >> 32),
+              __builtin_amdgcn_mbcnt_lo((uint32_t)fresh_mask, 0u));
+          if (fresh) slog[nlog + at] = nb;
+          nlog += (uint32_t)__popcll(fresh_mask);
+        }
       }
 
       if constexpr (PHASES) {
@@ -1388,8 +1457,9 @@ void search_kernel(SearchArgs a) {
       // are, so only the remaining ("live") keys take part in the merge.
       // No branch for empty slots: kInf ranks past the last entry, with no
       // entry equal to it, and is never kept.
-      uint64_t ge;
-      const uint32_t r = rank_in(Lc, Llen, last, key, ge);
+      uint64_t ge = kInf;
+      uint32_t r = Llen;
+      if (fresh_mask) r = rank_in(Lc, Llen, last, key, ge);
       bool keep = (ge >> 1) != (key >> 1) && r < Lq;
       if constexpr (BLOOM) {
         // an entry is set for this lane if it held a smaller tag: an
@@ -1612,6 +1682,23 @@ void search_kernel(SearchArgs a) {
       C[(iters & ~(kWave - 1u)) + lane] = ckey;
     __threadfence();
     __syncthreads();
+    if constexpr (SEEN) {
+      // clear the words of every id this query set (the log is read after
+      // the fence above); the stores complete before the next query's
+      // first update
+#pragma unroll 1
+      for (uint32_t i0 = 0; i0 < nlog; i0 += 4 * kWave) {
+        uint32_t id[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const uint32_t i = i0 + u * kWave + lane;
+          id[u] = i < nlog ? slog[i] : kNone;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (id[u] != kNone) sb[id[u] >> 5] = 0u;
+      }
+    }
     if (a.out_counters && lane == 0) {
       a.out_counters[qi * 4 + 0] = iters;
       a.out_counters[qi * 4 + 1] = status;
@@ -1780,8 +1867,9 @@ hipError_t occupancy_of(K kernel, size_t lds, int* per_cu) {
 }  // namespace
 
 // The search variants, one per translation unit (search_variants.hip):
-// v = host-resident adjacency (bit 0) | Bloom filter (bit 1), and v = 4 the
-// timed variant of v = 0.  launch runs
+// v = host-resident adjacency (bit 0) | filter << 1 (none, Bloom, seen
+// bitmap) | timed << 3; the timed variants exist for device-resident
+// adjacency without the Bloom filter (v = 8, 12).  launch runs
 // one search; occupancy gives the resident workgroups per CU at `lds` bytes
 // of LDS and enables that LDS size for the kernel, so it precedes a launch.
 #define BANG_VARIANT_DECL(V)                                                 \
@@ -1795,6 +1883,9 @@ BANG_VARIANT_DECL(1)
 BANG_VARIANT_DECL(2)
 BANG_VARIANT_DECL(3)
 BANG_VARIANT_DECL(4)
+BANG_VARIANT_DECL(5)
+BANG_VARIANT_DECL(8)
+BANG_VARIANT_DECL(12)
 #undef BANG_VARIANT_DECL
 
 }  // namespace bang

@@ -1,11 +1,11 @@
 // One search variant per translation unit, so that the variants compile in
-// parallel: BANG_VARIANT = host-resident adjacency (bit 0) | Bloom filter
-// (bit 1), or 4 for the timed variant of 0 (per-phase cycles), instantiated
-// for every compiled (dtype, m, d/m) and table form.
+// parallel: BANG_VARIANT = host-resident adjacency (bit 0) | visited filter
+// << 1 (bits 1-2: none, Bloom, seen bitmap) | timed (bit 3, per-phase
+// cycles), instantiated for every compiled (dtype, m, d/m) and table form.
 #include "search_kernel.h"
 
 #ifndef BANG_VARIANT
-#error "compile with -DBANG_VARIANT=0, 1, 2, 3 or 4"
+#error "compile with -DBANG_VARIANT=<host | filter << 1 | timed << 3>"
 #endif
 
 namespace bang {
@@ -13,8 +13,9 @@ namespace bang {
 namespace {
 
 constexpr bool kHostV = (BANG_VARIANT & 1) != 0;
-constexpr bool kBloomV = (BANG_VARIANT & 2) != 0;
-constexpr bool kPhasesV = BANG_VARIANT == 4;
+constexpr int kFiltV = (BANG_VARIANT >> 1) & 3;  // the filter
+constexpr bool kPhasesV = (BANG_VARIANT & 8) != 0;
+static_assert(kFiltV <= kFiltSeen, "unknown filter");
 
 template <int DT, int M, int DS>
 struct Launch {
@@ -22,20 +23,20 @@ struct Launch {
                         size_t lds, hipStream_t s) {
     switch (table) {
       case kTabF32:
-        hipLaunchKernelGGL((search_kernel<DT, M, DS, kTabF32, kHostV, kBloomV, kPhasesV>),
+        hipLaunchKernelGGL((search_kernel<DT, M, DS, kTabF32, kHostV, kFiltV, kPhasesV>),
                            dim3(grid), dim3(kWave), lds, s, a);
         break;
       case kTabF16:
-        hipLaunchKernelGGL((search_kernel<DT, M, DS, kTabF16, kHostV, kBloomV, kPhasesV>),
+        hipLaunchKernelGGL((search_kernel<DT, M, DS, kTabF16, kHostV, kFiltV, kPhasesV>),
                            dim3(grid), dim3(kWave), lds, s, a);
         break;
       case kTabU8:
-        hipLaunchKernelGGL((search_kernel<DT, M, DS, kTabU8, kHostV, kBloomV, kPhasesV>),
+        hipLaunchKernelGGL((search_kernel<DT, M, DS, kTabU8, kHostV, kFiltV, kPhasesV>),
                            dim3(grid), dim3(kWave), lds, s, a);
         break;
       case kTabExact:
         hipLaunchKernelGGL(
-            (search_kernel<DT, M, DS, kTabExact, kHostV, kBloomV, kPhasesV>), dim3(grid),
+            (search_kernel<DT, M, DS, kTabExact, kHostV, kFiltV, kPhasesV>), dim3(grid),
             dim3(kWave), lds, s, a);
         break;
       default:
@@ -50,17 +51,17 @@ struct Occupancy {
   static hipError_t run(int table, size_t lds, int* per_cu) {
     switch (table) {
       case kTabF32:
-        return occupancy_of(search_kernel<DT, M, DS, kTabF32, kHostV, kBloomV, kPhasesV>,
+        return occupancy_of(search_kernel<DT, M, DS, kTabF32, kHostV, kFiltV, kPhasesV>,
                             lds, per_cu);
       case kTabF16:
-        return occupancy_of(search_kernel<DT, M, DS, kTabF16, kHostV, kBloomV, kPhasesV>,
+        return occupancy_of(search_kernel<DT, M, DS, kTabF16, kHostV, kFiltV, kPhasesV>,
                             lds, per_cu);
       case kTabU8:
-        return occupancy_of(search_kernel<DT, M, DS, kTabU8, kHostV, kBloomV, kPhasesV>,
+        return occupancy_of(search_kernel<DT, M, DS, kTabU8, kHostV, kFiltV, kPhasesV>,
                             lds, per_cu);
       case kTabExact:
         return occupancy_of(
-            search_kernel<DT, M, DS, kTabExact, kHostV, kBloomV, kPhasesV>, lds, per_cu);
+            search_kernel<DT, M, DS, kTabExact, kHostV, kFiltV, kPhasesV>, lds, per_cu);
     }
     return hipErrorInvalidValue;
   }

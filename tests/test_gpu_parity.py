@@ -81,21 +81,26 @@ def f32bits(a):
     return np.ascontiguousarray(a, dtype=np.float32).view(np.uint32)
 
 
+# the oracle's search mode for each GPU visited filter: the set union
+# (Algorithm 1), the exact seen-set (Algorithm 2 without false positives)
+# and the paper's Bloom filter
+ORACLE_MODE = {"exact": "union", "seen": "exact", "bloom": "bloom"}
+
+
 def run_and_compare(ix, gi, q, k, L, c_max=0, iter_cap=0, label="",
                     table="f32", rerank_global=False, filter="exact",
-                    rerank="exact"):
+                    rerank="exact", seen_log_short=False):
     cap = iter_cap or oracle.iter_cap_for(L)
     qt = to_dev(q)
     ids, d, cand, cnt = gi.search(qt, k, L, c_max=c_max, iter_cap=iter_cap,
                                   want_cand=cap, want_counters=True,
                                   table=table, rerank_global=rerank_global,
-                                  filter=filter, rerank=rerank)
+                                  filter=filter, rerank=rerank,
+                                  seen_log_short=seen_log_short)
     torch.cuda.synchronize()
     ref = oracle.search(ix, q, k, L, c_max=c_max or None,
                         iter_cap=iter_cap or None, want_cand=True,
-                        table=table,
-                        mode=oracle.MODES["bloom" if filter == "bloom"
-                                          else "union"])
+                        table=table, mode=oracle.MODES[ORACLE_MODE[filter]])
     ids, d, cand, cnt = u32(ids), d.cpu().numpy(), u32(cand), u32(cnt)
     assert np.array_equal(cnt[:, 0], ref["iters"]), label
     assert np.array_equal(cnt[:, 1], ref["status"]), label
@@ -1170,3 +1175,162 @@ def test_bf16_rerank_is_refused_where_it_does_not_apply(small_indexes,
         bang.Index(ix.base, ix.adj, ix.medoid, ix.codebooks, ix.codes,
                    bf16_base=True)
     assert e.value.code == -4
+
+
+# --------------------------------------------------------------------------
+# the exact seen bitmap (BANG_FILTER_SEEN)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("name", list(SMALL))
+@pytest.mark.parametrize("k,L,table", [(1, 1, "f32"), (10, 16, "f32"),
+                                       (5, 33, "f32"), (10, 100, "f32"),
+                                       (10, 300, "f32"), (10, 1024, "f32"),
+                                       (10, 64, "f16"), (10, 200, "u8"),
+                                       (10, 64, "exact"),
+                                       (10, 300, "exact")])
+def test_seen_filter_bit_exact(small_indexes, name, k, L, table):
+    """The seen bitmap drops neighbours seen before the worklist rank: ids,
+    distances, expanded nodes and iteration counts equal the oracle's
+    Algorithm 2 with an exact seen-set, for every table form."""
+    ix, q, gi = small_indexes[name]
+    run_and_compare(ix, gi, q, k, L, table=table, filter="seen",
+                    label=f"{name} k={k} L={L} {table} seen")
+
+
+@pytest.mark.parametrize("name", ["u8-d64-m16", "f32-d128-m16",
+                                  "i8-d96-m48"])
+@pytest.mark.parametrize("k,L,table", [(10, 64, "f32"), (10, 256, "u8"),
+                                       (10, 100, "exact")])
+def test_seen_filter_host_adjacency_bit_exact(small_indexes,
+                                              small_host_indexes, name, k, L,
+                                              table):
+    """Host-resident rows with the seen bitmap: equal to the oracle."""
+    ix, q, _ = small_indexes[name]
+    run_and_compare(ix, small_host_indexes[name], q, k, L, table=table,
+                    filter="seen", label=f"{name} host seen")
+
+
+@pytest.mark.parametrize("k,L,table", [(10, 64, "f32"), (10, 512, "f32"),
+                                       (10, 100, "exact")])
+def test_seen_filter_saturated_log_bit_exact(small_indexes, k, L, table):
+    """A query whose log is full only tests its bitmap from then on (new
+    neighbours are ranked and the set union drops repeats): results are
+    still the oracle's, and the next search, with the log in full use, is
+    exact as well (the bits the short-logged queries set were cleared)."""
+    for name in ("u8-d128-m32", "f32-d32-m16"):
+        ix, q, gi = small_indexes[name]
+        run_and_compare(ix, gi, q, k, L, table=table, filter="seen",
+                        seen_log_short=True, label=f"{name} short log")
+        run_and_compare(ix, gi, q, k, L, table=table, filter="seen",
+                        label=f"{name} after short log")
+
+
+def test_seen_filter_repeated_launches_leave_the_bitmap_clear(small_indexes):
+    """Each query clears the bits it set: many launches with different
+    query sets, worklist sizes and table forms through one workspace each
+    equal the set-union search (whose results depend on no state)."""
+    ix, q, gi = small_indexes["u8-d128-m32"]
+    rng = np.random.default_rng(31)
+    qt = to_dev(q)
+    for rep in range(12):
+        L = int(rng.choice([16, 64, 200, 700]))
+        table = ["f32", "u8", "exact"][rep % 3]
+        sel = np.sort(rng.choice(len(q), int(rng.integers(1, len(q) + 1)),
+                                 replace=False))
+        qs = qt[torch.from_numpy(sel).cuda()].contiguous()
+        a = gi.search(qs, 10, L, table=table, filter="seen", want_cand=4 * L)
+        b = gi.search(qs, 10, L, table=table, filter="exact",
+                      want_cand=4 * L)
+        torch.cuda.synchronize()
+        for x, y in zip(a, b):
+            assert np.array_equal(x.cpu().numpy(), y.cpu().numpy()), (rep, L)
+
+
+@pytest.mark.parametrize("name", ["u8-d128-m32", "f32-d32-m16"])
+@pytest.mark.parametrize("table", ["f32", "u8", "exact"])
+def test_seen_filter_mixed_batch_equals_each_query_alone(small_indexes, name,
+                                                         table):
+    """A mixed batch (per-query k and L) with the seen bitmap: each row
+    equals that query searched alone with the set union."""
+    ix, q, gi = small_indexes[name]
+    nq = len(q)
+    rng = np.random.default_rng(77)
+    Ls = rng.choice([8, 16, 64, 150], nq).astype(np.int32)
+    ks = np.minimum(rng.choice([1, 5, 10], nq), Ls).astype(np.int32)
+    ids, d = gi.search(to_dev(q), 10, 150, table=table, filter="seen",
+                       query_L=to_dev(Ls), query_k=to_dev(ks))
+    torch.cuda.synchronize()
+    ids, d = u32(ids), d.cpu().numpy()
+    for i in range(nq):
+        r = oracle.search(ix, q[i:i + 1], int(ks[i]), int(Ls[i]),
+                          table=table)
+        assert np.array_equal(ids[i, :ks[i]], r["ids"][0]), i
+        assert np.array_equal(f32bits(d[i, :ks[i]]),
+                              f32bits(r["dists"][0])), i
+        assert (ids[i, ks[i]:] == NONE).all()
+
+
+def test_seen_filter_stopped_launch_leaves_the_bitmap_clear(small_indexes):
+    """Queries cut short by a stop request clear the bits they set: a
+    search after a stopped launch equals the oracle."""
+    import time
+    ix, q, gi = small_indexes["u8-d128-m32"]
+    bang = bang_mod()
+    qrep = to_dev(np.tile(q, (400, 1)))
+    ab = bang.StopRequest()
+    ids, d, cnt = gi.search(qrep, 10, 1024, want_counters=True, abort=ab,
+                            filter="seen")
+    torch.cuda.synchronize()
+    gi.search(qrep, 10, 1024, want_counters=True, abort=ab, filter="seen",
+              out=(ids, d))
+    time.sleep(0.002)
+    ab.set()
+    torch.cuda.synchronize()
+    ab.clear()
+    run_and_compare(ix, gi, q, 10, 1024, filter="seen",
+                    label="after a stopped seen-filter launch")
+    run_and_compare(ix, gi, q, 10, 64, table="exact", filter="seen",
+                    label="after a stopped seen-filter launch (exact)")
+    ab.close()
+
+
+@pytest.mark.parametrize("table", ["f32", "exact"])
+def test_seen_filter_timed_search_same_results(small_indexes, table):
+    """The timed copy of the seen-filter search returns the same results
+    and reports its phases."""
+    ix, q, gi = small_indexes["u8-d128-m32"]
+    qt = to_dev(q)
+    a = gi.search(qt, 10, 256, table=table, filter="seen", want_cand=1024,
+                  want_counters=True)
+    b = gi.search(qt, 10, 256, table=table, filter="seen", want_cand=1024,
+                  want_counters=True, want_phases=True)
+    torch.cuda.synchronize()
+    for x, y in zip(a, b[:4]):
+        assert np.array_equal(x.cpu().numpy(), y.cpu().numpy())
+    ph = b[4].cpu().numpy().astype(np.int64)
+    assert ph.shape == (len(q), 7) and (ph[:, 2] > 0).all()
+
+
+def test_sift1m_seen_filter_sampled_bit_exact():
+    """1M uint8 points with the seen bitmap, in the benchmark's launch
+    configuration: a seeded sample of queries equals the oracle bit for
+    bit at the bench points."""
+    w, ix, d = load_workload("sift1m")
+    gi = bang_mod().Index(ix.base, ix.adj, ix.medoid, ix.codebooks, ix.codes)
+    q = d["queries"]
+    qt = to_dev(q)
+    sample = np.sort(np.random.default_rng(2031).choice(len(q), 96,
+                                                        replace=False))
+    for L, table in [(64, "f32"), (768, "f32"), (768, "u8"), (256, "exact"),
+                     (1024, "f16")]:
+        cap = oracle.iter_cap_for(L)
+        ids, dist, cand, cnt = gi.search(qt, w.k, L, want_cand=cap,
+                                         want_counters=True, table=table,
+                                         filter="seen")
+        torch.cuda.synchronize()
+        ref = oracle.search(ix, q[sample], w.k, L, want_cand=True,
+                            table=table, mode=oracle.MODES["exact"])
+        assert np.array_equal(u32(cnt)[sample, 0], ref["iters"]), L
+        assert np.array_equal(u32(cand)[sample], ref["cand"]), L
+        assert np.array_equal(u32(ids)[sample], ref["ids"]), L
+        assert np.array_equal(f32bits(dist.cpu().numpy()[sample]),
+                              f32bits(ref["dists"])), L
