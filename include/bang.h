@@ -264,6 +264,25 @@ int bang_search(bang_index* index, const void* queries, uint64_t nq,
                 uint32_t k, uint32_t L, uint32_t* out_ids, float* out_dists,
                 const bang_search_opts* opts, void* stream);
 
+/* bang_search without any device allocation, for callers that cannot
+ * allocate: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  Same arguments, results and validation as
+ * bang_search; it calls no hipMalloc, hipFree or allocating routine.  Its
+ * device memory is a file-scope array of 32 MiB per GPU (set up by
+ * bang_index_create, held until the process ends): the launch counters and
+ * 8 * iter_cap bytes of expanded-node keys per resident wave, so a launch
+ * runs at most (32 MiB - 256) / (8 * iter_cap) waves (4 MiB keys: 1,364
+ * waves at L = 768), fewer than bang_search when its occupancy allows
+ * more; BANG_ENOMEM if one wave's keys do not fit.  The set-union filter
+ * only (BANG_EUNSUPPORTED for BLOOM or SEEN).  Every call on a GPU shares
+ * that GPU's array, which keeps the last call's contents: calls that
+ * overlap in time on one GPU (other streams, other threads) race and must
+ * be serialised by the caller. */
+int bang_search_noalloc(bang_index* index, const void* queries, uint64_t nq,
+                        uint32_t k, uint32_t L, uint32_t* out_ids,
+                        float* out_dists, const bang_search_opts* opts,
+                        void* stream);
+
 /* Stage 3 alone: exact top-k over given candidates.  cand: device
  * [nq][c_max] uint32; BANG_NONE or ids >= n are padding and are skipped;
  * ids in a row must be distinct.  1 <= c_max <= 4096, 1 <= k <= 1024.

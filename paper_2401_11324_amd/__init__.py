@@ -31,7 +31,8 @@ FILTERS = {"exact": 0, "bloom": 1, "seen": 2}
 ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EUNSUPPORTED",
           -5: "EABORTED"}
 EXPORTS = ("bang_index_create", "bang_index_destroy", "bang_build_pq_tables",
-           "bang_search", "bang_rerank", "bang_index_probe",
+           "bang_search", "bang_search_noalloc", "bang_rerank",
+           "bang_index_probe",
            "bang_server_create",
            "bang_server_destroy", "bang_server_submit", "bang_server_wait",
            "bang_server_replay", "bang_server_stats", "bang_abort_create",
@@ -91,6 +92,7 @@ def lib():
         L.bang_build_pq_tables.argtypes = [P, P, u64, P, P]
         L.bang_search.argtypes = [P, P, u64, u32, u32, P, P,
                                   ctypes.POINTER(SearchOpts), P]
+        L.bang_search_noalloc.argtypes = L.bang_search.argtypes
         L.bang_rerank.argtypes = [P, P, u64, P, u32, u32, P, P, P]
         L.bang_index_probe.argtypes = [P, u64, u64, P, ctypes.POINTER(u32), P]
         L.bang_server_create.argtypes = [P, ctypes.POINTER(ServerOpts),
@@ -228,7 +230,7 @@ class Index:
                rerank_global: bool = False, query_L=None, query_k=None,
                filter: str = "exact", want_phases: bool = False, out=None,
                abort=None, rerank: str = "exact", stream=None,
-               seen_log_short: bool = False):
+               seen_log_short: bool = False, _entry: str = "bang_search"):
         """Stages 1-3.  Returns (ids uint32-as-int32 [nq][k], dists
         float32 [nq][k]) and, on request, the expanded nodes [nq][want_cand]
         `table` is the PQ table storage the search ranks by: "f32", the
@@ -285,7 +287,7 @@ class Index:
         if want_phases:
             phases = torch.empty((nq, 7), dtype=torch.int32, device=q.device)
             opts.out_phases = phases.data_ptr()
-        _check(lib().bang_search(
+        _check(getattr(lib(), _entry)(
             self._h, qp, nq, k, L, _dev_ptr(ids, torch.int32, "ids"),
             _dev_ptr(dists, torch.float32, "dists"), ctypes.byref(opts),
             _stream(stream)))
@@ -299,6 +301,16 @@ class Index:
         if want_phases:
             res += (phases,)
         return res
+
+    def search_noalloc(self, q, k: int, L: int, out, table: str = "f32",
+                       query_L=None, query_k=None, rerank: str = "exact",
+                       abort=None, stream=None):
+        """bang_search_noalloc: the search with no device allocation into
+        the caller's `out` = (ids int32 [nq][k], dists float32 [nq][k])
+        CUDA tensors; the other arguments as in search.  Returns out."""
+        return self.search(q, k, L, out=out, table=table, query_L=query_L,
+                           query_k=query_k, rerank=rerank, abort=abort,
+                           stream=stream, _entry="bang_search_noalloc")
 
     def probe(self, nreads: int, seed: int = 0, stream=None) -> int:
         """Launch the random-row read probe (bang_index_probe) on `stream`

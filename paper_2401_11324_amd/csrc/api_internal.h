@@ -34,6 +34,9 @@ struct Workspace {
   uint32_t* seen_log = nullptr;
   uint32_t seen_words = 0;
   uint64_t seen_waves = 0;
+  // true for a fixed workspace that limits the resident grid to what its
+  // candidate buffer holds instead of failing (the no-allocation search)
+  bool clamp_grid = false;
 };
 
 int workspace_init(Workspace* ws, size_t cscratch_bytes);

@@ -283,6 +283,12 @@ int create_impl(const bang_index_desc* d, bang_index** out) {
   ix->dev.m = d->m;
   ix->dev.medoid = d->medoid;
   ix->dev.dtype = d->dtype;
+  // the no-allocation search's device memory on this GPU, found once
+  e = bang::noalloc_scratch_setup(ix->device);
+  if (e != hipSuccess) {
+    free_index(ix);
+    return hip_fail(e, "no-allocation scratch set-up");
+  }
   *out = ix;
   return BANG_OK;
 }
@@ -429,6 +435,17 @@ int search_with(bang_index* ix, Workspace* ws, bool grow, const void* queries,
                        &lds, &grid);
   if (rc) return rc;
   size_t need = (size_t)grid * iter_cap * sizeof(uint64_t);
+  if (need > ws->cscratch_bytes && ws->clamp_grid) {
+    // fewer resident waves, each with its whole candidate buffer
+    grid = ws->cscratch_bytes / ((size_t)iter_cap * sizeof(uint64_t));
+    if (grid == 0)
+      return fail(BANG_ENOMEM,
+                  "the no-allocation scratch (" +
+                      std::to_string(ws->cscratch_bytes) +
+                      " bytes of candidates) holds no wave of " +
+                      std::to_string(iter_cap) + " iterations");
+    need = (size_t)grid * iter_cap * sizeof(uint64_t);
+  }
   if (need > ws->cscratch_bytes) {
     if (!grow)
       return fail(BANG_ENOMEM, "search workspace of " +
@@ -574,6 +591,29 @@ int bang_search(bang_index* ix, const void* queries, uint64_t nq, uint32_t k,
   try {
     if (!ix) return fail(BANG_EINVAL, "null index");
     return bang::search_with(ix, &ix->ws, true, queries, nq, k, L, out_ids,
+                             out_dists, opts, static_cast<hipStream_t>(stream));
+  } catch (...) {
+    return fail(BANG_ENOMEM, "exception");
+  }
+}
+
+int bang_search_noalloc(bang_index* ix, const void* queries, uint64_t nq,
+                        uint32_t k, uint32_t L, uint32_t* out_ids,
+                        float* out_dists, const bang_search_opts* opts,
+                        void* stream) {
+  try {
+    if (!ix) return fail(BANG_EINVAL, "null index");
+    if (opts && opts->filter != BANG_FILTER_EXACT)
+      return fail(BANG_EUNSUPPORTED,
+                  "the no-allocation search has the set-union filter only");
+    void* p = bang::noalloc_scratch(ix->device);
+    if (!p) return fail(BANG_EDEVICE, "no-allocation scratch not set up");
+    bang::Workspace ws;
+    ws.qcounter = static_cast<uint32_t*>(p);
+    ws.cscratch = reinterpret_cast<uint64_t*>(static_cast<char*>(p) + 256);
+    ws.cscratch_bytes = bang::kNoallocScratchBytes - 256;
+    ws.clamp_grid = true;
+    return bang::search_with(ix, &ws, false, queries, nq, k, L, out_ids,
                              out_dists, opts, static_cast<hipStream_t>(stream));
   } catch (...) {
     return fail(BANG_ENOMEM, "exception");

@@ -5,7 +5,50 @@
 
 #include "search_kernel.h"
 
+#include <mutex>
+
 namespace bang {
+
+// Device memory of the no-allocation search (bang_search_noalloc): the two
+// launch counters in the first 256 bytes, then the expanded-node keys of
+// every resident wave.  Each GPU the library runs on holds its own copy
+// until the process ends; calls that overlap in time on one GPU share it
+// and race.  Host code addresses it only through the device pointer that
+// noalloc_scratch looked up for that GPU (the array's name is a host-side
+// stand-in, not a device address).
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_at[kMaxDevices];  // device address per GPU, once looked up
+}  // namespace
+
+hipError_t noalloc_scratch_setup(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_at[device]) return hipSuccess;
+  int cur = -1;
+  hipError_t e = hipGetDevice(&cur);
+  if (e != hipSuccess) return e;
+  if (cur != device) return hipErrorInvalidDevice;  // caller sets it current
+  void* p = nullptr;
+  e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  if (!p) return hipErrorInvalidSymbol;
+  // the counters start at zero (every search launch leaves them at zero)
+  e = hipMemset(p, 0, 256);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) return e;
+  g_scratch_at[device] = p;
+  return hipSuccess;
+}
+
+void* noalloc_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch_at[device];
+}
 
 namespace {
 

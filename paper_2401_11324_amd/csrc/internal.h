@@ -56,6 +56,15 @@ struct SearchLaunch {
   uint32_t grid;         // workgroups (one wave each)
 };
 
+// The no-allocation search's device memory: a file-scope array of
+// kNoallocScratchBytes per GPU (bang_kernels.hip).  setup looks its address
+// up on `device`, which must be current, and zeroes the launch counters; it
+// runs once per device (bang_index_create calls it).  noalloc_scratch
+// returns that address, or null before the setup.
+constexpr size_t kNoallocScratchBytes = (size_t)32 << 20;
+hipError_t noalloc_scratch_setup(int device);
+void* noalloc_scratch(int device);
+
 // True if (dtype, m, d/m) has a compiled kernel.
 bool supported(int dtype, uint32_t m, uint32_t dsub);
 
