@@ -74,10 +74,12 @@ WORKLOADS = {
                      32, 64, 1.2, 32, 10, 100_000, 10, (64,)),
     "sift1m": Workload("sift1m", 1, 1_000_000, 128, "u8", 1000, 0.0, 255.0,
                        20.0, 10_000, 64, 100, 1.2, 32, 10, 100_000, 10,
-                       (16, 32, 64, 128, 256, 512, 768, 1024)),
+                       (16, 32, 64, 128, 256, 512, 544, 576, 608, 640,
+                        704, 768, 1024)),
     "deep1m": Workload("deep1m", 2, 1_000_000, 96, "f32", 4096, 0.0, 0.0,
                        0.3, 10_000, 64, 100, 1.2, 48, 10, 100_000, 10,
-                       (16, 32, 64, 128, 192, 256, 384, 512), unit=True),
+                       (16, 32, 64, 96, 112, 128, 192, 256, 384, 512),
+                       unit=True),
 }
 
 

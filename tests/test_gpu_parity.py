@@ -280,8 +280,8 @@ def test_sift1m_full_batch_sampled_bit_exact():
     sample = np.sort(np.random.default_rng(2024).choice(len(q), 160,
                                                         replace=False))
     for L, table in [(L, "f32") for L in w.Ls if L <= 256] + [
-            (768, "f32"), (64, "f16"), (768, "f16"), (256, "u8"),
-            (768, "u8")]:
+            (608, "f32"), (768, "f32"), (64, "f16"), (608, "f16"),
+            (768, "f16"), (256, "u8"), (608, "u8"), (768, "u8")]:
         cap = oracle.iter_cap_for(L)
         ids, dist, cand, cnt = gi.search(qt, w.k, L, want_cand=cap,
                                          want_counters=True, table=table)
