@@ -1037,6 +1037,14 @@ __device__ __forceinline__ void load_row(const SearchArgs& a, uint32_t u,
   for (int i = 0; i < M / 16; ++i) code[i] = c[i];
 }
 
+// kPer consecutive worklist keys from p (LDS, 8-byte aligned) in one batch
+// of reads, with no branch between them.
+__device__ __forceinline__ void load_block(const uint64_t* p,
+                                           uint64_t (&x)[kPer]) {
+#pragma unroll
+  for (int t = 0; t < kPer; ++t) x[t] = p[t];
+}
+
 // Lanes past R hold no neighbour.
 __device__ __forceinline__ uint32_t row_mask(const SearchArgs& a, int lane,
                                              uint32_t nb) {
@@ -1511,31 +1519,35 @@ void search_kernel(SearchArgs a) {
         apos = cur + 1;
         akey = nx;
       } else {
-        // scan from the super-row holding u* (reads past Llen stay inside
-        // the buffer, which ends on a super-row boundary)
+        // scan from the super-row holding u*.  Each lane reads kPer
+        // entries at once whatever B is (no load waits behind a branch):
+        // those past its B belong to the next lane or, for the last lane
+        // of the last super-row, to the live-key buffer after the worklist,
+        // so every read stays inside the LDS block; they are not used.
         uint32_t ja = kNone;
         uint64_t va = kInf;
+        {
+          uint64_t x[kPer];
+          load_block(Lc + sbase + B * lane, x);
 #pragma unroll
-        for (int t = kPer - 1; t >= 0; --t) {
-          const uint32_t j = sbase + B * lane + t;
-          if ((uint32_t)t >= B) continue;
-          const uint64_t x = Lc[j];
-          if (j < Llen && j > cur && !(x & 1ull)) {
-            ja = j;
-            va = x;
+          for (int t = kPer - 1; t >= 0; --t) {
+            const uint32_t j = sbase + B * lane + t;
+            if ((uint32_t)t < B && j < Llen && j > cur && !(x[t] & 1ull)) {
+              ja = j;
+              va = x[t];
+            }
           }
         }
         uint64_t am = __ballot(ja != kNone);
         for (uint32_t base = sbase + sup; !am && base < Llen; base += sup) {
+          uint64_t x[kPer];
+          load_block(Lc + base + B * lane, x);
 #pragma unroll
           for (int t = kPer - 1; t >= 0; --t) {
             const uint32_t j = base + B * lane + t;
-            if ((uint32_t)t >= B) continue;
-            const uint64_t x = Lc[j];
-            const uint64_t v = j < Llen ? x : 1ull;
-            if (!(v & 1ull)) {
+            if ((uint32_t)t < B && j < Llen && !(x[t] & 1ull)) {
               ja = j;
-              va = v;
+              va = x[t];
             }
           }
           am = __ballot(ja != kNone);
@@ -1621,18 +1633,15 @@ void search_kernel(SearchArgs a) {
           excl_at[sr] = 0;
           hb_at[sr] = 0;
           if ((uint32_t)sr < nsup && (uint32_t)sr >= s0) {
-            const uint32_t base = sr * sup;
-            uint32_t tot = 0, hb = 0;
-#pragma unroll
-            for (int t = 0; t < kPer; ++t) {
-              // bytes past Llen count keys appended after every entry or
-              // are zero; they move no entry
-              if ((uint32_t)t < B) {
-                const uint32_t h = H[base + B * lane + t];
-                tot += h;
-                hb |= h << (8 * t);
-              }
-            }
+            // this lane's B histogram bytes from the two words holding
+            // them (bytes past Llen count keys appended after every entry
+            // or are zero; they move no entry)
+            const uint32_t o = sr * sup + B * lane;
+            const uint32_t w0 = Hw[o >> 2], w1 = Hw[(o >> 2) + 1];
+            uint32_t hb = __builtin_amdgcn_alignbyte(w1, w0, o & 3u);
+            if (B < 4) hb &= (1u << (8 * B)) - 1u;
+            const uint32_t tot = __builtin_amdgcn_udot4(hb, 0x01010101u, 0u,
+                                                        false);
             const uint32_t excl = wave_exclusive_scan(tot);
             excl_at[sr] = excl;
             hb_at[sr] = hb;
@@ -1640,17 +1649,16 @@ void search_kernel(SearchArgs a) {
           }
         }
       }
-      for (int sr = (int)nsup - 1; sr >= (int)s0; --sr) {
+#pragma unroll
+      for (int sr = kPer - 1; sr >= 0; --sr) {
+        if ((uint32_t)sr >= nsup || (uint32_t)sr < s0) continue;
         const uint32_t base = sr * sup;
         uint64_t v[kPer];
+        load_block(Lc + base + B * lane, v);  // as in the scan above
 #pragma unroll
         for (int t = 0; t < kPer; ++t) {
           const uint32_t j = base + B * lane + t;
-          v[t] = kInf;
-          if ((uint32_t)t < B) {
-            const uint64_t x = Lc[j];
-            v[t] = j < Llen ? x : kInf;
-          }
+          if ((uint32_t)t >= B || j >= Llen) v[t] = kInf;
           if (j == cur) v[t] |= 1ull;  // u*, marked visited
         }
         __syncthreads();  // the whole super-row is read before it moves
