@@ -1045,6 +1045,92 @@ __device__ __forceinline__ void load_block(const uint64_t* p,
   for (int t = 0; t < kPer; ++t) x[t] = p[t];
 }
 
+// Merge of the live new keys into the worklist (section "Parallel Merge":
+// position = own index + rank in the other list), in place.  Lc: the
+// worklist (Llen entries in super-rows of sup = 64*B, lane l owning B
+// consecutive entries of each); keep / kk / r: this lane's live key and
+// its worklist rank; idx: its index among the nv live keys; cur: u*,
+// marked visited on its way.  A new key's position is r + (live keys
+// below it); worklist entry j moves right by the live keys whose rank is
+// <= j, a prefix of the byte histogram H of live ranks over super-rows
+// s0 .. nsup-1 (NS = 1 when the worklist is a single super-row).  Every
+// LDS read goes out before the first write, so entries move in place; a
+// write with nothing to store goes to the lane's own slot of Nb, whose
+// live keys are no longer needed, instead of behind a branch.
+template <int NS>
+__device__ __forceinline__ void merge_live(
+    uint64_t* Lc, uint64_t* Nb, uint32_t* Hw, int lane, uint32_t B,
+    uint32_t sup, uint32_t Llen, uint32_t Lq, uint32_t cur, uint32_t nsup,
+    uint32_t s0, bool keep, uint64_t kk, uint32_t idx, uint32_t r,
+    uint32_t nv) {
+  uint64_t v[NS][kPer];
+  uint32_t o[NS];  // this lane's first position per super-row (also its
+                   // byte in H)
+#pragma unroll
+  for (int sr = 0; sr < NS; ++sr) {
+    // super-rows past the list read super-row 0 again (unused)
+    o[sr] = (NS == 1 || (uint32_t)sr < nsup ? sr * sup : 0u) + B * lane;
+    load_block(Lc + o[sr], v[sr]);
+  }
+  if (keep) {
+    Nb[idx] = kk;  // the live keys, compacted
+    atomicAdd(&Hw[r >> 2], 1u << (8 * (r & 3)));
+  }
+  if (lane < 4) Nb[nv + lane] = kInf;  // pad to a multiple of 4
+  __syncthreads();
+  // this lane's B histogram bytes per super-row, from the two words
+  // holding them (bytes past Llen count keys appended after every entry
+  // or are zero; they move no entry)
+  uint32_t w0[NS], w1[NS];
+#pragma unroll
+  for (int sr = 0; sr < NS; ++sr) {
+    w0[sr] = Hw[o[sr] >> 2];
+    w1[sr] = Hw[(o[sr] >> 2) + 1];
+  }
+  // rank among the live keys (their count below mine)
+  uint32_t rn = 0;
+  for (uint32_t j = 0; j < nv; j += 4) {
+    const uint64_t x0 = Nb[j], x1 = Nb[j + 1], x2 = Nb[j + 2], x3 = Nb[j + 3];
+    rn += (x0 < kk) + (x1 < kk) + (x2 < kk) + (x3 < kk);
+  }
+  const uint32_t bmask = B < 4 ? (1u << (8 * B)) - 1u : ~0u;
+  uint32_t hb[NS], shift0[NS];
+  uint32_t carry = 0;
+#pragma unroll
+  for (int sr = 0; sr < NS; ++sr) {
+    const bool act = (uint32_t)sr < nsup && (uint32_t)sr >= s0;
+    hb[sr] = act ? __builtin_amdgcn_alignbyte(w1[sr], w0[sr], o[sr] & 3u) &
+                       bmask
+                 : 0u;
+    const uint32_t tot = __builtin_amdgcn_udot4(hb[sr], 0x01010101u, 0u,
+                                                false);
+    uint32_t excl = 0;
+    if (NS == 1 || (uint32_t)sr < nsup) {
+      excl = wave_exclusive_scan(tot);
+      shift0[sr] = carry + excl;
+      carry += __builtin_amdgcn_readlane(excl + tot, kWave - 1);
+    } else {
+      shift0[sr] = carry;
+    }
+  }
+#pragma unroll
+  for (int sr = 0; sr < NS; ++sr) {
+    if ((uint32_t)sr >= nsup || (uint32_t)sr < s0) continue;
+    const uint32_t j0 = sr * sup + B * lane;
+    uint32_t p = j0 + shift0[sr];
+#pragma unroll
+    for (int t = 0; t < kPer; ++t) {
+      p += __builtin_amdgcn_ubfe(hb[sr], 8 * t, 8);
+      const uint32_t j = j0 + t;
+      const bool ok = (uint32_t)t < B && j < Llen && p < Lq;
+      uint64_t* dst = ok ? Lc + p : Nb + lane;
+      *dst = v[sr][t] | (uint64_t)(j == cur);
+      ++p;
+    }
+  }
+  if (keep && r + rn < Lq) Lc[r + rn] = kk;
+}
+
 // Lanes past R hold no neighbour.
 __device__ __forceinline__ uint32_t row_mask(const SearchArgs& a, int lane,
                                              uint32_t nb) {
@@ -1599,81 +1685,18 @@ void search_kernel(SearchArgs a) {
       const uint32_t rmin = first_of(r, __ballot(kk == bkey));
       const uint32_t idx = __builtin_amdgcn_mbcnt_hi(
           (uint32_t)(km >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)km, 0u));
-      if (keep) {
-        Nb[idx] = kk;  // the live keys, compacted
-        atomicAdd(&Hw[r >> 2], 1u << (8 * (r & 3)));
-      }
-      if (lane < 4) Nb[nv + lane] = kInf;  // pad to a multiple of 4
-      __syncthreads();
-
-      // rank among the live keys (their count below mine)
-      uint32_t rn = 0;
-      for (uint32_t j = 0; j < nv; j += 4) {
-        const uint64_t x0 = Nb[j], x1 = Nb[j + 1], x2 = Nb[j + 2], x3 = Nb[j + 3];
-        rn += (x0 < kk) + (x1 < kk) + (x2 < kk) + (x3 < kk);
-      }
-
-      // merge: position = own index + rank in the other list.  New keys
-      // below worklist entry j = H[0] + ... + H[j] (live keys whose
-      // worklist rank is <= j): a prefix over super-rows of 64*B entries.
-      // In place: entries only move right, so the super-rows are moved from
-      // the last to the first, each read completely before it is written;
-      // the new keys go last, into the gaps.  Pass 1 gets each super-row's
-      // prefix from the histogram alone.
-      const uint32_t nsup = (Llen + sup - 1) / sup;
-      const uint32_t s0 = rmin / sup;  // first super-row with a moving entry
-      uint32_t carry_at[kPer];  // prefix before super-row s (s < 4 rows)
-      uint32_t excl_at[kPer];
-      uint32_t hb_at[kPer];     // this lane's B histogram bytes, per row
-      {
-        uint32_t carry = 0;
-#pragma unroll
-        for (int sr = 0; sr < kPer; ++sr) {
-          carry_at[sr] = carry;
-          excl_at[sr] = 0;
-          hb_at[sr] = 0;
-          if ((uint32_t)sr < nsup && (uint32_t)sr >= s0) {
-            // this lane's B histogram bytes from the two words holding
-            // them (bytes past Llen count keys appended after every entry
-            // or are zero; they move no entry)
-            const uint32_t o = sr * sup + B * lane;
-            const uint32_t w0 = Hw[o >> 2], w1 = Hw[(o >> 2) + 1];
-            uint32_t hb = __builtin_amdgcn_alignbyte(w1, w0, o & 3u);
-            if (B < 4) hb &= (1u << (8 * B)) - 1u;
-            const uint32_t tot = __builtin_amdgcn_udot4(hb, 0x01010101u, 0u,
-                                                        false);
-            const uint32_t excl = wave_exclusive_scan(tot);
-            excl_at[sr] = excl;
-            hb_at[sr] = hb;
-            carry += __builtin_amdgcn_readlane(excl + tot, kWave - 1);
-          }
-        }
-      }
-#pragma unroll
-      for (int sr = kPer - 1; sr >= 0; --sr) {
-        if ((uint32_t)sr >= nsup || (uint32_t)sr < s0) continue;
-        const uint32_t base = sr * sup;
-        uint64_t v[kPer];
-        load_block(Lc + base + B * lane, v);  // as in the scan above
-#pragma unroll
-        for (int t = 0; t < kPer; ++t) {
-          const uint32_t j = base + B * lane + t;
-          if ((uint32_t)t >= B || j >= Llen) v[t] = kInf;
-          if (j == cur) v[t] |= 1ull;  // u*, marked visited
-        }
-        __syncthreads();  // the whole super-row is read before it moves
-        uint32_t sh = 0;
-#pragma unroll
-        for (int t = 0; t < kPer; ++t) {
-          const uint32_t j = base + B * lane + t;
-          sh += (hb_at[sr] >> (8 * t)) & 0xFFu;
-          if (v[t] != kInf) {
-            const uint32_t p = j + carry_at[sr] + excl_at[sr] + sh;
-            if (p < Lq) Lc[p] = v[t];
-          }
-        }
-      }
-      if (keep && r + rn < Lq) Lc[r + rn] = key;
+      // super-rows in use and the first one with a moving entry (Llen and
+      // rmin are below 4 super-rows: B is capped so that L fits in kPer)
+      const uint32_t nsup =
+          1u + (Llen > sup) + (Llen > 2u * sup) + (Llen > 3u * sup);
+      const uint32_t s0 = (rmin >= sup) + (rmin >= 2u * sup) +
+                          (rmin >= 3u * sup);
+      if (nsup == 1)
+        merge_live<1>(Lc, Nb, Hw, lane, B, sup, Llen, Lq, cur, nsup, s0, keep,
+                      kk, idx, r, nv);
+      else
+        merge_live<kPer>(Lc, Nb, Hw, lane, B, sup, Llen, Lq, cur, nsup, s0,
+                         keep, kk, idx, r, nv);
       // clear the histogram bytes used (positions rmin .. Llen)
       for (uint32_t t = rmin / 4 + lane; t <= Llen / 4; t += kWave) Hw[t] = 0u;
       Llen = min(Lq, Llen + nv);
