@@ -8,8 +8,10 @@ the HBM roofline, and the CPU oracle timed on the host.
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--L L]
 
 Prints one JSON line; `value` is the plain FP32 form's QPS and
-`precision_form` holds the reduced-precision measurements.  A step is one
-bang_search call over the 10,000 resident queries; each form's timed region
+`precision_form` holds the reduced-precision measurements (FP16 / u8 table
+storage, and each form ranking by tables built with BF16 MFMA).  A step is
+one bang_search call over the 10,000 resident queries (with BF16-MFMA
+tables: their build, then the search); each form's timed region
 holds exactly K steps, bracketed by a device synchronisation on both sides,
 each step bracketed by HIP events on the stream the kernel runs on.
 """
@@ -31,6 +33,7 @@ METRIC = ("QPS at recall@10>=0.9 on 1 GPU, plain FP32 vs reduced-precision "
           "form; p50/p99 ms")
 WORKLOAD = "sift1m"
 HBM_PEAK_GBS = 8000.0
+BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 MFMA
 # MI355X's host link: PCIe 5.0 x16, 64 GB/s per direction
 HOST_LINK_PEAK_GBS = 64.0
 TARGET_RECALL = 0.9
@@ -240,11 +243,64 @@ def deep_section(a, bang, torch):
         rec["recall_equal_to_exact_rerank"] = rec["recall10"] == \
             out["forms"][t]["recall10"]
         out["forms"][t + "+bf16_rerank"] = rec
+    # the tables by BF16 MFMA with FP32 accumulation (a step builds them,
+    # then searches by them), each PQ form at its point; and the whole
+    # precision form: BF16-MFMA tables stored as FP16 / u8, then the BF16
+    # re-rank with the FP32 recheck
+    for t in TABLES:
+        rec = run.measure(t, out["forms"][t]["L"], bf16_tables=True)
+        rec["recall_lost_vs_fp32_tables_same_L"] = round(
+            out["forms"][t]["recall10"] - rec["recall10"], 4)
+        out["forms"][t + "+bf16_mfma_tables"] = rec
+    for t in ("f16", "u8"):
+        rec = run.measure(t, out["forms"][t]["L"], bf16_tables=True,
+                          rerank="bf16")
+        rec["recall_lost_vs_f32_same_L"] = round(
+            by[("f32", rec["L"])] - rec["recall10"], 4)
+        out["forms"][t + "+bf16_mfma_tables+bf16_rerank"] = rec
+    out["table_build"] = table_build_section(run)
     base = out["forms"]["f32"]["qps"]
     for t in out["forms"]:
         out["forms"][t]["speedup_vs_f32"] = round(
             out["forms"][t]["qps"] / base, 3)
     run.gi.close()
+    return out
+
+
+def table_build_section(run, reps=20):
+    """Stage 1 alone for the whole query batch: the FP32 table kernel
+    against the BF16-MFMA one (bang_build_pq_tables_bf16), each as time,
+    table bytes written per second and, for the MFMA build, its inner-
+    product FLOP rate against the BF16 dense peak (2 nq m 256 ds FLOP,
+    d/m padded to the MFMA's K of 4)."""
+    torch, gi, q = run.torch, run.gi, run.q
+    stream = torch.cuda.current_stream()
+    nq, m = q.shape[0], run.w.m
+    ds = run.w.d // m
+    out = {"queries": nq, "table_bytes": nq * m * 256 * 4}
+    for name, bf in (("fp32", False), ("bf16_mfma", True)):
+        T = gi.build_pq_tables(q, bf16=bf)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            gi.build_pq_tables(q, out=T, bf16=bf)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        ms = float(np.mean(ts))
+        rec = {"ms": round(ms, 4),
+               "written_gbs": round(out["table_bytes"] / (ms / 1e3) / 1e9, 1)}
+        if bf:
+            kpad = -(-ds // 4) * 4
+            fl = 2.0 * nq * m * 256 * kpad
+            rec["mfma_tflops"] = round(fl / (ms / 1e3) / 1e12, 4)
+            rec["mfma_frac_of_bf16_peak"] = round(
+                fl / (ms / 1e3) / 1e12 / BF16_PEAK_TFLOPS, 6)
+            rec["k_used_of_padded"] = f"{ds}/{kpad}"
+        out[name] = rec
     return out
 
 
@@ -618,15 +674,17 @@ class Runner:
         ok = [s for s in rows if s["recall10"] >= TARGET_RECALL]
         return ok[0]["L"] if ok else max(rows, key=lambda s: s["recall10"])["L"]
 
-    def adc_error(self, table, cand, iters, nq=100, per_q=256):
+    def adc_error(self, table, cand, iters, nq=100, per_q=256,
+                  bf16_tables=False):
         """Relative error of the distance the search ranks by under a table
         form, against the ADC in FP64 (the same codes, the codebooks and
         query in FP64), over the first nq queries and up to per_q of each
-        one's expanded nodes (the nodes the search ranked)."""
+        one's expanded nodes (the nodes the search ranked); bf16_tables:
+        the table built by BF16 MFMA."""
         torch = self.torch
         d, m = self.d, self.w.m
         ds = self.w.d // m
-        T = self.gi.build_pq_tables(self.q[:nq])
+        T = self.gi.build_pq_tables(self.q[:nq], bf16=bf16_tables)
         torch.cuda.synchronize()
         T = T.cpu().numpy().reshape(nq, m, 256)
         cb = d["codebooks"].astype(np.float64)  # [m][256][ds]
@@ -673,8 +731,11 @@ class Runner:
                 "bf16_mean": float(e16.mean()),
                 "fp32_max": float(e32.max()), "fp32_mean": float(e32.mean())}
 
-    def measure(self, table, L, index=None, filter="exact", rerank="exact"):
-        """K timed steps of one form; returns its record."""
+    def measure(self, table, L, index=None, filter="exact", rerank="exact",
+                bf16_tables=False):
+        """K timed steps of one form; returns its record.  bf16_tables: a
+        step is the BF16-MFMA table build followed by the search ranking by
+        those tables."""
         torch, w, a = self.torch, self.w, self.a
         gi_ = index or self.gi
         q, dev, gt = self.q, self.dev, self.gt
@@ -682,17 +743,23 @@ class Runner:
         nq, k = q.shape[0], w.k
         ids = torch.empty((nq, k), dtype=torch.int32, device=dev)
         dist = torch.empty((nq, k), dtype=torch.float32, device=dev)
-        for _ in range(a.warmup):
+        tabs = (gi_.build_pq_tables(q, bf16=True) if bf16_tables else None)
+
+        def step():
+            if bf16_tables:
+                gi_.build_pq_tables(q, out=tabs, bf16=True)
             gi_.search(q, k, L, out=(ids, dist), table=table, filter=filter,
-                       rerank=rerank)
+                       rerank=rerank, tables=tabs)
+
+        for _ in range(a.warmup):
+            step()
         torch.cuda.synchronize()
         ev = [(torch.cuda.Event(enable_timing=True),
                torch.cuda.Event(enable_timing=True)) for _ in range(a.steps)]
         wall0 = time.perf_counter()
         for e0, e1 in ev:
             e0.record(stream)
-            gi_.search(q, k, L, out=(ids, dist), table=table, filter=filter,
-                       rerank=rerank)
+            step()
             e1.record(stream)
         torch.cuda.synchronize()
         wall = time.perf_counter() - wall0
@@ -710,7 +777,8 @@ class Runner:
         _, _, cand, cnt, times = gi_.search(q, k, L, want_cand=cap,
                                            want_counters=True,
                                            want_times=True, table=table,
-                                           filter=filter, rerank=rerank)
+                                           filter=filter, rerank=rerank,
+                                           tables=tabs)
         torch.cuda.synchronize()
         cand = cand.cpu().numpy().view(np.uint32)
         cnt = cnt.cpu().numpy()
@@ -736,6 +804,7 @@ class Runner:
                                   iters, cand, 4 * L, exact=exact)
         ms_step = wall * 1e3 / a.steps
         recd = {"table": table, "L": L, "filter": filter, "rerank": rerank,
+                "table_build": "bf16_mfma" if bf16_tables else "fp32",
                 "recall10": round(rec, 4),
                 "adjacency_bytes_per_launch": int(iters.astype(np.int64).sum()
                                                   * 4 * w.R),
@@ -755,7 +824,8 @@ class Runner:
                 "result_rel_dist_err_vs_fp64": float(rel.max()) if rel.size
                 else 0.0}
         if not exact:
-            recd["adc_rel_err_vs_fp64"] = self.adc_error(table, cand, iters)
+            recd["adc_rel_err_vs_fp64"] = self.adc_error(
+                table, cand, iters, bf16_tables=bf16_tables)
         if rerank == "bf16":
             ncand = np.minimum(iters.astype(np.int64), 4 * L)
             recd["bf16_rerank"] = {
@@ -839,6 +909,14 @@ def main(argv=None):
 
     plain = measure("f32", pick_L("f32"))
     prec = {t: measure(t, pick_L(t)) for t in ("f16", "u8")}
+    # the same forms ranking by tables built with BF16 MFMA (a step builds
+    # them, then searches by them), at each form's point
+    for t, rec0 in (("f32", plain), ("f16", prec["f16"]), ("u8", prec["u8"])):
+        rec = measure(t, rec0["L"], bf16_tables=True)
+        rec["recall_lost_vs_fp32_tables_same_L"] = round(
+            rec0["recall10"] - rec["recall10"], 4)
+        prec[t + "+bf16_mfma_tables"] = rec
+    prec["table_build"] = table_build_section(run)
     # the paper's Exact-distance Version: no table, no re-rank
     exact = None if a.no_sweep and not a.L else measure("exact",
                                                          pick_L("exact"))

@@ -154,6 +154,15 @@ typedef struct {
                                keep their results. */
   uint32_t rerank;          /* BANG_RERANK_EXACT (default) or
                                BANG_RERANK_BF16 */
+  const float* tables;      /* NULL, or device [nq][m][256] FP32 PQ tables
+                               built beforehand (bang_build_pq_tables or
+                               bang_build_pq_tables_bf16): query i is
+                               searched by tables[i] (stored in the table
+                               form above) instead of a table the search
+                               builds; 4-byte aligned; not with
+                               BANG_TABLE_EXACT.  With the tables of
+                               bang_build_pq_tables the results are those of
+                               the search without this option. */
 } bang_search_opts;
 
 /* Re-rank forms (float data; integer data is always re-ranked exactly).
@@ -250,6 +259,20 @@ int bang_index_destroy(bang_index* index);
  * [nq][m][256] FP32.  nq = 0 is a no-op. */
 int bang_build_pq_tables(bang_index* index, const void* queries, uint64_t nq,
                          float* tables_out, void* stream);
+
+/* The precision form's table build (stage 1 by matrix cores): the same
+ * tables with BF16 MFMA and FP32 accumulation.  tables_out[q][j][c] =
+ * |q_j|^2 + |c_jc|^2 - 2 <bf16(q_j), bf16(c_jc)>, the squared norms summed
+ * in FP32 from the unrounded coordinates in order, the inner product of
+ * the coordinates rounded to bfloat16 (nearest, ties to even) by
+ * v_mfma_f32_32x32x4_2b_bf16 (FP32 accumulation in the hardware's order).
+ * Its error against the exact table is at most about 2^-6 sum_t |q_t c_t|
+ * (bfloat16 rounding of both factors), so the search's ids can differ from
+ * those of the FP32 tables where that moves a key.  Arguments as
+ * bang_build_pq_tables; feed the result to bang_search through
+ * bang_search_opts.tables. */
+int bang_build_pq_tables_bf16(bang_index* index, const void* queries,
+                              uint64_t nq, float* tables_out, void* stream);
 
 /* Stages 1-3 (Algorithm 2 with the in-memory graph, then the re-rank of
  * section "Re-ranking"): for each query, greedy search from the medoid with

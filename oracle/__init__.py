@@ -14,6 +14,8 @@ in oracle.c):
                      the filtered form of Algorithm 2), re-rank; or the
                      Exact-distance Version (no table, no re-rank)
 * ``rerank``         stage 3 alone over given candidates
+* ``pq_table_terms`` / ``bf16_table_bound``   the table in FP64 and the
+                     error bound of its BF16-MFMA form (precision form)
 * ``bruteforce``     exact k nearest (ground truth)
 * ``train_pq`` / ``pq_encode``   PQ codebooks (k-means) and codes
 * ``medoid`` / ``vamana_build`` / ``robust_prune`` / ``connect`` /
@@ -294,6 +296,69 @@ def rerank(index: Index, queries: np.ndarray, cand: np.ndarray, k: int,
 def bf16_round(x: float) -> float:
     """x rounded to bfloat16 (nearest, ties to even), as a float."""
     return float(lib().or_bf16_round(float(x)))
+
+
+def bf16_round_array(x: np.ndarray) -> np.ndarray:
+    """Every element rounded to bfloat16 (nearest, ties to even), as FP64:
+    the nearest number with an 8-bit significand, found from the FP64
+    significand scaled to 8 integer bits and rounded half to even.  Finite
+    inputs in the normal range of bfloat16 (every table input here)."""
+    x = np.asarray(x, dtype=np.float64)
+    m, e = np.frexp(x)                 # x = m * 2^e, 0.5 <= |m| < 1
+    return np.ldexp(np.rint(np.ldexp(m, 8)), e - 8)
+
+
+# unit roundoffs: bfloat16 (8-bit significand) and FP32 (24-bit)
+BF16_U = 2.0 ** -8
+FP32_U = 2.0 ** -24
+
+
+def pq_table_terms(queries: np.ndarray, codebooks: np.ndarray):
+    """The PQ table of section "Construction of PQDistTable in Parallel" in
+    FP64 with the sums its error bounds need, per (query, subspace j,
+    centroid c) with t over the subspace's coordinates: T = sum (q_t -
+    c_t)^2 (exact to FP64 rounding), S_qc = sum |q_t c_t|, S_qq = sum q_t^2,
+    S_cc = sum c_t^2, and T_b = |q|^2 + |c|^2 - 2 sum bf16(q_t) bf16(c_t),
+    the table with both factors of the inner product rounded to bfloat16.
+    Each [nq][m][256]."""
+    q = np.asarray(queries, dtype=np.float64)
+    cb = np.asarray(codebooks, dtype=np.float64)      # [m][256][ds]
+    m, _, ds = cb.shape
+    qs = q.reshape(q.shape[0], m, 1, ds)
+    cs = cb[None]
+    T = ((qs - cs) ** 2).sum(-1)
+    S_qc = np.abs(qs * cs).sum(-1)
+    S_qq = (qs ** 2).sum(-1) + 0.0 * S_qc
+    S_cc = (cs ** 2).sum(-1) + 0.0 * S_qc
+    Tb = S_qq + S_cc - 2.0 * (bf16_round_array(qs) *
+                              bf16_round_array(cs)).sum(-1)
+    return T, S_qc, S_qq, S_cc, Tb
+
+
+def bf16_table_bound(queries: np.ndarray, codebooks: np.ndarray):
+    """(T, E): the exact table and a bound E on |T~ - T| for the table
+    built by BF16 MFMA with FP32 accumulation, T~ = fl(fl(|q|^2 + |c|^2) -
+    2 X~), where |q|^2 and |c|^2 are FP32 sums of the unrounded
+    coordinates and X~ the FP32-accumulated inner product of the
+    coordinates rounded to bfloat16.  With u = 2^-8 and v = 2^-24:
+      * rounding both factors: |bf16(q)bf16(c) - qc| <= (2u + u^2)|qc|;
+      * the products are exact in FP32 (8-bit significands) and their
+        ds-term sum, in any order, errs by at most g S~ with g = (ds+1) v
+        and S~ <= (1 + u)^2 S_qc;
+      * each norm errs by at most g times itself, their sum and the last
+        subtraction by v times their magnitudes (<= S_qq + S_cc + 2 S~).
+    So E = 2 (2u + u^2 + g (1 + u)^2) S_qc + g (S_qq + S_cc)
+           + 2 v (S_qq + S_cc + 2 (1 + u)^2 S_qc), doubled for margin in
+    the FP32 terms only."""
+    T, S_qc, S_qq, S_cc, _ = pq_table_terms(queries, codebooks)
+    ds = np.asarray(codebooks).shape[2]
+    u, v = BF16_U, FP32_U
+    g = (ds + 1) * v
+    w = (1.0 + u) ** 2
+    E = (2.0 * (2.0 * u + u * u) * S_qc
+         + 2.0 * (2.0 * g * w * S_qc + g * (S_qq + S_cc)
+                  + 2.0 * v * (S_qq + S_cc + 2.0 * w * S_qc)))
+    return T, E
 
 
 def bf16_band(index: Index, query: np.ndarray, ids: np.ndarray):

@@ -31,7 +31,8 @@ FILTERS = {"exact": 0, "bloom": 1, "seen": 2}
 ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EUNSUPPORTED",
           -5: "EABORTED"}
 EXPORTS = ("bang_index_create", "bang_index_destroy", "bang_build_pq_tables",
-           "bang_search", "bang_search_noalloc", "bang_rerank",
+           "bang_build_pq_tables_bf16", "bang_search", "bang_search_noalloc",
+           "bang_rerank",
            "bang_index_probe",
            "bang_server_create",
            "bang_server_destroy", "bang_server_submit", "bang_server_wait",
@@ -63,7 +64,8 @@ class SearchOpts(ctypes.Structure):
                 ("table", ctypes.c_uint32), ("flags", ctypes.c_uint32),
                 ("query_L", ctypes.c_void_p), ("query_k", ctypes.c_void_p),
                 ("filter", ctypes.c_uint32), ("out_phases", ctypes.c_void_p),
-                ("abort", ctypes.c_void_p), ("rerank", ctypes.c_uint32)]
+                ("abort", ctypes.c_void_p), ("rerank", ctypes.c_uint32),
+                ("tables", ctypes.c_void_p)]
 
 
 class ServerOpts(ctypes.Structure):
@@ -90,6 +92,7 @@ def lib():
                                         ctypes.POINTER(P)]
         L.bang_index_destroy.argtypes = [P]
         L.bang_build_pq_tables.argtypes = [P, P, u64, P, P]
+        L.bang_build_pq_tables_bf16.argtypes = [P, P, u64, P, P]
         L.bang_search.argtypes = [P, P, u64, u32, u32, P, P,
                                   ctypes.POINTER(SearchOpts), P]
         L.bang_search_noalloc.argtypes = L.bang_search.argtypes
@@ -210,8 +213,10 @@ class Index:
             raise ValueError(f"queries must be [nq][{self.d}]")
         return _dev_ptr(q, want, "queries")
 
-    def build_pq_tables(self, q, out=None, stream=None):
-        """Stage 1: tables [nq][m][256] float32 on the queries' device."""
+    def build_pq_tables(self, q, out=None, stream=None, bf16: bool = False):
+        """Stage 1: tables [nq][m][256] float32 on the queries' device;
+        bf16=True builds them by BF16 MFMA with FP32 accumulation
+        (bang_build_pq_tables_bf16)."""
         import torch
         qp = self._queries(q)
         if out is None:
@@ -219,9 +224,10 @@ class Index:
                               device=q.device)
         elif tuple(out.shape) != (q.shape[0], self.m, 256):
             raise ValueError(f"out must have shape ({q.shape[0]}, {self.m}, 256)")
-        _check(lib().bang_build_pq_tables(
-            self._h, qp, q.shape[0], _dev_ptr(out, torch.float32, "out"),
-            _stream(stream)))
+        fn = (lib().bang_build_pq_tables_bf16 if bf16
+              else lib().bang_build_pq_tables)
+        _check(fn(self._h, qp, q.shape[0], _dev_ptr(out, torch.float32, "out"),
+                  _stream(stream)))
         return out
 
     def search(self, q, k: int, L: int, c_max: int = 0, iter_cap: int = 0,
@@ -230,7 +236,8 @@ class Index:
                rerank_global: bool = False, query_L=None, query_k=None,
                filter: str = "exact", want_phases: bool = False, out=None,
                abort=None, rerank: str = "exact", stream=None,
-               seen_log_short: bool = False, _entry: str = "bang_search"):
+               seen_log_short: bool = False, tables=None,
+               _entry: str = "bang_search"):
         """Stages 1-3.  Returns (ids uint32-as-int32 [nq][k], dists
         float32 [nq][k]) and, on request, the expanded nodes [nq][want_cand]
         `table` is the PQ table storage the search ranks by: "f32", the
@@ -247,7 +254,10 @@ class Index:
         a timed copy of the search).  abort: a StopRequest the search
         obeys (bang_search_opts.abort).  rerank: "exact" or "bf16" (float
         data on an index with bf16_base; the same answer, counters[:, 2]
-        the candidates recomputed in FP32).  seen_log_short: with the
+        the candidates recomputed in FP32).  tables: float32 CUDA tensor
+        [nq][m][256] of PQ tables built beforehand (build_pq_tables,
+        optionally bf16=True) that the search ranks by instead of building
+        its own.  seen_log_short: with the
         "seen" filter, stop setting bits after 64 logged ids and only test
         from then on (BANG_SEARCH_SEEN_LOG_SHORT; for testing)."""
         import torch
@@ -266,6 +276,10 @@ class Index:
         if abort is not None:
             opts.abort = abort._h.value
         opts.rerank = RERANKS[rerank]
+        if tables is not None:
+            if tuple(tables.shape) != (nq, self.m, 256):
+                raise ValueError(f"tables must have shape ({nq}, {self.m}, 256)")
+            opts.tables = _dev_ptr(tables, torch.float32, "tables").value
         for t, nm in ((query_L, "query_L"), (query_k, "query_k")):
             if t is not None:
                 if tuple(t.shape) != (nq,):

@@ -421,6 +421,12 @@ int search_with(bang_index* ix, Workspace* ws, bool grow, const void* queries,
   if (rerank == BANG_RERANK_BF16 && table == BANG_TABLE_EXACT)
     return fail(BANG_EINVAL,
                 "the exact-distance search has no re-rank to make BF16");
+  const float* const tables = o ? o->tables : nullptr;
+  if (tables && table == BANG_TABLE_EXACT)
+    return fail(BANG_EINVAL,
+                "the exact-distance search has no table to take (tables)");
+  if (tables && !aligned(tables, 4))
+    return fail(BANG_EINVAL, "tables not 4-byte aligned");
 
   size_t lds;
   uint64_t grid;
@@ -521,6 +527,7 @@ int search_with(bang_index* ix, Workspace* ws, bool grow, const void* queries,
   l.out_phases = phases;
   l.cscratch = ws->cscratch;
   l.qcounter = ws->qcounter;
+  l.tables = tables;
   l.bloom = filter == BANG_FILTER_BLOOM ? ws->bloom : nullptr;
   l.bloom_epoch = filter == BANG_FILTER_BLOOM ? ws->bloom_epoch : nullptr;
   if (filter == BANG_FILTER_SEEN) {
@@ -579,6 +586,28 @@ int bang_build_pq_tables(bang_index* ix, const void* queries, uint64_t nq,
     e = bang::launch_tables(ix->dev, queries, nq, tables_out,
                             static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "table launch");
+    return BANG_OK;
+  } catch (...) {
+    return fail(BANG_ENOMEM, "exception");
+  }
+}
+
+int bang_build_pq_tables_bf16(bang_index* ix, const void* queries,
+                              uint64_t nq, float* tables_out, void* stream) {
+  try {
+    if (!ix) return fail(BANG_EINVAL, "null index");
+    if (nq == 0) return BANG_OK;
+    int rc = check_queries(ix, queries);
+    if (rc) return rc;
+    if (!tables_out || !aligned(tables_out, 16))
+      return fail(BANG_EINVAL, "tables_out null or not 16-byte aligned");
+    if (ix->dev.d / ix->dev.m > 8)
+      return fail(BANG_EUNSUPPORTED, "d/m above 8");
+    hipError_t e = hipSetDevice(ix->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    e = bang::launch_tables_mfma(ix->dev, queries, nq, tables_out,
+                                 static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "BF16 MFMA table launch");
     return BANG_OK;
   } catch (...) {
     return fail(BANG_ENOMEM, "exception");

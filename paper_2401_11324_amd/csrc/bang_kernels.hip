@@ -188,6 +188,113 @@ __device__ __forceinline__ uint16_t to_bf16(float x) {
   return (uint16_t)((b + 0x7FFFu + ((b >> 16) & 1u)) >> 16);
 }
 
+// The PQ table with BF16 MFMA and FP32 accumulation (the precision form's
+// table build): T[q][j][c] = |q_j|^2 + |c|^2 - 2 <bf16(q_j), bf16(c)>,
+// the norms summed in FP32 from the unrounded coordinates, in order.  One
+// wave per tile of 32 queries: for each subspace, v_mfma_f32_32x32x4_2b_bf16
+// multiplies the 32 queries (rows, K = 4 coordinates per block) by 64
+// centroids (block b holds 32 of them), so four MFMAs cover the 256
+// centroids of a subspace of d/m = 4; d/m = 2 pads K with zeros, d/m = 8
+// takes two K chunks; each wave covers kMfmaJ subspaces.  Lane layout
+// (gfx950): A and B lane l feed block
+// l / 32, row or column l % 32; result register v of lane l is block
+// v / 16, row 8 ((v % 16) / 4) + 4 (l / 32) + v % 4, column l % 32.
+typedef short bf16x4_t __attribute__((ext_vector_type(4)));
+typedef float f32x32_t __attribute__((ext_vector_type(32)));
+
+constexpr int kMfmaJ = 8;  // subspaces per wave (grid y = m / kMfmaJ)
+
+template <int DT, int M, int DS>
+__global__ __launch_bounds__(64) void table_mfma_kernel(
+    const unsigned char* __restrict__ queries, uint64_t nq,
+    const float* __restrict__ cb, float* __restrict__ out) {
+  constexpr int D = M * DS;
+  constexpr int KC = (DS + 3) / 4;  // K chunks of 4 coordinates
+  static_assert(M % kMfmaJ == 0, "subspaces are taken kMfmaJ at a time");
+  __shared__ float qn_s[kMfmaJ][32];  // |q_j|^2 of the tile's 32 queries
+  const int lane = threadIdx.x;
+  const int half = lane >> 5, i = lane & 31;
+  const uint64_t q0 = (uint64_t)blockIdx.x * 32;
+  const int j0 = blockIdx.y * kMfmaJ;
+  // this lane's query row (rows past nq read query q0, and are not written)
+  const uint64_t qa = q0 + i < nq ? q0 + i : q0;
+  const unsigned char* q = queries + qa * D * Elem<DT>::size;
+  if (half == 0) {
+    for (int jj = 0; jj < kMfmaJ; ++jj) {
+      float s = 0.0f;
+#pragma unroll
+      for (int t = 0; t < DS; ++t) {
+        const float v = Elem<DT>::f(q, (j0 + jj) * DS + t);
+        s = s + v * v;
+      }
+      qn_s[jj][i] = s;
+    }
+  }
+  __syncthreads();
+  for (int j = j0; j < j0 + kMfmaJ; ++j) {
+    bf16x4_t a[KC];
+#pragma unroll
+    for (int kc = 0; kc < KC; ++kc)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int t = kc * 4 + k;
+        a[kc][k] = t < DS ? (short)to_bf16(Elem<DT>::f(q, j * DS + t)) : 0;
+      }
+    float qn[16];  // |q_j|^2 of the rows this lane's results belong to
+#pragma unroll
+    for (int v = 0; v < 16; ++v)
+      qn[v] = qn_s[j - j0][8 * (v / 4) + 4 * half + v % 4];
+#pragma unroll
+    for (int c4 = 0; c4 < 4; ++c4) {
+      const int cb0 = 64 * c4;
+      const float* cen = cb + ((size_t)j * 256 + cb0 + 32 * half + i) * DS;
+      bf16x4_t b[KC];
+      float cn = 0.0f;
+#pragma unroll
+      for (int kc = 0; kc < KC; ++kc)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int t = kc * 4 + k;
+          const float v = t < DS ? cen[t] : 0.0f;
+          b[kc][k] = (short)to_bf16(v);
+          if (t < DS) cn = cn + v * v;
+        }
+      // |c|^2 of block 0's and block 1's column of this lane
+      const float cn_other = __shfl_xor(cn, 32);
+      const float cnb[2] = {half == 0 ? cn : cn_other,
+                            half == 0 ? cn_other : cn};
+      f32x32_t acc = {};
+#pragma unroll
+      for (int kc = 0; kc < KC; ++kc)
+        acc = __builtin_amdgcn_mfma_f32_32x32x4bf16_1k(a[kc], b[kc], acc, 0,
+                                                       0, 0);
+#pragma unroll
+      for (int v = 0; v < 32; ++v) {
+        const int blk = v / 16, vv = v % 16;
+        const uint64_t row = q0 + 8 * (vv / 4) + 4 * half + vv % 4;
+        if (row < nq) {
+          const float tq = qn[vv] + cnb[blk];
+          out[row * (uint64_t)M * 256 + (uint64_t)j * 256 + cb0 + 32 * blk +
+              i] = tq - 2.0f * acc[v];
+        }
+      }
+    }
+  }
+}
+
+template <int DT, int M, int DS>
+struct RunTablesMfma {
+  static hipError_t run(const unsigned char* q, uint64_t nq, const float* cb,
+                        float* out, hipStream_t s) {
+    const uint64_t grid = (nq + 31) / 32;
+    if (grid > 0x7FFFFFFFull) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((table_mfma_kernel<DT, M, DS>),
+                       dim3((uint32_t)grid, M / kMfmaJ), dim3(64), 0, s, q, nq,
+                       cb, out);
+    return hipGetLastError();
+  }
+};
+
 __global__ __launch_bounds__(256) void bf16_base_kernel(
     const float* __restrict__ base, uint64_t total,
     uint16_t* __restrict__ out) {
@@ -324,6 +431,13 @@ hipError_t launch_tables(const DeviceIndex& ix, const void* queries,
                              (const unsigned char*)queries, nq, ix.cb, out, s);
 }
 
+hipError_t launch_tables_mfma(const DeviceIndex& ix, const void* queries,
+                              uint64_t nq, float* out, hipStream_t s) {
+  return dispatch<RunTablesMfma>(ix.dtype, ix.m, ix.d / ix.m,
+                                 (const unsigned char*)queries, nq, ix.cb, out,
+                                 s);
+}
+
 hipError_t launch_search(const DeviceIndex& ix, const SearchLaunch& l,
                          hipStream_t s) {
   const size_t lds = search_lds_bytes(ix.m, l.L, l.iter_cap, l.table);
@@ -364,6 +478,7 @@ hipError_t launch_search(const DeviceIndex& ix, const SearchLaunch& l,
   a.abort_fired = l.abort_fired;
   a.base16 = l.rerank_bf16 ? ix.base16 : nullptr;
   a.norm16 = l.rerank_bf16 ? ix.norm16 : nullptr;
+  a.tables = l.tables;
   a.seen = l.seen;
   a.seen_log = l.seen_log;
   a.seen_words = l.seen_words;

@@ -46,6 +46,8 @@ struct SearchLaunch {
   uint32_t* out_phases;  // [nq][7] per-phase cycles (timed variant) or null
   uint32_t* bloom;       // null (exact filter) or [grid][BANG_BLOOM_Z]
   uint32_t* bloom_epoch; // [grid] query epoch of each wave's filter
+  const float* tables;   // null, or [nq][m][256] FP32 tables to search by
+                         // (instead of building them)
   uint32_t* seen;        // null, or [grid][seen_words] seen bitmaps (zero
                          // between queries; BANG_FILTER_SEEN)
   uint32_t* seen_log;    // [grid][seen_log_entries()] ids set per query
@@ -95,6 +97,10 @@ hipError_t search_occupancy(const DeviceIndex& ix, int table, int filter,
 
 hipError_t launch_tables(const DeviceIndex& ix, const void* queries,
                          uint64_t nq, float* out, hipStream_t s);
+// The same tables by BF16 MFMA with FP32 accumulation (bang.h
+// bang_build_pq_tables_bf16).
+hipError_t launch_tables_mfma(const DeviceIndex& ix, const void* queries,
+                              uint64_t nq, float* out, hipStream_t s);
 hipError_t launch_search(const DeviceIndex& ix, const SearchLaunch& a,
                          hipStream_t s);
 // Random-row read probe over the index's adjacency (bang_index_probe);

@@ -307,25 +307,48 @@ __device__ __forceinline__ void table_entries(
   }
 }
 
-// The query's table in LDS, in the storage form TT (one wave, 64 lanes).
-// lo (U8 only): m floats of LDS for the per-subspace offsets.  Out of line:
-// it runs once per query, and its registers are then not allocated together
-// with the search loop's (measured 1-3% faster at L=768).
+// The same entries read from a table built beforehand (Tq: [m][256] FP32).
+template <int M, class F>
+__device__ __forceinline__ void table_entries_given(const float* __restrict__ Tq,
+                                                    int lane, F&& f) {
+  constexpr int R = 256 / kWave;
+#pragma unroll 4
+  for (int j = 0; j < M; ++j) {
+    float e[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) e[r] = Tq[j * 256 + lane + kWave * r];
+    f(j, e);
+  }
+}
+
+// The query's table in LDS, in the storage form TT (one wave, 64 lanes),
+// built from the codebooks or, when Tq is not null, taken from the FP32
+// table there.  lo (U8 only): m floats of LDS for the per-subspace offsets.
+// Out of line: it runs once per query, and its registers are then not
+// allocated together with the search loop's (measured 1-3% faster at
+// L=768).
 template <int DT, int M, int DS, int TT>
 __device__ __attribute__((noinline)) void build_table_q(QueryLanes<DT, M * DS> Q,
                                               const float* __restrict__ cb,
+                                              const float* __restrict__ Tq,
                                               void* Tv, float* lo, int lane) {
   constexpr int R = 256 / kWave;
+  auto entries = [&](auto&& f) {
+    if (Tq)
+      table_entries_given<M>(Tq, lane, f);
+    else
+      table_entries<DT, M, DS>(Q, cb, lane, f);
+  };
   if constexpr (TT == kTabF32) {
     float* T = reinterpret_cast<float*>(Tv);
-    table_entries<DT, M, DS>(Q, cb, lane, [&](int j, const float (&e)[R]) {
+    entries([&](int j, const float (&e)[R]) {
 #pragma unroll
       for (int r = 0; r < R; ++r) T[j * 256 + lane + kWave * r] = e[r];
     });
   } else {
     // pass 1: the statistics the storage needs
     float mx = 0.0f;  // F16: largest entry; U8: widest subspace range
-    table_entries<DT, M, DS>(Q, cb, lane, [&](int j, const float (&e)[R]) {
+    entries([&](int j, const float (&e)[R]) {
       float vmin = __uint_as_float(0x7F800000u), vmax = 0.0f;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
@@ -353,7 +376,7 @@ __device__ __attribute__((noinline)) void build_table_q(QueryLanes<DT, M * DS> Q
     }
     // pass 2: the entries again (bit-identical), stored in the reduced form
     typename Tab<TT>::E* T = reinterpret_cast<typename Tab<TT>::E*>(Tv);
-    table_entries<DT, M, DS>(Q, cb, lane, [&](int j, const float (&e)[R]) {
+    entries([&](int j, const float (&e)[R]) {
       const float lj = (TT == kTabU8) ? lo[j] : 0.0f;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
@@ -986,6 +1009,9 @@ struct SearchArgs {
   uint32_t* seen_log;
   uint32_t seen_words;
   uint32_t seen_cap;  // ids a query may log, <= kSeenLog
+  // null, or [nq][m][256] FP32 tables built beforehand (e.g. by BF16 MFMA):
+  // each query's table is taken from here instead of being built
+  const float* tables;
 };
 
 namespace {
@@ -1413,7 +1439,9 @@ void search_kernel(SearchArgs a) {
       for (int i = 0; i < M / 16; ++i)
         scode[i] = reinterpret_cast<const uint4*>(a.codes + (size_t)s * M)[i];
       load_row<M, true, HOST>(a, s, lane, nb, code);  // in flight meanwhile
-      build_table_q<DT, M, DS, TT>(Q, a.cb, T, lo, lane);
+      build_table_q<DT, M, DS, TT>(
+          Q, a.cb, a.tables ? a.tables + (size_t)qi * M * 256 : nullptr, T,
+          lo, lane);
     } else {
       load_row<M, false, HOST>(a, s, lane, nb, code);
     }

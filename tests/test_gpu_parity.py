@@ -1334,3 +1334,87 @@ def test_sift1m_seen_filter_sampled_bit_exact():
         assert np.array_equal(u32(ids)[sample], ref["ids"]), L
         assert np.array_equal(f32bits(dist.cpu().numpy()[sample]),
                               f32bits(ref["dists"])), L
+
+
+# --------------------------------------------------------------------------
+# tables built beforehand: the BF16-MFMA build and bang_search_opts.tables
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("name", list(SMALL))
+def test_bf16_mfma_tables_within_the_bound(small_indexes, name):
+    """Every entry of the BF16-MFMA table lies within the oracle's error
+    bound of the exact (FP64) table, for each data type and d/m = 2, 4, 8;
+    rows past a multiple of 32 queries are written too."""
+    ix, q, gi = small_indexes[name]
+    T = gi.build_pq_tables(to_dev(q), bf16=True)
+    torch.cuda.synchronize()
+    T = T.cpu().numpy().astype(np.float64)
+    T64, E = oracle.bf16_table_bound(q, ix.codebooks)
+    err = np.abs(T - T64)
+    assert (err <= E).all(), (name, float((err / E).max()))
+    # the rounding is visible (the build is not the FP32 one) unless every
+    # input is exactly representable
+    T32 = oracle.pq_tables(q, ix.codebooks).astype(np.float64)
+    assert not np.array_equal(T, T32)
+
+
+@pytest.mark.parametrize("name", ["u8-d128-m32", "f32-d32-m16",
+                                  "i8-d96-m48"])
+@pytest.mark.parametrize("k,L,table", [(10, 64, "f32"), (10, 256, "f16"),
+                                       (5, 100, "u8"), (10, 16, "f32")])
+def test_search_by_given_tables_bit_exact(small_indexes, name, k, L, table):
+    """A search ranking by tables given beforehand (the oracle's canonical
+    FP32 tables, moved to the device) equals the oracle's search, which
+    builds the same tables itself: ids, distances and expanded nodes."""
+    ix, q, gi = small_indexes[name]
+    T = to_dev(oracle.pq_tables(q, ix.codebooks))
+    cap = oracle.iter_cap_for(L)
+    ids, d, cand, cnt = gi.search(to_dev(q), k, L, want_cand=cap,
+                                  want_counters=True, table=table, tables=T)
+    torch.cuda.synchronize()
+    ref = oracle.search(ix, q, k, L, want_cand=True, table=table)
+    assert np.array_equal(u32(cnt)[:, 0], ref["iters"])
+    assert np.array_equal(u32(cand), ref["cand"])
+    assert np.array_equal(u32(ids), ref["ids"])
+    assert np.array_equal(f32bits(d.cpu().numpy()), f32bits(ref["dists"]))
+
+
+@pytest.mark.parametrize("table", ["f32", "f16", "u8"])
+def test_search_by_bf16_mfma_tables_returns_exact_distances(small_indexes,
+                                                            table):
+    """Searching by the BF16-MFMA tables: the answer is re-ranked exactly,
+    so each returned distance is the canonical FP32 distance of its id (the
+    oracle's re-rank of the returned ids), rows are sorted and distinct."""
+    ix, q, gi = small_indexes["u8-d128-m32"]
+    qt = to_dev(q)
+    T = gi.build_pq_tables(qt, bf16=True)
+    ids, d = gi.search(qt, 10, 128, table=table, tables=T)
+    torch.cuda.synchronize()
+    ids, d = u32(ids), d.cpu().numpy()
+    rid, rd = oracle.rerank(ix, q, ids, 10)
+    assert np.array_equal(rid, ids)
+    assert np.array_equal(f32bits(rd), f32bits(d))
+    assert all(len(set(r)) == len(r) for r in ids)
+
+
+def test_search_by_tables_rejected_for_exact_distances(small_indexes):
+    ix, q, gi = small_indexes["u8-d64-m16"]
+    bang = bang_mod()
+    T = gi.build_pq_tables(to_dev(q))
+    with pytest.raises(bang.BangError):
+        gi.search(to_dev(q), 10, 32, table="exact", tables=T)
+
+
+@pytest.mark.parametrize("wname,nq", [("sift1m", 96), ("deep1m", 64)])
+def test_bf16_mfma_tables_within_the_bound_1m(wname, nq):
+    """The benchmark's indexes (d/m = 4 on the 1M uint8 index, d/m = 2 on
+    the d=96 float index): a seeded sample of queries, every entry within
+    the bound."""
+    w, ix, d = load_workload(wname)
+    gi = bang_mod().Index(ix.base, ix.adj, ix.medoid, ix.codebooks, ix.codes)
+    sel = np.sort(np.random.default_rng(5).choice(len(d["queries"]), nq,
+                                                  replace=False))
+    q = d["queries"][sel]
+    T = gi.build_pq_tables(to_dev(q), bf16=True)
+    torch.cuda.synchronize()
+    T64, E = oracle.bf16_table_bound(q, ix.codebooks)
+    assert (np.abs(T.cpu().numpy().astype(np.float64) - T64) <= E).all()

@@ -1018,3 +1018,83 @@ def test_bf16_rerank_with_k_candidates_or_fewer_rechecks_all():
     assert rc[0] == 3
     assert np.array_equal(ids, want_ids)
     assert np.array_equal(dists.view(np.uint32), want_d.view(np.uint32))
+
+
+# --------------------------------------------------------------------------
+# the precision form's BF16-MFMA table: FP64 terms and the error bound
+# --------------------------------------------------------------------------
+def test_bf16_round_array_hand_worked_and_equal_to_the_scalar_rounding():
+    """Hand-worked bfloat16 roundings (8-bit significand, ties to even),
+    and agreement with the oracle's scalar rounding on random floats and on
+    exact midpoints."""
+    x = np.array([1.0, 1 + 2 ** -8, 1 + 3 * 2 ** -8, 1 + 2 ** -8 + 2 ** -20,
+                  255.0, 257.0, -3.0, 0.0])
+    want = np.array([1.0, 1.0, 1 + 2 ** -6, 1 + 2 ** -7, 255.0, 256.0, -3.0,
+                     0.0])
+    assert np.array_equal(oracle.bf16_round_array(x), want)
+    rng = np.random.default_rng(11)
+    r = (rng.standard_normal(300) * 10.0 ** rng.integers(-3, 4, 300))
+    r = r.astype(np.float32).astype(np.float64)
+    mids = (1.0 + (2 * rng.integers(0, 128, 50) + 1) * 2.0 ** -8) * \
+        2.0 ** rng.integers(-5, 6, 50)
+    for v in np.concatenate([r, mids, -mids]):
+        assert oracle.bf16_round_array(np.array([v]))[0] == \
+            oracle.bf16_round(v), v
+
+
+def test_pq_table_terms_closed_forms():
+    """T is the table of the FP32 oracle up to FP32 rounding; with inputs
+    that bfloat16 holds exactly (integers up to 256) the rounded inner
+    product is exact, so T_b equals T."""
+    rng = np.random.default_rng(12)
+    q = rng.integers(0, 256, (5, 16)).astype(np.float32)
+    cb = rng.integers(-256, 257, (4, 256, 4)).astype(np.float32)
+    T, S_qc, S_qq, S_cc, Tb = oracle.pq_table_terms(q, cb)
+    assert np.array_equal(Tb, T)
+    T32 = oracle.pq_tables(q, cb).astype(np.float64)
+    assert np.allclose(T32, T, rtol=0, atol=1e-6 * T.max())
+    assert np.allclose(S_qq[:, :, 0], (q.reshape(5, 4, 4) ** 2).sum(-1))
+    assert (S_qc <= np.sqrt(S_qq * S_cc) * (1 + 1e-12)).all()
+
+
+@pytest.mark.parametrize("ds", [2, 4, 8])
+def test_bf16_table_bound_contains_the_rounded_and_fp32_forms(ds):
+    """The bound contains the error of the table with bf16-rounded inner
+    products (exact arithmetic otherwise) and of FP32 evaluations of the
+    formula in two summation orders, on float data of several magnitudes
+    and on integer data; and it is not vacuous: on coordinates that round
+    by nearly the most, the rounded table's error reaches a quarter of it."""
+    rng = np.random.default_rng(13 + ds)
+    m = 8
+    for scale in (1e-2, 1.0, 300.0):
+        q = (rng.standard_normal((6, m * ds)) * scale).astype(np.float32)
+        cb = (rng.standard_normal((m, 256, ds)) * scale).astype(np.float32)
+        T, E = oracle.bf16_table_bound(q, cb)
+        _, _, S_qq, S_cc, Tb = oracle.pq_table_terms(q, cb)
+        assert (np.abs(Tb - T) <= E).all()
+        # FP32 evaluations: norms in order, inner product in order and in
+        # reverse, then (|q|^2 + |c|^2) - 2X
+        qb = oracle.bf16_round_array(q).astype(np.float32)
+        cbb = oracle.bf16_round_array(cb).astype(np.float32)
+        qs = q.reshape(6, m, 1, ds)
+        qbs = qb.reshape(6, m, 1, ds)
+        for order in (range(ds), reversed(range(ds))):
+            X = np.zeros((6, m, 256), np.float32)
+            for t in order:
+                X = X + qbs[..., t] * cbb[None, :, :, t]
+            nq_ = np.zeros((6, m, 1), np.float32)
+            nc_ = np.zeros((1, m, 256), np.float32)
+            for t in range(ds):
+                nq_ = nq_ + qs[..., t] * qs[..., t]
+                nc_ = nc_ + cb[None, :, :, t] * cb[None, :, :, t]
+            T32 = (nq_ + nc_) - np.float32(2.0) * X
+            assert (np.abs(T32.astype(np.float64) - T) <= E).all()
+    # coordinates just below a bfloat16 midpoint, all of one sign: each
+    # factor rounds down by almost u/2 relative, so the inner product errs
+    # by close to u times S_qc
+    q = np.full((1, m * ds), 1 + 2 ** -8 - 2 ** -20, np.float32)
+    cb = np.full((m, 256, ds), 1 + 2 ** -8 - 2 ** -20, np.float32)
+    T, E = oracle.bf16_table_bound(q, cb)
+    _, _, _, _, Tb = oracle.pq_table_terms(q, cb)
+    assert (np.abs(Tb - T) <= E).all()
+    assert (np.abs(Tb - T) >= 0.25 * E).all()
