@@ -174,7 +174,8 @@ def cpu_baseline(idx_np, queries, k, L, budget_s=15.0, budget1_s=8.0):
 # offered queries/s: 10^4 to 10^6 in half decades
 SERVE_RATES = (1e4, 10 ** 4.5, 1e5, 10 ** 5.5, 1e6)
 SERVE_P99_TARGET_MS = 50.0
-SERVE_CANDIDATES = ((1024, 2), (4096, 2), (4096, 4), (16384, 2))
+SERVE_CANDIDATES = ((1024, 2, False), (4096, 2, False), (4096, 4, False),
+                    (16384, 2, False), (4096, 2, True), (16384, 2, True))
 
 
 def serving_section(gi, d, w, gt):
@@ -189,22 +190,36 @@ def serving_section(gi, d, w, gt):
     max_k, max_L = 100, 128
     # calibrate near the highest offered rate, where the candidates differ
     calib = synth.serving_requests(w, SERVE_RATES[-1], 0.2, salt=1)
-    (mb, sl), trials = serving.autotune(gi, qnp, calib, SERVE_CANDIDATES,
-                                        max_k, max_L, SERVE_P99_TARGET_MS)
+    (mb, sl, gr), trials = serving.autotune(gi, qnp, calib, SERVE_CANDIDATES,
+                                            max_k, max_L, SERVE_P99_TARGET_MS)
     rates = []
     for i, rate in enumerate(SERVE_RATES):
         req = synth.serving_requests(w, rate, min(1.0, 2e5 / rate),
                                      salt=10 + i)
-        s, ids, _ = serving.run_load(gi, qnp, req, mb, sl, max_k, max_L)
+        s, ids, _ = serving.run_load(gi, qnp, req, mb, sl, max_k, max_L,
+                                     graphs=gr)
         s["recall10"] = round(recall_at_k(ids[:, :10], gt[req["rows"]], 10), 4)
         rates.append(s)
+    # the same streams at the lowest and highest rate, with and without the
+    # slots replaying captured HIP graphs
+    graphs = []
+    for i, rate in ((0, SERVE_RATES[0]), (len(SERVE_RATES) - 1,
+                                          SERVE_RATES[-1])):
+        req = synth.serving_requests(w, rate, min(1.0, 2e5 / rate),
+                                     salt=10 + i)
+        for g in (False, True):
+            s, _, _ = serving.run_load(gi, qnp, req, mb, sl, max_k, max_L,
+                                       graphs=g)
+            graphs.append(s)
     return {"table": "f32",
             "requests": "sizes log-uniform 1-256 queries, k in {10,100}, "
                         "L in {32,64,128} raised to k, Poisson arrivals",
-            "autotune": {"chosen": {"max_batch": mb, "slots": sl},
+            "autotune": {"chosen": {"max_batch": mb, "slots": sl,
+                                    "graphs": gr},
                          "p99_target_ms": SERVE_P99_TARGET_MS,
                          "trials": trials},
-            "rates": rates}
+            "rates": rates,
+            "graphs_vs_direct": graphs}
 
 
 DEEP_WORKLOAD = "deep1m"

@@ -380,7 +380,15 @@ typedef struct {
                                admission by footprint, fewer slots when
                                `slots` of them do not fit (ENOMEM if one
                                does not) */
+  uint32_t flags;           /* 0, or BANG_SERVER_GRAPHS */
 } bang_server_opts;
+
+/* Each slot replays its batches from HIP graphs: the copies of the queries
+ * and their (k, L) in, the search and the copies of the results out are
+ * captured once per (batch size rounded up to a power of two, largest k,
+ * largest L) and replayed; the rows past the batch are searched with
+ * L = k = 1 and dropped.  Results are the same as without the flag. */
+#define BANG_SERVER_GRAPHS 1u
 
 /* Allocate the slots (device workspace and buffers, pinned host buffers)
  * and start the scheduler thread.  The index must outlive the server.

@@ -72,7 +72,8 @@ class ServerOpts(ctypes.Structure):
     _fields_ = [("max_batch", ctypes.c_uint32), ("slots", ctypes.c_uint32),
                 ("max_k", ctypes.c_uint32), ("max_L", ctypes.c_uint32),
                 ("table", ctypes.c_uint32),
-                ("hbm_budget_bytes", ctypes.c_uint64)]
+                ("hbm_budget_bytes", ctypes.c_uint64),
+                ("flags", ctypes.c_uint32)]
 
 
 _lib = None
@@ -408,15 +409,17 @@ class Server:
     submit(q, k, L) queues a request of host queries (numpy [nq][d]) and
     returns a ticket; wait(ticket) returns (ids uint32 [nq][k], dists
     float32 [nq][k]).  replay() drives an open-loop arrival schedule from
-    native code and returns results and per-request latencies."""
+    native code and returns results and per-request latencies.  graphs:
+    each slot replays its batches from captured HIP graphs
+    (BANG_SERVER_GRAPHS)."""
 
     def __init__(self, index: Index, max_batch: int = 4096, slots: int = 2,
                  max_k: int = 100, max_L: int = 256, table: str = "f32",
-                 hbm_budget_bytes: int = 0):
+                 hbm_budget_bytes: int = 0, graphs: bool = False):
         self._h = None
         self.index = index  # the index must outlive the server
         o = ServerOpts(max_batch, slots, max_k, max_L, TABLES[table],
-                       hbm_budget_bytes)
+                       hbm_budget_bytes, 1 if graphs else 0)
         h = ctypes.c_void_p()
         _check(lib().bang_server_create(index._h, ctypes.byref(o),
                                         ctypes.byref(h)))

@@ -58,6 +58,9 @@ struct Slot {
   std::vector<std::shared_ptr<Request>> batch;
   uint32_t kb = 0;  // row stride of this batch's results
   bool busy = false;
+  // BANG_SERVER_GRAPHS: the batch's copies and search captured once per
+  // (bucket of queries, k, L) and replayed; key bucket | k << 21 | L << 42
+  std::unordered_map<uint64_t, hipGraphExec_t> graphs;
 };
 
 }  // namespace
@@ -83,6 +86,8 @@ namespace {
 
 void free_slot(Slot& s) {
   if (s.stream) (void)hipStreamSynchronize(s.stream);
+  for (auto& g : s.graphs) (void)hipGraphExecDestroy(g.second);
+  s.graphs.clear();
   bang::workspace_free(&s.ws);
   (void)hipFree(s.d_q);
   (void)hipFree(s.d_L);
@@ -127,6 +132,8 @@ int init_slot(bang_server* sv, Slot& s, size_t ws_bytes) {
                          hipHostMallocDefault)))
     return fail(BANG_ENOMEM, std::string("server pinned buffers: ") +
                                  hipGetErrorString(e));
+  // graph buckets search padding rows too: defined (zero) queries
+  std::memset(s.h_q, 0, B * sv->row);
   return BANG_OK;
 }
 
@@ -140,6 +147,82 @@ void fail_batch(bang_server* sv, Slot& s, int code, const std::string& why) {
   s.batch.clear();
   s.busy = false;
   sv->done_cv.notify_all();
+}
+
+// Enqueue a staged batch's copies in, search and copies back, n queries
+// with result stride kb and worklists up to Lb, on the slot's stream.
+int enqueue(bang_server* sv, Slot& s, uint32_t n, uint32_t kb, uint32_t Lb) {
+  hipError_t e;
+  if ((e = hipMemcpyAsync(s.d_q, s.h_q, (size_t)n * sv->row,
+                          hipMemcpyHostToDevice, s.stream)) ||
+      (e = hipMemcpyAsync(s.d_L, s.h_L, (size_t)n * 4, hipMemcpyHostToDevice,
+                          s.stream)) ||
+      (e = hipMemcpyAsync(s.d_k, s.h_k, (size_t)n * 4, hipMemcpyHostToDevice,
+                          s.stream)))
+    return hip_fail(e, "server copy in");
+  bang_search_opts so{};
+  so.table = sv->o.table;
+  so.query_L = s.d_L;
+  so.query_k = s.d_k;
+  int rc = bang::search_with(sv->ix, &s.ws, false, s.d_q, n, kb, Lb, s.d_ids,
+                             s.d_d, &so, s.stream);
+  if (rc) return rc;
+  if ((e = hipMemcpyAsync(s.h_ids, s.d_ids, (size_t)n * kb * 4,
+                          hipMemcpyDeviceToHost, s.stream)) ||
+      (e = hipMemcpyAsync(s.h_d, s.d_d, (size_t)n * kb * 4,
+                          hipMemcpyDeviceToHost, s.stream)))
+    return hip_fail(e, "server copy out");
+  return BANG_OK;
+}
+
+// The batch as one graph launch: n queries rounded up to a bucket (a power
+// of two, at most max_batch), the rows past n searched with L = k = 1 (a
+// single expansion; their results are not read).  Each (bucket, kb, Lb)
+// is captured the first time it occurs and replayed after that; the search
+// leaves its counters at zero, so a replay needs no reset.
+void launch_graph(bang_server* sv, Slot& s, uint32_t n, uint32_t kb,
+                  uint32_t Lb) {
+  uint32_t nb = 1;
+  while (nb < n) nb <<= 1;
+  nb = std::min(nb, sv->o.max_batch);
+  for (uint32_t i = n; i < nb; ++i) s.h_L[i] = s.h_k[i] = 1;
+  const uint64_t key = (uint64_t)nb | ((uint64_t)kb << 21) |
+                       ((uint64_t)Lb << 42);
+  hipError_t e;
+  auto it = s.graphs.find(key);
+  if (it == s.graphs.end()) {
+    hipGraph_t g = nullptr;
+    hipGraphExec_t x = nullptr;
+    e = hipStreamBeginCapture(s.stream, hipStreamCaptureModeRelaxed);
+    if (e != hipSuccess) {
+      fail_batch(sv, s, BANG_EDEVICE, hipGetErrorString(e));
+      return;
+    }
+    const int rc = enqueue(sv, s, nb, kb, Lb);
+    const std::string why = rc ? bang::last_error() : std::string();
+    e = hipStreamEndCapture(s.stream, &g);
+    if (rc || e != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      fail_batch(sv, s, rc ? rc : BANG_EDEVICE,
+                 rc ? why : std::string(hipGetErrorString(e)));
+      return;
+    }
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      fail_batch(sv, s, BANG_EDEVICE, hipGetErrorString(e));
+      return;
+    }
+    it = s.graphs.emplace(key, x).first;
+  }
+  if ((e = hipGraphLaunch(it->second, s.stream)) ||
+      (e = hipEventRecord(s.done, s.stream))) {
+    fail_batch(sv, s, BANG_EDEVICE, hipGetErrorString(e));
+    return;
+  }
+  std::lock_guard<std::mutex> g(sv->mu);
+  sv->launches++;
+  sv->queries += n;
 }
 
 // Stage a batch into the slot and enqueue copies, search and copies back.
@@ -157,6 +240,10 @@ void launch(bang_server* sv, Slot& s) {
     Lb = std::max(Lb, r->L);
   }
   s.kb = kb;
+  if (sv->o.flags & BANG_SERVER_GRAPHS) {
+    launch_graph(sv, s, n, kb, Lb);
+    return;
+  }
   hipError_t e;
   if ((e = hipMemcpyAsync(s.d_q, s.h_q, (size_t)n * sv->row,
                           hipMemcpyHostToDevice, s.stream)) ||
@@ -352,6 +439,8 @@ int bang_server_create(bang_index* ix, const bang_server_opts* o,
         o->max_k > o->max_L)
       return fail(BANG_EINVAL, "need 1 <= max_k <= max_L <= 1024");
     if (o->table > BANG_TABLE_EXACT) return fail(BANG_EINVAL, "unknown table form");
+    if (o->flags & ~BANG_SERVER_GRAPHS)
+      return fail(BANG_EINVAL, "unknown server flags");
     hipError_t e = hipSetDevice(ix->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
     const uint32_t cap = std::max(4 * o->max_L, o->max_L + 64);

@@ -2,10 +2,11 @@
 
 `run_load` replays an open-loop request stream through a Server and sums
 it up (offered and sustained query rates, p50/p99 request latency);
-`autotune` picks the server's batch size and slot count for a load: it
-replays the same calibration stream through each candidate configuration
-and keeps the one with the highest sustained rate whose p99 latency stays
-within the target (else the one with the lowest p99).
+`autotune` picks the server's batch size, slot count and whether slots
+replay captured HIP graphs, for a load: it replays the same calibration
+stream through each candidate configuration and keeps the one with the
+highest sustained rate whose p99 latency stays within the target (else the
+one with the lowest p99).
 """
 from __future__ import annotations
 
@@ -15,11 +16,11 @@ from . import Server
 
 
 def run_load(index, queries, req, max_batch: int, slots: int, max_k: int,
-             max_L: int, table: str = "f32"):
+             max_L: int, table: str = "f32", graphs: bool = False):
     """Replay `req` (synth.serving_requests output) through a new Server;
     returns (summary dict, ids, dists)."""
     sv = Server(index, max_batch=max_batch, slots=slots, max_k=max_k,
-                max_L=max_L, table=table)
+                max_L=max_L, table=table, graphs=graphs)
     try:
         ids, d, lat = sv.replay(queries[req["rows"]], req["nq"], req["k"],
                                 req["L"], req["arrival_s"],
@@ -32,7 +33,8 @@ def run_load(index, queries, req, max_batch: int, slots: int, max_k: int,
     nq = int(req["nq"].sum())
     span = float(done.max() - arr.min()) if len(arr) else 0.0
     offered = nq / float(max(arr.max(), 1e-9)) if len(arr) > 1 else 0.0
-    out = {"max_batch": max_batch, "slots": slots, "requests": len(arr),
+    out = {"max_batch": max_batch, "slots": slots, "graphs": bool(graphs),
+           "requests": len(arr),
            "queries": nq, "offered_qps": round(offered, 1),
            "sustained_qps": round(nq / span, 1) if span > 0 else 0.0,
            "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
@@ -45,14 +47,18 @@ def run_load(index, queries, req, max_batch: int, slots: int, max_k: int,
 
 def autotune(index, queries, req, candidates, max_k: int, max_L: int,
              p99_target_ms: float, table: str = "f32"):
-    """Try each (max_batch, slots) on the calibration stream `req`; return
-    (best (max_batch, slots), list of per-candidate summaries)."""
+    """Try each (max_batch, slots[, graphs]) on the calibration stream
+    `req`; return (best (max_batch, slots, graphs), list of per-candidate
+    summaries)."""
     trials = []
-    for mb, sl in candidates:
-        s, _, _ = run_load(index, queries, req, mb, sl, max_k, max_L, table)
+    for c in candidates:
+        mb, sl = c[0], c[1]
+        gr = bool(c[2]) if len(c) > 2 else False
+        s, _, _ = run_load(index, queries, req, mb, sl, max_k, max_L, table,
+                           graphs=gr)
         trials.append(s)
     best = choose(trials, p99_target_ms)
-    return (best["max_batch"], best["slots"]), trials
+    return (best["max_batch"], best["slots"], best["graphs"]), trials
 
 
 def choose(trials, p99_target_ms: float) -> dict:

@@ -463,10 +463,13 @@ def test_mixed_batch_equals_each_query_alone(small_indexes, name, table):
         assert np.array_equal(a_ids, ref["ids"]), (k, L)
 
 
-def test_server_replay_results_equal_alone(small_indexes):
+@pytest.mark.parametrize("graphs", [False, True])
+def test_server_replay_results_equal_alone(small_indexes, graphs):
     """Requests with mixed sizes, k and L arrive open-loop (Poisson) and
     overlap on the device in two slots; each result equals a search of its
-    queries alone."""
+    queries alone, also when the slots replay captured HIP graphs (batches
+    rounded up to a power of two, several (k, L) combinations, each graph
+    replayed many times)."""
     ix, q, gi = small_indexes["u8-d128-m32"]
     bang = bang_mod()
     rng = np.random.default_rng(11)
@@ -477,7 +480,8 @@ def test_server_replay_results_equal_alone(small_indexes):
     rows = rng.integers(0, len(q), int(nq.sum()))
     Q = q[rows]
     arr = np.cumsum(rng.exponential(2e-4, nreq))
-    sv = bang.Server(gi, max_batch=24, slots=2, max_k=32, max_L=128)
+    sv = bang.Server(gi, max_batch=24, slots=2, max_k=32, max_L=128,
+                     graphs=graphs)
     ids, d, lat = sv.replay(Q, nq, k, L, arr, kstride=32)
     st = sv.stats()
     sv.close()
