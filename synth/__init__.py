@@ -80,10 +80,6 @@ WORKLOADS = {
                        0.3, 10_000, 64, 100, 1.2, 48, 10, 100_000, 10,
                        (16, 32, 64, 96, 112, 128, 192, 256, 384, 512),
                        unit=True),
-    # the float recipe at its full size (10M points, d=96, m=48)
-    "deep10m": Workload("deep10m", 2, 10_000_000, 96, "f32", 4096, 0.0, 0.0,
-                        0.3, 10_000, 64, 100, 1.2, 48, 10, 100_000, 10,
-                        (32, 64, 96, 128, 160, 192, 256, 384), unit=True),
 }
 
 
