@@ -675,10 +675,11 @@ __device__ __forceinline__ float coop_dist(const void* __restrict__ base,
 // bit ignored, is below x's (1 <= len <= 1024, last = A[len-1]), and in ge
 // the entry A[P] (kInf when P = len).  (a >> 1) < (x >> 1) is tested as
 // a < (x & ~1).  Radix-4 lifting: three independent probes per level, half
-// the dependent LDS reads of a binary search.  The probe at index P is the
-// first failing one of the last level that fails, so ge comes for free;
-// probes past A[len-2] are clamped to A[len-1] = last, which is known not
-// to be below x (a clamp instead of a branch).
+// the dependent LDS reads of a binary search, down to a last level that
+// reads the four entries P can be (pos .. pos+3): the first of them not
+// below x is A[P], so ge comes from that level alone.  Probes past
+// A[len-2] are clamped to A[len-1] = last, which is known not to be below
+// x (a clamp instead of a branch).
 __device__ __forceinline__ uint32_t rank_in(const uint64_t* A, uint32_t len,
                                             uint64_t last, uint64_t x,
                                             uint64_t& ge) {
@@ -689,24 +690,24 @@ __device__ __forceinline__ uint32_t rank_in(const uint64_t* A, uint32_t len,
   }
   const uint32_t lim = len - 1;  // the answer is at most lim
   uint32_t pos = 0;
-  uint64_t g = last;
-  for (uint32_t s = 256; s > 0; s >>= 2) {
+  for (uint32_t s = 256; s > 1; s >>= 2) {
     if (s > lim) continue;
     const uint32_t i1 = pos + s - 1, i2 = i1 + s, i3 = i2 + s;
     const uint64_t v1 = A[min(i1, lim)];
     const uint64_t v2 = A[min(i2, lim)];
     const uint64_t v3 = A[min(i3, lim)];
-    const bool p1 = v1 < xs, p2 = v2 < xs, p3 = v3 < xs;
-    if (!p1)
-      g = v1;
-    else if (!p2)
-      g = v2;
-    else if (!p3)
-      g = v3;
-    pos += s * ((uint32_t)p1 + (uint32_t)p2 + (uint32_t)p3);
+    pos += s * ((uint32_t)(v1 < xs) + (uint32_t)(v2 < xs) +
+                (uint32_t)(v3 < xs));
   }
-  ge = g;
-  return pos;
+  // P is in pos .. pos+3 (and at most lim, where A[lim] = last is not
+  // below x)
+  const uint64_t v0 = A[min(pos, lim)];
+  const uint64_t v1 = A[min(pos + 1, lim)];
+  const uint64_t v2 = A[min(pos + 2, lim)];
+  const uint64_t v3 = A[min(pos + 3, lim)];
+  const bool p0 = v0 < xs, p1 = v1 < xs, p2 = v2 < xs;
+  ge = !p0 ? v0 : (!p1 ? v1 : (!p2 ? v2 : v3));
+  return pos + (uint32_t)p0 + (uint32_t)p1 + (uint32_t)p2;
 }
 
 // Ascending bitonic sort of S[0..P) in LDS by one wave (P a power of two).
