@@ -531,30 +531,15 @@ def scale_host(a) -> int:
     # one persistent launch of the 100M configuration's mixed batch: 100,000
     # queries, k in {1, 10, 100}, L = max(k, round(exp(U[ln 16, ln 256])))
     kq, Lq = synth.mixed_batch(SCALE_MIXED_NQ, salt=3)
-    qk = torch.from_numpy(kq.astype(np.int32)).cuda()
-    qL = torch.from_numpy(Lq.astype(np.int32)).cuda()
-    kmax, Lmax = int(kq.max()), int(Lq.max())
-    ids, dist, cnt = gi.search(qall, kmax, Lmax, query_L=qL, query_k=qk,
-                               want_counters=True)
-    torch.cuda.synchronize()
-    iters = cnt.cpu().numpy()[:, 0].astype(np.int64)
-    ev = [(torch.cuda.Event(enable_timing=True),
-           torch.cuda.Event(enable_timing=True)) for _ in range(a.steps)]
-    for e0, e1 in ev:
-        e0.record(stream)
-        gi.search(qall, kmax, Lmax, query_L=qL, query_k=qk, out=(ids, dist))
-        e1.record(stream)
-    torch.cuda.synchronize()
-    ms = float(np.mean([e0.elapsed_time(e1) for e0, e1 in ev]))
-    link = iters.sum() * 4 * R / (ms / 1e3) / 1e9
-    mixed = {"queries": SCALE_MIXED_NQ, "k": "uniform over {1, 10, 100}",
-             "L": "max(k, round(exp(U[ln 16, ln 256])))",
-             "mean_L": round(float(Lq.mean()), 1),
-             "qps": round(SCALE_MIXED_NQ / (ms / 1e3), 1),
-             "kernel_ms_mean": round(ms, 3),
-             "mean_iterations": round(float(iters.mean()), 2),
-             "host_link_gbs": round(link, 2),
-             "host_link_frac": round(link / HOST_LINK_PEAK_GBS, 4)}
+    from paper_2401_11324_amd import tuning
+    tiles, tile_trials = tuning.launch_tiles(gi, qall, kq, Lq)
+    log(f"tiles: {tiles}")
+    mixed = mixed_launch(gi, qall, kq, Lq, tiles, a.steps, R)
+    mixed["tiles"] = {"chosen": tiles, "trials": tile_trials}
+    mixed["untuned"] = mixed_launch(gi, qall, kq, Lq, None, a.steps, R)
+    for m_ in (mixed, mixed["untuned"]):
+        m_["host_link_frac"] = round(m_["adjacency_gbs"] /
+                                     HOST_LINK_PEAK_GBS, 4)
     log(f"mixed batch: {mixed}")
     del ids, dist, cnt
     # the serving loop on the same host-resident index (configuration 4's
@@ -583,6 +568,73 @@ def scale_host(a) -> int:
                                 "Poisson arrivals", "rates": serve}}}),
           flush=True)
     return 0
+
+
+def mixed_launch(gi, q, kq, Lq, tiles, steps, R, gt=None):
+    """One persistent launch of a mixed batch (per-query k and L) with
+    the take order and waves per CU of `tiles` (None: the batch's order,
+    full occupancy): QPS, iterations, adjacency bytes per second and,
+    given ground truth for the rows, recall@10 of the queries with k >= 10."""
+    import torch
+    from paper_2401_11324_amd import tuning
+    nq = q.shape[0]
+    qk = torch.from_numpy(kq.astype(np.int32)).cuda()
+    qL = torch.from_numpy(Lq.astype(np.int32)).cuda()
+    kmax, Lmax = int(kq.max()), int(Lq.max())
+    order, w = None, 0
+    if tiles is not None:
+        o = tuning.order_of(tiles["order"], Lq)
+        order = None if o is None else torch.from_numpy(o).cuda()
+        w = tiles["waves_per_cu"]
+    kw = dict(query_L=qL, query_k=qk, order=order, waves_per_cu=w)
+    ids, dist, cnt = gi.search(q, kmax, Lmax, want_counters=True, **kw)
+    torch.cuda.synchronize()
+    iters = cnt.cpu().numpy()[:, 0].astype(np.int64)
+    stream = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True),
+           torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for e0, e1 in ev:
+        e0.record(stream)
+        gi.search(q, kmax, Lmax, out=(ids, dist), **kw)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    ms = float(np.mean([e0.elapsed_time(e1) for e0, e1 in ev]))
+    link = iters.sum() * 4 * R / (ms / 1e3) / 1e9
+    out = {"queries": nq, "k": "uniform over {1, 10, 100}",
+           "L": "max(k, round(exp(U[ln 16, ln 256])))",
+           "mean_L": round(float(Lq.mean()), 1),
+           "qps": round(nq / (ms / 1e3), 1),
+           "kernel_ms_mean": round(ms, 3),
+           "mean_iterations": round(float(iters.mean()), 2),
+           "adjacency_gbs": round(link, 2)}
+    if gt is not None:
+        sel = kq >= 10
+        got = ids.cpu().numpy().view(np.uint32)[sel, :10]
+        out["recall10_of_k_ge_10"] = round(recall_at_k(got, gt[sel], 10), 4)
+    return out
+
+
+def mixed_section(run, nq=100_000):
+    """Configuration 3's query recipe on the 1M index: 100,000 queries
+    (the 10,000 repeated) with k uniform over {1, 10, 100} and
+    L = max(k, round(exp(U[ln 16, ln 256]))) in one persistent launch,
+    with the autotuned take order and waves per CU against the batch's own
+    order at full occupancy."""
+    import synth
+    from paper_2401_11324_amd import tuning
+    torch = run.torch
+    reps = -(-nq // run.q.shape[0])
+    q = run.q.repeat(reps, 1)[:nq].contiguous()
+    gt = np.tile(run.gt, (reps, 1))[:nq]
+    kq, Lq = synth.mixed_batch(nq, salt=3)
+    tiles, trials = tuning.launch_tiles(run.gi, q, kq, Lq)
+    tuned = mixed_launch(run.gi, q, kq, Lq, tiles, run.a.steps, run.w.R, gt)
+    plain = mixed_launch(run.gi, q, kq, Lq, None, run.a.steps, run.w.R, gt)
+    del q
+    torch.cuda.empty_cache()
+    return {"tiles": {"chosen": tiles, "trials": trials}, "tuned": tuned,
+            "untuned": plain,
+            "speedup": round(tuned["qps"] / plain["qps"], 3)}
 
 
 def copy_probe(mib: int) -> int:
@@ -1027,6 +1079,7 @@ def main(argv=None):
         if exact is not None:
             pts.append(("exact", exact["L"], exact))
         out["bloom_filter"] = bloom_section(run, pts)
+        out["mixed_batch"] = mixed_section(run)
         # plus a small worklist, where the once-per-query table build and
         # re-rank weigh most
         out["phase_split"] = phase_section(

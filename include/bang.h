@@ -163,6 +163,16 @@ typedef struct {
                                BANG_TABLE_EXACT.  With the tables of
                                bang_build_pq_tables the results are those of
                                the search without this option. */
+  const uint32_t* order;    /* NULL, or device [nq]: the order in which the
+                               persistent waves take the queries (the t-th
+                               query taken is order[t]; a permutation of
+                               0..nq-1, entries >= nq are skipped).  Results
+                               stay in each query's own row and do not
+                               depend on the order; it sets how the
+                               launch's tail is balanced (e.g. the longest
+                               worklists first in a mixed batch). */
+  uint32_t waves_per_cu;    /* 0, or a cap on the resident waves per CU
+                               (at most what LDS and registers allow) */
 } bang_search_opts;
 
 /* Re-rank forms (float data; integer data is always re-ranked exactly).

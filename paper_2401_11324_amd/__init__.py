@@ -65,7 +65,8 @@ class SearchOpts(ctypes.Structure):
                 ("query_L", ctypes.c_void_p), ("query_k", ctypes.c_void_p),
                 ("filter", ctypes.c_uint32), ("out_phases", ctypes.c_void_p),
                 ("abort", ctypes.c_void_p), ("rerank", ctypes.c_uint32),
-                ("tables", ctypes.c_void_p)]
+                ("tables", ctypes.c_void_p), ("order", ctypes.c_void_p),
+                ("waves_per_cu", ctypes.c_uint32)]
 
 
 class ServerOpts(ctypes.Structure):
@@ -237,8 +238,8 @@ class Index:
                rerank_global: bool = False, query_L=None, query_k=None,
                filter: str = "exact", want_phases: bool = False, out=None,
                abort=None, rerank: str = "exact", stream=None,
-               seen_log_short: bool = False, tables=None,
-               _entry: str = "bang_search"):
+               seen_log_short: bool = False, tables=None, order=None,
+               waves_per_cu: int = 0, _entry: str = "bang_search"):
         """Stages 1-3.  Returns (ids uint32-as-int32 [nq][k], dists
         float32 [nq][k]) and, on request, the expanded nodes [nq][want_cand]
         `table` is the PQ table storage the search ranks by: "f32", the
@@ -258,7 +259,10 @@ class Index:
         the candidates recomputed in FP32).  tables: float32 CUDA tensor
         [nq][m][256] of PQ tables built beforehand (build_pq_tables,
         optionally bf16=True) that the search ranks by instead of building
-        its own.  seen_log_short: with the
+        its own.  order (int32 CUDA tensor [nq], a permutation): the order
+        in which the persistent waves take the queries; waves_per_cu: a
+        cap on resident waves per CU (0: as many as fit); neither changes
+        results.  seen_log_short: with the
         "seen" filter, stop setting bits after 64 logged ids and only test
         from then on (BANG_SEARCH_SEEN_LOG_SHORT; for testing)."""
         import torch
@@ -277,6 +281,11 @@ class Index:
         if abort is not None:
             opts.abort = abort._h.value
         opts.rerank = RERANKS[rerank]
+        if order is not None:
+            if tuple(order.shape) != (nq,):
+                raise ValueError(f"order must have shape ({nq},)")
+            opts.order = _dev_ptr(order, torch.int32, "order").value
+        opts.waves_per_cu = int(waves_per_cu)
         if tables is not None:
             if tuple(tables.shape) != (nq, self.m, 256):
                 raise ValueError(f"tables must have shape ({nq}, {self.m}, 256)")

@@ -304,7 +304,7 @@ int check_queries(const bang_index* ix, const void* queries) {
 // Launch geometry of a search: LDS bytes and resident workgroups.
 int search_geometry(bang_index* ix, uint64_t nq, uint32_t L, uint32_t iter_cap,
                     uint32_t table, int filter, bool phases, size_t* lds,
-                    uint64_t* grid) {
+                    uint64_t* grid, uint32_t waves_per_cu = 0) {
   *lds = bang::search_lds_bytes(ix->dev.m, L, iter_cap, (int)table);
   hipError_t e = hipSetDevice(ix->device);
   if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
@@ -318,6 +318,7 @@ int search_geometry(bang_index* ix, uint64_t nq, uint32_t L, uint32_t iter_cap,
                              &per_cu);
   if (e != hipSuccess) return hip_fail(e, "occupancy query");
   if (per_cu < 1) return fail(BANG_EUNSUPPORTED, "search kernel cannot be resident");
+  if (waves_per_cu) per_cu = std::min<int>(per_cu, (int)waves_per_cu);
   *grid = std::min<uint64_t>((uint64_t)per_cu * ix->num_cus, nq);
   return BANG_OK;
 }
@@ -437,8 +438,11 @@ int search_with(bang_index* ix, Workspace* ws, bool grow, const void* queries,
                 "adjacency and no Bloom filter");
   if (phases && !aligned(phases, 4))
     return fail(BANG_EINVAL, "out_phases not 4-byte aligned");
+  const uint32_t* const order = o ? o->order : nullptr;
+  if (order && !aligned(order, 4))
+    return fail(BANG_EINVAL, "order not 4-byte aligned");
   rc = search_geometry(ix, nq, L, iter_cap, table, fkind, phases != nullptr,
-                       &lds, &grid);
+                       &lds, &grid, o ? o->waves_per_cu : 0u);
   if (rc) return rc;
   size_t need = (size_t)grid * iter_cap * sizeof(uint64_t);
   if (need > ws->cscratch_bytes && ws->clamp_grid) {
@@ -528,6 +532,7 @@ int search_with(bang_index* ix, Workspace* ws, bool grow, const void* queries,
   l.cscratch = ws->cscratch;
   l.qcounter = ws->qcounter;
   l.tables = tables;
+  l.order = order;
   l.bloom = filter == BANG_FILTER_BLOOM ? ws->bloom : nullptr;
   l.bloom_epoch = filter == BANG_FILTER_BLOOM ? ws->bloom_epoch : nullptr;
   if (filter == BANG_FILTER_SEEN) {

@@ -479,6 +479,7 @@ hipError_t launch_search(const DeviceIndex& ix, const SearchLaunch& l,
   a.base16 = l.rerank_bf16 ? ix.base16 : nullptr;
   a.norm16 = l.rerank_bf16 ? ix.norm16 : nullptr;
   a.tables = l.tables;
+  a.order = l.order;
   a.seen = l.seen;
   a.seen_log = l.seen_log;
   a.seen_words = l.seen_words;

@@ -48,6 +48,7 @@ struct SearchLaunch {
   uint32_t* bloom_epoch; // [grid] query epoch of each wave's filter
   const float* tables;   // null, or [nq][m][256] FP32 tables to search by
                          // (instead of building them)
+  const uint32_t* order;  // null, or [nq]: the order the waves take queries
   uint32_t* seen;        // null, or [grid][seen_words] seen bitmaps (zero
                          // between queries; BANG_FILTER_SEEN)
   uint32_t* seen_log;    // [grid][seen_log_entries()] ids set per query

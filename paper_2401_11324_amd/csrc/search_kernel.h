@@ -1013,6 +1013,9 @@ struct SearchArgs {
   // null, or [nq][m][256] FP32 tables built beforehand (e.g. by BF16 MFMA):
   // each query's table is taken from here instead of being built
   const float* tables;
+  // null, or [nq]: the order in which the waves take the queries (query
+  // order[t] is the t-th taken); results stay in each query's own row
+  const uint32_t* order;
 };
 
 namespace {
@@ -1329,7 +1332,12 @@ void search_kernel(SearchArgs a) {
     uint32_t qi = 0;
     if (lane == 0) qi = atomicAdd(a.qcounter, 1u);
     qi = __builtin_amdgcn_readfirstlane(qi);
-    if (qi >= a.nq) {
+    const uint32_t turn = qi;  // the queries are taken in a.order if given
+    if (turn < a.nq && a.order) {
+      qi = __builtin_amdgcn_readfirstlane(a.order[turn]);
+      if (qi >= a.nq) continue;  // not a query of the batch: nothing to do
+    }
+    if (turn >= a.nq) {
       // the last workgroup out returns both counters to zero for the next
       // launch (no reset kernel or memset on the stream)
       if (lane == 0) {

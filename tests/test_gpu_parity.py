@@ -1422,3 +1422,28 @@ def test_bf16_mfma_tables_within_the_bound_1m(wname, nq):
     torch.cuda.synchronize()
     T64, E = oracle.bf16_table_bound(q, ix.codebooks)
     assert (np.abs(T.cpu().numpy().astype(np.float64) - T64) <= E).all()
+
+
+@pytest.mark.parametrize("table", ["f32", "exact"])
+def test_take_order_and_wave_cap_change_no_result(small_indexes, table):
+    """A mixed batch taken in other orders (reversed, random, longest
+    worklist first, with ids past the batch to skip) and with fewer
+    resident waves returns the same rows, bit for bit."""
+    ix, q, gi = small_indexes["u8-d128-m32"]
+    nq = len(q)
+    rng = np.random.default_rng(21)
+    Ls = rng.choice([8, 16, 64, 150], nq).astype(np.int32)
+    ks = np.minimum(rng.choice([1, 5, 10], nq), Ls).astype(np.int32)
+    qt, qL, qk = to_dev(q), to_dev(Ls), to_dev(ks)
+    base = gi.search(qt, 10, 150, table=table, query_L=qL, query_k=qk)
+    torch.cuda.synchronize()
+    orders = [np.arange(nq)[::-1], rng.permutation(nq),
+              np.argsort(-Ls, kind="stable")]
+    for o in orders:
+        for w in (0, 1, 2):
+            got = gi.search(qt, 10, 150, table=table, query_L=qL,
+                            query_k=qk, order=to_dev(o.astype(np.int32)),
+                            waves_per_cu=w)
+            torch.cuda.synchronize()
+            for x, y in zip(base, got):
+                assert np.array_equal(x.cpu().numpy(), y.cpu().numpy()), w
