@@ -1447,3 +1447,37 @@ def test_take_order_and_wave_cap_change_no_result(small_indexes, table):
             torch.cuda.synchronize()
             for x, y in zip(base, got):
                 assert np.array_equal(x.cpu().numpy(), y.cpu().numpy()), w
+
+
+def test_rows_past_4_gib_sampled_bit_exact():
+    """A synthetic 17M-node int8 graph (synth.scale_graph_index: rows of
+    random ids over the whole range): the packed rows in device memory (39
+    GB) and the pinned host adjacency (4.4 GB) both reach past 2^32 bytes,
+    so the search addresses rows with 64-bit offsets; 48 queries equal the
+    oracle (ids, distances, expanded nodes and iteration counts) with both
+    placements."""
+    n = 17_000_000
+    d = synth.scale_graph_index(n, nq=48)
+    assert n * 2304 > 1 << 32 and n * 64 * 4 > 1 << 32
+    ix = oracle.Index(d["base"], d["adj"], d["medoid"], d["codebooks"],
+                      d["codes"])
+    q = d["queries"]
+    k, L = 10, 64
+    cap = oracle.iter_cap_for(L)
+    ref = oracle.search(ix, q, k, L, want_cand=True)
+    # the search reaches rows above both 4 GiB marks
+    expanded = ref["cand"][ref["cand"] != NONE].astype(np.int64)
+    assert (expanded * 2304 >= 1 << 32).any()
+    assert (expanded * 256 >= 1 << 32).any()
+    for host in (False, True):
+        gi = bang_mod().Index(d["base"], d["adj"], d["medoid"],
+                              d["codebooks"], d["codes"], host_adj=host)
+        ids, dist, cand, cnt = gi.search(to_dev(q), k, L, want_cand=cap,
+                                         want_counters=True)
+        torch.cuda.synchronize()
+        assert np.array_equal(u32(cnt)[:, 0], ref["iters"]), host
+        assert np.array_equal(u32(cand), ref["cand"]), host
+        assert np.array_equal(u32(ids), ref["ids"]), host
+        assert np.array_equal(f32bits(dist.cpu().numpy()),
+                              f32bits(ref["dists"])), host
+        gi.close()
