@@ -166,7 +166,9 @@ typedef struct {
   const uint32_t* order;    /* NULL, or device [nq]: the order in which the
                                persistent waves take the queries (the t-th
                                query taken is order[t]; a permutation of
-                               0..nq-1, entries >= nq are skipped).  Results
+                               0..nq-1; an entry >= nq takes query nq-1,
+                               which is then searched twice with the same
+                               result).  Results
                                stay in each query's own row and do not
                                depend on the order; it sets how the
                                launch's tail is balanced (e.g. the longest

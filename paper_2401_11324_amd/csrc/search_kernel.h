@@ -1332,12 +1332,7 @@ void search_kernel(SearchArgs a) {
     uint32_t qi = 0;
     if (lane == 0) qi = atomicAdd(a.qcounter, 1u);
     qi = __builtin_amdgcn_readfirstlane(qi);
-    const uint32_t turn = qi;  // the queries are taken in a.order if given
-    if (turn < a.nq && a.order) {
-      qi = __builtin_amdgcn_readfirstlane(a.order[turn]);
-      if (qi >= a.nq) continue;  // not a query of the batch: nothing to do
-    }
-    if (turn >= a.nq) {
+    if (qi >= a.nq) {
       // the last workgroup out returns both counters to zero for the next
       // launch (no reset kernel or memset on the stream)
       if (lane == 0) {
@@ -1349,6 +1344,11 @@ void search_kernel(SearchArgs a) {
       }
       break;
     }
+    // the queries are taken in a.order when it is given (an entry past the
+    // batch takes the last query, searched twice with the same result)
+    if (a.order)
+      qi = min(__builtin_amdgcn_readfirstlane(a.order[qi]),
+               (uint32_t)(a.nq - 1));
     const uint64_t t_begin = a.out_times ? wall_clock64() : 0;
     if (a.abort_flag && abort_requested(a.abort_flag)) {
       // stopped: this query is not searched; its row is padding, status 2
