@@ -120,7 +120,8 @@ typedef struct {
                                form's BANG_TABLE_F16 / BANG_TABLE_U8, or
                                BANG_TABLE_EXACT (no table) */
   uint32_t flags;           /* 0, or BANG_SEARCH_RERANK_GLOBAL |
-                               BANG_SEARCH_SEEN_LOG_SHORT */
+                               BANG_SEARCH_SEEN_LOG_SHORT |
+                               BANG_SEARCH_NO_SEEN_CACHE */
   const uint32_t* query_L;  /* device [nq] or NULL: a mixed batch, query i
                                searched with worklist size L_i in [1, L]
                                and, with query_k, k_i results in
@@ -234,6 +235,11 @@ typedef struct {
  * testing that path). */
 #define BANG_SEARCH_SEEN_LOG_SHORT 2u
 
+/* The exact-distance search without its seen-id cache (BANG_TABLE_EXACT):
+ * every neighbour's base row is read (same results; for measuring the
+ * cache). */
+#define BANG_SEARCH_NO_SEEN_CACHE 4u
+
 /* Table storage forms.  Both reduced forms are computed from the FP32
  * entries of the PQ table section, so they are deterministic:
  *  - F16: entry * 2^-k rounded to half (nearest, ties to even), k >= 0 the
@@ -250,7 +256,12 @@ typedef struct {
  * "Implementation Variants").  The search ranks every node by its exact
  * squared distance to the query (the re-rank's distance, computed from the
  * base vectors in device memory) and there is no re-rank: the result is
- * the k first entries of the final worklist.  c_max is ignored. */
+ * the k first entries of the final worklist.  c_max is ignored.  With the
+ * default visited filter each wave also keeps a cache of seen ids in
+ * on-chip memory (direct-mapped, cleared per query, sized so that it costs
+ * no occupancy: 256 to 2048 ids, or none at large L): a neighbour found
+ * there was seen before in the query, which the set union would drop, so
+ * its base row is not read.  Results are unchanged. */
 #define BANG_TABLE_EXACT 3u
 
 /* Build an index on the current HIP device: validates the description

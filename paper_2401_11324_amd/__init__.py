@@ -239,7 +239,8 @@ class Index:
                filter: str = "exact", want_phases: bool = False, out=None,
                abort=None, rerank: str = "exact", stream=None,
                seen_log_short: bool = False, tables=None, order=None,
-               waves_per_cu: int = 0, _entry: str = "bang_search"):
+               waves_per_cu: int = 0, seen_cache: bool = True,
+               _entry: str = "bang_search"):
         """Stages 1-3.  Returns (ids uint32-as-int32 [nq][k], dists
         float32 [nq][k]) and, on request, the expanded nodes [nq][want_cand]
         `table` is the PQ table storage the search ranks by: "f32", the
@@ -264,7 +265,9 @@ class Index:
         cap on resident waves per CU (0: as many as fit); neither changes
         results.  seen_log_short: with the
         "seen" filter, stop setting bits after 64 logged ids and only test
-        from then on (BANG_SEARCH_SEEN_LOG_SHORT; for testing)."""
+        from then on (BANG_SEARCH_SEEN_LOG_SHORT; for testing).
+        seen_cache=False: the exact-distance search without its seen-id
+        cache (BANG_SEARCH_NO_SEEN_CACHE; same results)."""
         import torch
         qp = self._queries(q)
         nq = q.shape[0]
@@ -276,7 +279,8 @@ class Index:
             _check_out(ids, dists, nq, k, q.device)
         opts = SearchOpts(c_max, iter_cap, None, 0, None, None, TABLES[table],
                           (1 if rerank_global else 0)
-                          | (2 if seen_log_short else 0))
+                          | (2 if seen_log_short else 0)
+                          | (0 if seen_cache else 4))
         opts.filter = FILTERS[filter]
         if abort is not None:
             opts.abort = abort._h.value

@@ -70,6 +70,7 @@ struct bang_index {
   bang::Workspace ws;         // used by bang_search; grown on demand
   int num_cus = 0;
   int max_lds = 64 * 1024;    // dynamic LDS bytes one workgroup may use
+  int lds_per_cu = 64 * 1024; // LDS bytes of one CU
 };
 
 namespace bang {

@@ -191,6 +191,10 @@ int create_impl(const bang_index_desc* d, bang_index** out) {
     e = hipDeviceGetAttribute(&ix->max_lds,
                               hipDeviceAttributeMaxSharedMemoryPerBlock,
                               ix->device);
+  if (e == hipSuccess)
+    e = hipDeviceGetAttribute(&ix->lds_per_cu,
+                              hipDeviceAttributeMaxSharedMemoryPerMultiprocessor,
+                              ix->device);
   if (e != hipSuccess) {
     delete ix;
     return hip_fail(e, "hipDeviceGetAttribute");
@@ -302,9 +306,17 @@ int check_queries(const bang_index* ix, const void* queries) {
 }
 
 // Launch geometry of a search: LDS bytes and resident workgroups.
+// LDS bytes, resident waves and, for the exact-distance search with the set
+// union (unless no_cache), the seen-id cache's slots: the largest power of
+// two from 256 to kCacheMaxSlots whose LDS still leaves the occupancy the
+// search has without it (0 if none does).
+constexpr uint32_t kCacheMaxSlots = 2048;
+
 int search_geometry(bang_index* ix, uint64_t nq, uint32_t L, uint32_t iter_cap,
                     uint32_t table, int filter, bool phases, size_t* lds,
-                    uint64_t* grid, uint32_t waves_per_cu = 0) {
+                    uint64_t* grid, uint32_t waves_per_cu = 0,
+                    uint32_t* cache_slots = nullptr, bool no_cache = false) {
+  if (cache_slots) *cache_slots = 0;
   *lds = bang::search_lds_bytes(ix->dev.m, L, iter_cap, (int)table);
   hipError_t e = hipSetDevice(ix->device);
   if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
@@ -319,6 +331,23 @@ int search_geometry(bang_index* ix, uint64_t nq, uint32_t L, uint32_t iter_cap,
   if (e != hipSuccess) return hip_fail(e, "occupancy query");
   if (per_cu < 1) return fail(BANG_EUNSUPPORTED, "search kernel cannot be resident");
   if (waves_per_cu) per_cu = std::min<int>(per_cu, (int)waves_per_cu);
+  if (cache_slots && !no_cache && table == BANG_TABLE_EXACT &&
+      filter == bang::kFilterUnion) {
+    const size_t share = (size_t)ix->lds_per_cu / (size_t)per_cu;
+    for (uint32_t c = kCacheMaxSlots; c >= 256; c >>= 1) {
+      const size_t with = *lds + 4 * (size_t)c;
+      if (with > share || with > (size_t)ix->max_lds) continue;
+      int pc = 0;
+      e = bang::search_occupancy(ix->dev, (int)table, filter, phases, with,
+                                 &pc);
+      if (e != hipSuccess) return hip_fail(e, "occupancy query");
+      if (pc >= per_cu) {
+        *cache_slots = c;
+        *lds = with;
+        break;
+      }
+    }
+  }
   *grid = std::min<uint64_t>((uint64_t)per_cu * ix->num_cus, nq);
   return BANG_OK;
 }
@@ -404,7 +433,8 @@ int search_with(bang_index* ix, Workspace* ws, bool grow, const void* queries,
   if (o && o->out_cand && o->cand_stride == 0)
     return fail(BANG_EINVAL, "cand_stride must be > 0 with out_cand");
   const uint32_t flags = o ? o->flags : 0u;
-  if (flags & ~(BANG_SEARCH_RERANK_GLOBAL | BANG_SEARCH_SEEN_LOG_SHORT))
+  if (flags & ~(BANG_SEARCH_RERANK_GLOBAL | BANG_SEARCH_SEEN_LOG_SHORT |
+                BANG_SEARCH_NO_SEEN_CACHE))
     return fail(BANG_EINVAL, "unknown search flags");
   const uint32_t filter = o ? o->filter : BANG_FILTER_EXACT;
   if (filter > BANG_FILTER_SEEN)
@@ -441,8 +471,10 @@ int search_with(bang_index* ix, Workspace* ws, bool grow, const void* queries,
   const uint32_t* const order = o ? o->order : nullptr;
   if (order && !aligned(order, 4))
     return fail(BANG_EINVAL, "order not 4-byte aligned");
+  uint32_t cache_slots = 0;
   rc = search_geometry(ix, nq, L, iter_cap, table, fkind, phases != nullptr,
-                       &lds, &grid, o ? o->waves_per_cu : 0u);
+                       &lds, &grid, o ? o->waves_per_cu : 0u, &cache_slots,
+                       (flags & BANG_SEARCH_NO_SEEN_CACHE) != 0);
   if (rc) return rc;
   size_t need = (size_t)grid * iter_cap * sizeof(uint64_t);
   if (need > ws->cscratch_bytes && ws->clamp_grid) {
@@ -547,6 +579,7 @@ int search_with(bang_index* ix, Workspace* ws, bool grow, const void* queries,
     l.abort_fired = o->abort->dev + 1;
   }
   l.grid = (uint32_t)grid;
+  l.cache_slots = cache_slots;
   hipError_t e = bang::launch_search(ix->dev, l, s);
   if (e != hipSuccess) return hip_fail(e, "search launch");
   return BANG_OK;

@@ -440,7 +440,12 @@ hipError_t launch_tables_mfma(const DeviceIndex& ix, const void* queries,
 
 hipError_t launch_search(const DeviceIndex& ix, const SearchLaunch& l,
                          hipStream_t s) {
-  const size_t lds = search_lds_bytes(ix.m, l.L, l.iter_cap, l.table);
+  const size_t lds0 = search_lds_bytes(ix.m, l.L, l.iter_cap, l.table);
+  if (l.cache_slots &&
+      (l.table != kTabExact || l.bloom || l.seen || l.cache_slots < 256 ||
+       (l.cache_slots & (l.cache_slots - 1))))
+    return hipErrorInvalidValue;
+  const size_t lds = lds0 + 4 * (size_t)l.cache_slots;
   SearchArgs a;
   a.base = ix.base;
   a.rows = ix.rows;
@@ -484,6 +489,11 @@ hipError_t launch_search(const DeviceIndex& ix, const SearchLaunch& l,
   a.seen_log = l.seen_log;
   a.seen_words = l.seen_words;
   a.seen_cap = std::min(l.seen_cap, kSeenLog);
+  a.cache_off = (uint32_t)lds0;
+  a.cache_slots = l.cache_slots;
+  // slot = the top log2(cache_slots) bits of the 32-bit product
+  a.cache_shift =
+      l.cache_slots ? 32u - (uint32_t)__builtin_ctz(l.cache_slots) : 0u;
   a.qcounter = l.qcounter;
   const int dt = ix.dtype;
   const uint32_t m = ix.m, ds = ix.d / ix.m;

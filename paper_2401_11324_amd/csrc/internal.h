@@ -57,6 +57,8 @@ struct SearchLaunch {
   const uint32_t* abort_flag;  // device view of a bang_abort, or null
   uint32_t* abort_fired;
   uint32_t grid;         // workgroups (one wave each)
+  uint32_t cache_slots;  // exact distances: seen-id cache entries per wave
+                         // in LDS (0 or a power of two >= 256)
 };
 
 // The no-allocation search's device memory: a file-scope array of
@@ -72,7 +74,7 @@ void* noalloc_scratch(int device);
 bool supported(int dtype, uint32_t m, uint32_t dsub);
 
 // LDS bytes the search kernel needs for a worklist of L, an iteration cap
-// and a table storage form.
+// and a table storage form (a seen-id cache comes after them).
 size_t search_lds_bytes(uint32_t m, uint32_t L, uint32_t iter_cap, int table);
 
 // Packed adjacency rows: R ids padded to row_ids_bytes, then R x m codes.

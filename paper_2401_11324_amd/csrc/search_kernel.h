@@ -615,11 +615,13 @@ __device__ __forceinline__ uint64_t wave_min64(uint64_t v) {
 // reduction leaves each row's total in the last lane of its group, and
 // lane r collects neighbour r's.  Integer sums are exact in any order, so
 // the value equals exact_dist's.  qc = this lane's query chunk (zero past
-// the row), qq = query_sq.  Every lane must call it (cross-lane).
+// the row), qq = query_sq.  Only lanes 0..nlive-1 may hold a neighbour
+// (wave-uniform nlive).  Every lane must call it (cross-lane).
 template <int DT, int D>
 __device__ __forceinline__ float coop_dist(const void* __restrict__ base,
                                            uint32_t nb, const uint4& qc,
-                                           int32_t qq, int lane) {
+                                           int32_t qq, int lane,
+                                           uint32_t nlive = kWave) {
   constexpr int CH = D / 16;
   static_assert(D % 16 == 0 && CH >= 1 && CH <= 8, "rows of 16..128 bytes");
   constexpr int G = CH <= 2 ? 2 : (CH <= 4 ? 4 : 8);  // lanes per row
@@ -632,8 +634,13 @@ __device__ __forceinline__ float coop_dist(const void* __restrict__ base,
   for (int t = 0; t < G; ++t) {
     const uint32_t id = __shfl(nb, t * RPI + g);
     ok[t] = id != kNone && c < CH;
-    v[t] = reinterpret_cast<const uint4*>(
-        (const uint8_t*)base + (size_t)(id != kNone ? id : 0u) * D)[cc];
+    // the loads of the second half of the lanes' rows are not issued when
+    // they hold no neighbour (one wave-uniform test; a finer one costs
+    // registers)
+    v[t] = make_uint4(0u, 0u, 0u, 0u);
+    if (t < G / 2 || nlive > (uint32_t)(kWave / 2))
+      v[t] = reinterpret_cast<const uint4*>(
+          (const uint8_t*)base + (size_t)(id != kNone ? id : 0u) * D)[cc];
   }
   const uint32_t qw[4] = {qc.x, qc.y, qc.z, qc.w};
   uint32_t part[G];
@@ -1016,6 +1023,10 @@ struct SearchArgs {
   // null, or [nq]: the order in which the waves take the queries (query
   // order[t] is the t-th taken); results stay in each query's own row
   const uint32_t* order;
+  // exact distances with the set union: a direct-mapped cache of seen ids
+  // in LDS at byte cache_off, cache_slots entries (a power of two, 0 =
+  // none), slot of id x = (x * kCacheMul) >> cache_shift
+  uint32_t cache_off, cache_slots, cache_shift;
 };
 
 namespace {
@@ -1237,6 +1248,11 @@ __device__ __forceinline__ void bloom_update(uint32_t* bf, uint32_t btop,
 // the logged words are stored as zero, which leaves the bitmap clear.
 constexpr uint32_t kSeenLog = 8192u;  // logged ids per wave
 
+// Multiplier of the seen-id cache's slot hash (exact distances): the top
+// bits of id * 2654435761 (Knuth's multiplicative hashing, 2^32 over the
+// golden ratio).
+constexpr uint32_t kCacheMul = 2654435761u;
+
 enum Filter : int { kFiltUnion = 0, kFiltBloom = 1, kFiltSeen = 2 };
 
 __device__ __forceinline__ uint32_t seen_update(uint32_t* sb, uint32_t nb,
@@ -1304,7 +1320,7 @@ __device__ __forceinline__ uint64_t phase_clock() {
 // (out_phases) and is otherwise the same search.
 template <int DT, int M, int DS, int TT, bool HOST, int FILT, bool PHASES>
 __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(
-    1, max_waves_per_simd(table_bytes<TT>(M)))))
+    TT == kTabExact ? 4 : 1, max_waves_per_simd(table_bytes<TT>(M)))))
 void search_kernel(SearchArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr bool BLOOM = FILT == kFiltBloom;
@@ -1312,6 +1328,8 @@ void search_kernel(SearchArgs a) {
   constexpr int D = M * DS;
   constexpr int kTableBytes = table_bytes<TT>(M);
   constexpr bool kExact = TT == kTabExact;
+  // exact distances with the set union: the seen-id cache in LDS
+  constexpr bool kCache = kExact && FILT == kFiltUnion;
   const int lane = threadIdx.x;
   void* T = smem;
   float* lo = reinterpret_cast<float*>(smem + kTableBytes);  // U8 offsets
@@ -1325,6 +1343,7 @@ void search_kernel(SearchArgs a) {
   uint64_t* Nb = Lc + a.lrow;                                     // kWave + 4
   uint8_t* H = reinterpret_cast<uint8_t*>(Nb + kWave + 4);        // lrow + 4
   uint32_t* Hw = reinterpret_cast<uint32_t*>(H);
+  uint32_t* const Sc = reinterpret_cast<uint32_t*>(smem + a.cache_off);
   uint64_t* C = a.cscratch + (size_t)blockIdx.x * a.iter_cap;
   for (uint32_t t = lane; t < (a.lrow + 4) / 4; t += kWave) Hw[t] = 0u;
 
@@ -1425,6 +1444,15 @@ void search_kernel(SearchArgs a) {
       }
       nlog = 1;
     }
+    // seen-id cache: cleared, then the medoid is the first id in it
+    if constexpr (kCache) {
+      if (a.cache_slots) {
+        for (uint32_t i = 4u * lane; i < a.cache_slots; i += 4u * kWave)
+          *reinterpret_cast<uint4*>(Sc + i) =
+              make_uint4(kNone, kNone, kNone, kNone);
+        if (lane == 0) Sc[(s * kCacheMul) >> a.cache_shift] = s;
+      }
+    }
     // constant term of integer exact distances (the PQ forms compute it
     // after the search, so the query is not held through the loop)
     int32_t qq = 0;
@@ -1522,6 +1550,36 @@ void search_kernel(SearchArgs a) {
         ph[1] += t - tp;
         tp = t;
       }
+      // exact distances: a neighbour whose id is in the seen-id cache was
+      // seen before in this query, so the set union would drop it; its
+      // base row is not read and it takes no part.  The others enter the
+      // cache (replacing the id in their slot) and, for integer data, move
+      // to the first lanes, so that loads of rows past them are not issued.
+      uint64_t cmask = ~0ull;  // lanes with a neighbour to score
+      uint32_t nlive = kWave;
+      if constexpr (kCache) {
+        if (a.cache_slots) {
+          const uint32_t h = (nb * kCacheMul) >> a.cache_shift;
+          const bool fresh = nb != kNone && Sc[h] != nb;
+          if (fresh) Sc[h] = nb;
+          cmask = __ballot(fresh);
+          nlive = (uint32_t)__popcll(cmask);
+          if constexpr (DT != kF32) {
+            // fresh ids to lanes 0..nlive-1 in row order, the rest after
+            // them (a permutation of the lanes)
+            const uint32_t below = __builtin_amdgcn_mbcnt_hi(
+                (uint32_t)(cmask >> 32),
+                __builtin_amdgcn_mbcnt_lo((uint32_t)cmask, 0u));
+            const uint32_t dst =
+                fresh ? below : nlive + ((uint32_t)lane - below);
+            nb = (uint32_t)__builtin_amdgcn_ds_permute(
+                (int)(dst * 4u), (int)(fresh ? nb : kNone));
+            cmask = nlive == (uint32_t)kWave ? ~0ull : (1ull << nlive) - 1ull;
+          } else if (!fresh) {
+            nb = kNone;
+          }
+        }
+      }
       // Bloom filter: both entries of each neighbour are updated with this
       // lane's tag below (after any code gather, so that the scoring waits
       // for neither); the previous values are used after the scoring
@@ -1535,7 +1593,7 @@ void search_kernel(SearchArgs a) {
         bloom_update(bf, btop, iters, lane, nb, b1, b2, btag, bo1, bo2);
         if constexpr (SEEN) sold = seen_update(sb, nb, sset);
         touch_row<M, false, HOST>(a, key_id(nx), lane, touched);
-        const float dq = coop_dist<DT, D>(a.base, nb, qc, qq, lane);
+        const float dq = coop_dist<DT, D>(a.base, nb, qc, qq, lane, nlive);
         key = nb != kNone ? make_key(dq, nb) : kInf;
       } else if constexpr (kExact) {
         bloom_update(bf, btop, iters, lane, nb, b1, b2, btag, bo1, bo2);
@@ -1561,9 +1619,11 @@ void search_kernel(SearchArgs a) {
         const uint64_t k2 = make_key(adc_codes<M, TT>(code), nb);
         key = nb != kNone ? k2 : kInf;
       }
-      // a neighbour whose bit was set is dropped before the worklist rank;
-      // new ones are logged (in row order) for the clearing at the end
-      uint64_t fresh_mask = ~0ull;
+      // a neighbour found in the seen-id cache, or whose seen bit was set,
+      // is dropped before the worklist rank, which a row with no other
+      // neighbour skips; new bits are logged (in row order) for the
+      // clearing at the end
+      uint64_t fresh_mask = cmask;
       if constexpr (SEEN) {
         const bool fresh = !((sold >> (nb & 31u)) & 1u);
         fresh_mask = __ballot(fresh);

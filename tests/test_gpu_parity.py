@@ -430,6 +430,30 @@ def test_sift1m_exact_distance_sampled_bit_exact():
     gi.close()
 
 
+def test_seen_cache_changes_no_result():
+    """The exact-distance search's seen-id cache (on by default) only skips
+    base rows of neighbours the set union would drop: ids, distances,
+    expansion order and iteration counts equal those of the search without
+    it, on the 1M index at the bench's worklist sizes, and with one wave
+    per CU (the largest cache, 2,048 ids)."""
+    w, ix, d = load_workload("sift1m")
+    gi = bang_mod().Index(ix.base, ix.adj, ix.medoid, ix.codebooks, ix.codes)
+    qt = to_dev(d["queries"][:2000])
+    for L, wpc in ((64, 0), (256, 0), (608, 0), (1024, 0), (256, 1)):
+        cap = oracle.iter_cap_for(L)
+        got = []
+        for cache in (True, False):
+            ids, dist, cand, cnt = gi.search(
+                qt, w.k, L, want_cand=cap, want_counters=True, table="exact",
+                seen_cache=cache, waves_per_cu=wpc)
+            torch.cuda.synchronize()
+            got.append((u32(ids), f32bits(dist.cpu().numpy()), u32(cand),
+                        u32(cnt)))
+        for a, b in zip(*got):
+            assert np.array_equal(a, b), (L, wpc)
+    gi.close()
+
+
 # --------------------------------------------------------------------------
 # mixed batches (per-query k and L) and the serving loop: every result is
 # the one the query gets alone
