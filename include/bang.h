@@ -258,8 +258,9 @@ typedef struct {
  * base vectors in device memory) and there is no re-rank: the result is
  * the k first entries of the final worklist.  c_max is ignored.  With the
  * default visited filter each wave also keeps a cache of seen ids in
- * on-chip memory (direct-mapped, cleared per query, sized so that it costs
- * no occupancy: 256 to 2048 ids, or none at large L): a neighbour found
+ * on-chip memory (direct-mapped, cleared per query, sized from the LDS the
+ * wave's share leaves at the search's occupancy: 256 to 4096 ids, or none
+ * at large L): a neighbour found
  * there was seen before in the query, which the set union would drop, so
  * its base row is not read.  Results are unchanged. */
 #define BANG_TABLE_EXACT 3u

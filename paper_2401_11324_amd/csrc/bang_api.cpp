@@ -310,7 +310,7 @@ int check_queries(const bang_index* ix, const void* queries) {
 // union (unless no_cache), the seen-id cache's slots: the largest power of
 // two from 256 to kCacheMaxSlots whose LDS still leaves the occupancy the
 // search has without it (0 if none does).
-constexpr uint32_t kCacheMaxSlots = 2048;
+constexpr uint32_t kCacheMaxSlots = 4096;
 
 int search_geometry(bang_index* ix, uint64_t nq, uint32_t L, uint32_t iter_cap,
                     uint32_t table, int filter, bool phases, size_t* lds,

@@ -435,7 +435,7 @@ def test_seen_cache_changes_no_result():
     base rows of neighbours the set union would drop: ids, distances,
     expansion order and iteration counts equal those of the search without
     it, on the 1M index at the bench's worklist sizes, and with one wave
-    per CU (the largest cache, 2,048 ids)."""
+    per CU (the largest cache, 4,096 ids)."""
     w, ix, d = load_workload("sift1m")
     gi = bang_mod().Index(ix.base, ix.adj, ix.medoid, ix.codebooks, ix.codes)
     qt = to_dev(d["queries"][:2000])
