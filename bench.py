@@ -799,10 +799,11 @@ class Runner:
                 "fp32_max": float(e32.max()), "fp32_mean": float(e32.mean())}
 
     def measure(self, table, L, index=None, filter="exact", rerank="exact",
-                bf16_tables=False):
+                bf16_tables=False, seen_cache=True):
         """K timed steps of one form; returns its record.  bf16_tables: a
         step is the BF16-MFMA table build followed by the search ranking by
-        those tables."""
+        those tables.  seen_cache=False: the exact-distance search without
+        its seen-id cache."""
         torch, w, a = self.torch, self.w, self.a
         gi_ = index or self.gi
         q, dev, gt = self.q, self.dev, self.gt
@@ -816,7 +817,7 @@ class Runner:
             if bf16_tables:
                 gi_.build_pq_tables(q, out=tabs, bf16=True)
             gi_.search(q, k, L, out=(ids, dist), table=table, filter=filter,
-                       rerank=rerank, tables=tabs)
+                       rerank=rerank, tables=tabs, seen_cache=seen_cache)
 
         for _ in range(a.warmup):
             step()
@@ -845,7 +846,7 @@ class Runner:
                                            want_counters=True,
                                            want_times=True, table=table,
                                            filter=filter, rerank=rerank,
-                                           tables=tabs)
+                                           tables=tabs, seen_cache=seen_cache)
         torch.cuda.synchronize()
         cand = cand.cpu().numpy().view(np.uint32)
         cnt = cnt.cpu().numpy()
@@ -969,12 +970,21 @@ def main(argv=None):
               f"`python -m oracle.build_index {w.name}`", file=sys.stderr)
         return 3
     run = Runner(w, a, bang, torch)
+    t0 = time.perf_counter()
+
+    def progress(msg):
+        # one line per finished section on stderr (the JSON line stays the
+        # only output on stdout)
+        print(f"[bench {time.perf_counter() - t0:6.1f}s] {msg}",
+              file=sys.stderr, flush=True)
     d, gi, gt, k = run.d, run.gi, run.gt, w.k
     sweep = run.sweep(() if a.no_sweep else TABLES + ("exact",))
     pick_L = run.pick_L
     measure = run.measure
 
+    progress("L sweep")
     plain = measure("f32", pick_L("f32"))
+    progress("plain FP32")
     prec = {t: measure(t, pick_L(t)) for t in ("f16", "u8")}
     # the same forms ranking by tables built with BF16 MFMA (a step builds
     # them, then searches by them), at each form's point
@@ -984,9 +994,20 @@ def main(argv=None):
             rec0["recall10"] - rec["recall10"], 4)
         prec[t + "+bf16_mfma_tables"] = rec
     prec["table_build"] = table_build_section(run)
+    progress("precision forms")
     # the paper's Exact-distance Version: no table, no re-rank
     exact = None if a.no_sweep and not a.L else measure("exact",
                                                          pick_L("exact"))
+    if exact is not None:
+        # the same point without the seen-id cache, which reads every
+        # neighbour's base row (the packed-row figures above count that
+        # design's reads)
+        nc = measure("exact", exact["L"], seen_cache=False)
+        exact["without_seen_cache"] = {
+            "qps": nc["qps"], "kernel_ms_mean": nc["kernel_ms_mean"],
+            "recall10": nc["recall10"]}
+        exact["seen_cache_speedup"] = round(exact["qps"] / nc["qps"], 3)
+        progress("exact distances")
     L = plain["L"]
     host = None
     if not a.no_host:
@@ -1006,6 +1027,7 @@ def main(argv=None):
             "bytes": "adjacency rows, 4R bytes per expansion",
             "random_row_probe": hprobe,
             "frac_of_probe": round(link / hprobe["gbs"], 4)}
+        progress("host-resident adjacency")
     # the rate at which random packed rows can be read at all (the search's
     # access pattern with no work between reads)
     probe = gather_probe(gi, torch, 1 << 22)
@@ -1074,26 +1096,34 @@ def main(argv=None):
         out["host_resident"] = host
     if not a.no_ablation:
         out["batch_size"] = batch_section(run, L)
+        progress("batch sizes")
         out["pq_subspaces"] = m_section(run, bang)
+        progress("subspace counts")
         pts = [("f32", L, plain)]
         if exact is not None:
             pts.append(("exact", exact["L"], exact))
         out["bloom_filter"] = bloom_section(run, pts)
+        progress("Bloom filter")
         out["mixed_batch"] = mixed_section(run)
+        progress("mixed batch")
         # plus a small worklist, where the once-per-query table build and
         # re-rank weigh most
         out["phase_split"] = phase_section(
             run, [("f32", L), ("u8", prec["u8"]["L"])] +
             ([("exact", exact["L"])] if exact is not None else []) +
             ([("f32", 64)] if L != 64 else []))
+        progress("phase split")
     if not a.no_serve:
         out["serving"] = serving_section(gi, d, w, gt)
+        progress("serving")
     if not a.no_deep:
         out["precision_form_deep1m"] = deep_section(a, bang, torch)
+        progress("deep1m")
     if exact is not None:
         out["exact_distance"] = exact
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(d, d["queries"], k, L)
+        progress("CPU baseline")
     print(json.dumps(out), flush=True)
     return 0
 

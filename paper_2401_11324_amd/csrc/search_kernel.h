@@ -1135,25 +1135,29 @@ __device__ __forceinline__ void merge_live(
     rn += (x0 < kk) + (x1 < kk) + (x2 < kk) + (x3 < kk);
   }
   const uint32_t bmask = B < 4 ? (1u << (8 * B)) - 1u : ~0u;
-  uint32_t hb[NS], shift0[NS];
-  uint32_t carry = 0;
+  // this lane's live-key count per super-row, one byte each: a count, and
+  // any sum of them over lanes, is at most nv <= 64, so one scan of the
+  // packed word scans every super-row at once with no carry between bytes
+  static_assert(NS <= 4, "one byte per super-row");
+  uint32_t hb[NS];
+  uint32_t tot = 0;
 #pragma unroll
   for (int sr = 0; sr < NS; ++sr) {
     const bool act = (uint32_t)sr < nsup && (uint32_t)sr >= s0;
     hb[sr] = act ? __builtin_amdgcn_alignbyte(w1[sr], w0[sr], o[sr] & 3u) &
                        bmask
                  : 0u;
-    const uint32_t tot = __builtin_amdgcn_udot4(hb[sr], 0x01010101u, 0u,
-                                                false);
-    uint32_t excl = 0;
-    if (NS == 1 || (uint32_t)sr < nsup) {
-      excl = wave_exclusive_scan(tot);
-      shift0[sr] = carry + excl;
-      carry += __builtin_amdgcn_readlane(excl + tot, kWave - 1);
-    } else {
-      shift0[sr] = carry;
-    }
+    tot |= __builtin_amdgcn_udot4(hb[sr], 0x01010101u, 0u, false) << (8 * sr);
   }
+  const uint32_t excl = wave_exclusive_scan(tot);
+  // byte sr of carry: the live keys of the super-rows before sr
+  const uint32_t carry =
+      __builtin_amdgcn_readlane(excl + tot, kWave - 1) * 0x01010100u;
+  uint32_t shift0[NS];
+#pragma unroll
+  for (int sr = 0; sr < NS; ++sr)
+    shift0[sr] = __builtin_amdgcn_ubfe(carry, 8 * sr, 8) +
+                 __builtin_amdgcn_ubfe(excl, 8 * sr, 8);
 #pragma unroll
   for (int sr = 0; sr < NS; ++sr) {
     if ((uint32_t)sr >= nsup || (uint32_t)sr < s0) continue;
