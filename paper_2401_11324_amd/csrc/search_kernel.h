@@ -1090,20 +1090,22 @@ __device__ __forceinline__ void load_block(const uint64_t* p,
 // position = own index + rank in the other list), in place.  Lc: the
 // worklist (Llen entries in super-rows of sup = 64*B, lane l owning B
 // consecutive entries of each); keep / kk / r: this lane's live key and
-// its worklist rank; idx: its index among the nv live keys; cur: u*,
-// marked visited on its way.  A new key's position is r + (live keys
-// below it); worklist entry j moves right by the live keys whose rank is
-// <= j, a prefix of the byte histogram H of live ranks over super-rows
-// s0 .. nsup-1 (NS = 1 when the worklist is a single super-row).  Every
-// LDS read goes out before the first write, so entries move in place; a
-// write with nothing to store goes to the lane's own slot of Nb, whose
-// live keys are no longer needed, instead of behind a branch.
+// its worklist rank; idx: its index among the nv live keys (u* is
+// already marked visited in the list).  A new key's position is r + (live
+// keys below it); worklist entry j moves right by the live keys whose
+// rank is <= j, a prefix of the byte histogram H of live ranks over
+// super-rows s0 .. nsup-1 (NS = 1 when the worklist is a single
+// super-row).  Every LDS read goes out before the first write, so entries
+// move in place; a write with nothing to store goes to the lane's own
+// slot of Nb, whose live keys are no longer needed, instead of behind a
+// branch.  Slots of a block past the list are moved too: every live rank
+// is below them, so they land at or past the new end (and before Lq),
+// where nothing reads them.
 template <int NS>
 __device__ __forceinline__ void merge_live(
     uint64_t* Lc, uint64_t* Nb, uint32_t* Hw, int lane, uint32_t B,
-    uint32_t sup, uint32_t Llen, uint32_t Lq, uint32_t cur, uint32_t nsup,
-    uint32_t s0, bool keep, uint64_t kk, uint32_t idx, uint32_t r,
-    uint32_t nv) {
+    uint32_t sup, uint32_t Lq, uint32_t nsup, uint32_t s0, bool keep,
+    uint64_t kk, uint32_t idx, uint32_t r, uint32_t nv) {
   uint64_t v[NS][kPer];
   uint32_t o[NS];  // this lane's first position per super-row (also its
                    // byte in H)
@@ -1166,10 +1168,9 @@ __device__ __forceinline__ void merge_live(
 #pragma unroll
     for (int t = 0; t < kPer; ++t) {
       p += __builtin_amdgcn_ubfe(hb[sr], 8 * t, 8);
-      const uint32_t j = j0 + t;
-      const bool ok = (uint32_t)t < B && j < Llen && p < Lq;
+      const bool ok = (uint32_t)t < B && p < Lq;
       uint64_t* dst = ok ? Lc + p : Nb + lane;
-      *dst = v[sr][t] | (uint64_t)(j == cur);
+      *dst = v[sr][t];
       ++p;
     }
   }
@@ -1793,11 +1794,11 @@ void search_kernel(SearchArgs a) {
       const uint32_t s0 = (rmin >= sup) + (rmin >= 2u * sup) +
                           (rmin >= 3u * sup);
       if (nsup == 1)
-        merge_live<1>(Lc, Nb, Hw, lane, B, sup, Llen, Lq, cur, nsup, s0, keep,
-                      kk, idx, r, nv);
+        merge_live<1>(Lc, Nb, Hw, lane, B, sup, Lq, nsup, s0, keep, kk, idx,
+                      r, nv);
       else
-        merge_live<kPer>(Lc, Nb, Hw, lane, B, sup, Llen, Lq, cur, nsup, s0,
-                         keep, kk, idx, r, nv);
+        merge_live<kPer>(Lc, Nb, Hw, lane, B, sup, Lq, nsup, s0, keep, kk,
+                         idx, r, nv);
       // clear the histogram bytes used (positions rmin .. Llen)
       for (uint32_t t = rmin / 4 + lane; t <= Llen / 4; t += kWave) Hw[t] = 0u;
       Llen = min(Lq, Llen + nv);
