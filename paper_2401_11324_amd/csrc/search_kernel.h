@@ -594,6 +594,17 @@ __device__ __forceinline__ uint64_t min_dpp(uint64_t v) {
   return t < v ? t : v;
 }
 
+// Minimum of one u32 per lane across the wave, returned to every lane.
+__device__ __forceinline__ uint32_t wave_min32(uint32_t v) {
+  v = min(v, dpp<0x111>(0xFFFFFFFFu, v));
+  v = min(v, dpp<0x112>(0xFFFFFFFFu, v));
+  v = min(v, dpp<0x114>(0xFFFFFFFFu, v));
+  v = min(v, dpp<0x118>(0xFFFFFFFFu, v));
+  v = min(v, dpp<0x142, 0xA>(0xFFFFFFFFu, v));
+  v = min(v, dpp<0x143, 0xC>(0xFFFFFFFFu, v));
+  return __builtin_amdgcn_readlane(v, 63);
+}
+
 // Minimum of one u64 per lane across the wave, returned to every lane.
 __device__ __forceinline__ uint64_t wave_min64(uint64_t v) {
   v = min_dpp<0x111>(v);
@@ -1746,17 +1757,31 @@ void search_kernel(SearchArgs a) {
                  first_of((uint32_t)va, am);
         }
       }
-      // no live key (most expansions once the worklist is full): b does
-      // not exist and the wave minimum is skipped
+      // b, the best live key, has the smallest worklist rank rb of them
+      // (ranks follow key order); live keys of equal rank fall between the
+      // same two entries and are told apart by a wave minimum over those
+      // lanes alone.  No live key (most expansions once the worklist is
+      // full): b does not exist.
       const uint64_t km = __ballot(keep);
-      const uint64_t bkey = km ? wave_min64(kk) : kInf;
+      uint64_t bkey = kInf;
+      uint32_t rb = kNone;
+      if (km) {
+        rb = wave_min32(keep ? r : kNone);
+        const uint64_t tie = __ballot(keep && r == rb);
+        if ((tie & (tie - 1)) == 0) {
+          const int l = __builtin_ctzll(tie);
+          bkey = ((uint64_t)__builtin_amdgcn_readlane((uint32_t)(kk >> 32), l)
+                  << 32) |
+                 __builtin_amdgcn_readlane((uint32_t)kk, l);
+        } else {
+          bkey = wave_min64(keep && r == rb ? kk : kInf);
+        }
+      }
       uint32_t best = kNone;
       uint64_t bestkey = kInf;
       if (bkey < akey) {
-        const uint64_t bl = __ballot(kk == bkey);
-        const uint32_t bpos = first_of(r, bl);
-        if (bpos < Lq) {
-          best = bpos;
+        if (rb < Lq) {
+          best = rb;
           bestkey = bkey;
         }
       } else if (akey != kInf) {
@@ -1784,7 +1809,7 @@ void search_kernel(SearchArgs a) {
         continue;
       }
       // smallest worklist rank of a live key (b's): entries below it stay
-      const uint32_t rmin = first_of(r, __ballot(kk == bkey));
+      const uint32_t rmin = rb;
       const uint32_t idx = __builtin_amdgcn_mbcnt_hi(
           (uint32_t)(km >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)km, 0u));
       // super-rows in use and the first one with a moving entry (Llen and
