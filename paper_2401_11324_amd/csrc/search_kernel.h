@@ -689,16 +689,24 @@ __device__ __forceinline__ float coop_dist(const void* __restrict__ base,
   return (float)(int32_t)(tot + (uint32_t)qq);
 }
 
+// The u64 at LDS byte address b (the dynamic LDS block starts at address
+// 0: search_kernel declares no static LDS).
+__device__ __forceinline__ uint64_t lds_u64(uint32_t b) {
+  using lds_t = __attribute__((address_space(3))) const uint64_t;
+  return *reinterpret_cast<lds_t*>(static_cast<uintptr_t>(b));
+}
+
 // Number P of entries of the sorted LDS list A[0..len) whose key, visited
 // bit ignored, is below x's (1 <= len <= 1024, last = A[len-1]), and in ge
-// the entry A[P] (kInf when P = len).  (a >> 1) < (x >> 1) is tested as
-// a < (x & ~1).  Radix-4 lifting: three independent probes per level, half
-// the dependent LDS reads of a binary search, down to a last level that
-// reads the four entries P can be (pos .. pos+3): the first of them not
-// below x is A[P], so ge comes from that level alone.  Probes past
-// A[len-2] are clamped to A[len-1] = last, which is known not to be below
-// x (a clamp instead of a branch).
-__device__ __forceinline__ uint32_t rank_in(const uint64_t* A, uint32_t len,
+// the entry A[P] (kInf when P = len); A is at LDS byte address base.
+// (a >> 1) < (x >> 1) is tested as a < (x & ~1).  Radix-4 lifting: three
+// independent probes per level, half the dependent LDS reads of a binary
+// search, down to a last level that reads the four entries P can be
+// (pos .. pos+3): the first of them not below x is A[P], so ge comes from
+// that level alone.  Probes past A[len-2] are clamped to A[len-1] = last,
+// which is known not to be below x (a clamp instead of a branch); probes
+// are kept as byte addresses, so each is one add and one clamp.
+__device__ __forceinline__ uint32_t rank_in(uint32_t base, uint32_t len,
                                             uint64_t last, uint64_t x,
                                             uint64_t& ge) {
   const uint64_t xs = x & ~1ull;
@@ -707,25 +715,25 @@ __device__ __forceinline__ uint32_t rank_in(const uint64_t* A, uint32_t len,
     return len;
   }
   const uint32_t lim = len - 1;  // the answer is at most lim
-  uint32_t pos = 0;
+  const uint32_t la = base + 8u * lim;
+  uint32_t pa = base;  // address of A[pos]
   for (uint32_t s = 256; s > 1; s >>= 2) {
     if (s > lim) continue;
-    const uint32_t i1 = pos + s - 1, i2 = i1 + s, i3 = i2 + s;
-    const uint64_t v1 = A[min(i1, lim)];
-    const uint64_t v2 = A[min(i2, lim)];
-    const uint64_t v3 = A[min(i3, lim)];
-    pos += s * ((uint32_t)(v1 < xs) + (uint32_t)(v2 < xs) +
-                (uint32_t)(v3 < xs));
+    const uint64_t v1 = lds_u64(min(pa + 8u * (s - 1), la));
+    const uint64_t v2 = lds_u64(min(pa + 8u * (2 * s - 1), la));
+    const uint64_t v3 = lds_u64(min(pa + 8u * (3 * s - 1), la));
+    pa += 8u * s *
+          ((uint32_t)(v1 < xs) + (uint32_t)(v2 < xs) + (uint32_t)(v3 < xs));
   }
   // P is in pos .. pos+3 (and at most lim, where A[lim] = last is not
   // below x)
-  const uint64_t v0 = A[min(pos, lim)];
-  const uint64_t v1 = A[min(pos + 1, lim)];
-  const uint64_t v2 = A[min(pos + 2, lim)];
-  const uint64_t v3 = A[min(pos + 3, lim)];
+  const uint64_t v0 = lds_u64(min(pa, la));
+  const uint64_t v1 = lds_u64(min(pa + 8u, la));
+  const uint64_t v2 = lds_u64(min(pa + 16u, la));
+  const uint64_t v3 = lds_u64(min(pa + 24u, la));
   const bool p0 = v0 < xs, p1 = v1 < xs, p2 = v2 < xs;
   ge = !p0 ? v0 : (!p1 ? v1 : (!p2 ? v2 : v3));
-  return pos + (uint32_t)p0 + (uint32_t)p1 + (uint32_t)p2;
+  return (pa - base) / 8u + (uint32_t)p0 + (uint32_t)p1 + (uint32_t)p2;
 }
 
 // Ascending bitonic sort of S[0..P) in LDS by one wave (P a power of two).
@@ -1666,7 +1674,7 @@ void search_kernel(SearchArgs a) {
       // entry equal to it, and is never kept.
       uint64_t ge = kInf;
       uint32_t r = Llen;
-      if (fresh_mask) r = rank_in(Lc, Llen, last, key, ge);
+      if (fresh_mask) r = rank_in(a.region0, Llen, last, key, ge);
       bool keep = (ge >> 1) != (key >> 1) && r < Lq;
       if constexpr (BLOOM) {
         // an entry is set for this lane if it held a smaller tag: an
