@@ -1130,9 +1130,11 @@ __device__ __forceinline__ void merge_live(
                    // byte in H)
 #pragma unroll
   for (int sr = 0; sr < NS; ++sr) {
-    // super-rows past the list read super-row 0 again (unused)
+    // super-rows past the list read super-row 0 again (unused); only the
+    // super-rows that move (s0 .. nsup-1) are read
     o[sr] = (NS == 1 || (uint32_t)sr < nsup ? sr * sup : 0u) + B * lane;
-    load_block(Lc + o[sr], v[sr]);
+    if (NS == 1 || ((uint32_t)sr >= s0 && (uint32_t)sr < nsup))
+      load_block(Lc + o[sr], v[sr]);
   }
   if (keep) {
     Nb[idx] = kk;  // the live keys, compacted
@@ -1184,10 +1186,21 @@ __device__ __forceinline__ void merge_live(
     if ((uint32_t)sr >= nsup || (uint32_t)sr < s0) continue;
     const uint32_t j0 = sr * sup + B * lane;
     uint32_t p = j0 + shift0[sr];
+    // with several super-rows B = kPer; a super-row whose entries all stay
+    // below Lq after moving right by at most nv needs no test per entry
+    if (NS > 1 && (sr + 1) * sup + nv <= Lq) {
+#pragma unroll
+      for (int t = 0; t < kPer; ++t) {
+        p += __builtin_amdgcn_ubfe(hb[sr], 8 * t, 8);
+        Lc[p] = v[sr][t];
+        ++p;
+      }
+      continue;
+    }
 #pragma unroll
     for (int t = 0; t < kPer; ++t) {
       p += __builtin_amdgcn_ubfe(hb[sr], 8 * t, 8);
-      const bool ok = (uint32_t)t < B && p < Lq;
+      const bool ok = (NS > 1 || (uint32_t)t < B) && p < Lq;
       uint64_t* dst = ok ? Lc + p : Nb + lane;
       *dst = v[sr][t];
       ++p;
