@@ -701,14 +701,16 @@ __device__ __forceinline__ uint64_t lds_u64(uint32_t b) {
 // the entry A[P] (kInf when P = len); A is at LDS byte address base.
 // (a >> 1) < (x >> 1) is tested as a < (x & ~1).  Radix-4 lifting: three
 // independent probes per level, half the dependent LDS reads of a binary
-// search, down to a last level that reads the four entries P can be
-// (pos .. pos+3): the first of them not below x is A[P], so ge comes from
-// that level alone.  Probes past A[len-2] are clamped to A[len-1] = last,
+// search (those of the first level, the same for every key, given in top),
+// down to a last level that reads the four entries P can be (pos ..
+// pos+3): the first of them not below x is A[P], so ge comes from that
+// level alone.  Probes past A[len-2] are clamped to A[len-1] = last,
 // which is known not to be below x (a clamp instead of a branch); probes
 // are kept as byte addresses, so each is one add and one clamp.
 __device__ __forceinline__ uint32_t rank_in(uint32_t base, uint32_t len,
-                                            uint64_t last, uint64_t x,
-                                            uint64_t& ge) {
+                                            uint64_t last,
+                                            const uint64_t (&top)[3],
+                                            uint64_t x, uint64_t& ge) {
   const uint64_t xs = x & ~1ull;
   if (last < xs) {
     ge = kInf;
@@ -716,8 +718,13 @@ __device__ __forceinline__ uint32_t rank_in(uint32_t base, uint32_t len,
   }
   const uint32_t lim = len - 1;  // the answer is at most lim
   const uint32_t la = base + 8u * lim;
+  // the first level's probes were read by the caller (top: A[255], A[511],
+  // A[767], clamped to A[lim], which is not below x)
   uint32_t pa = base;  // address of A[pos]
-  for (uint32_t s = 256; s > 1; s >>= 2) {
+  if (lim >= 256)
+    pa += 2048u * ((uint32_t)(top[0] < xs) + (uint32_t)(top[1] < xs) +
+                   (uint32_t)(top[2] < xs));
+  for (uint32_t s = 64; s > 1; s >>= 2) {
     if (s > lim) continue;
     const uint64_t v1 = lds_u64(min(pa + 8u * (s - 1), la));
     const uint64_t v2 = lds_u64(min(pa + 8u * (2 * s - 1), la));
@@ -1531,6 +1538,11 @@ void search_kernel(SearchArgs a) {
     uint64_t curkey = make_key(d0, s);
     if (lane == 0) Lc[0] = curkey;
     uint32_t Llen = 1, cur = 0, iters = 0, status = 0;
+    // the rank's first-level entries (255, 511, 767, clamped to the last
+    // one), the same for every key until the list changes: read after each
+    // merge, off the rank's path, and only once the list passes 256
+    // entries (the rank skips the level below that)
+    uint64_t top[3] = {curkey, curkey, curkey};
     uint32_t touched = 0;  // result of the last touch_row (never read)
     // the expanded keys, written to C 64 at a time: lane e holds that of
     // expansion e mod 64 until its group of 64 is stored
@@ -1687,7 +1699,7 @@ void search_kernel(SearchArgs a) {
       // entry equal to it, and is never kept.
       uint64_t ge = kInf;
       uint32_t r = Llen;
-      if (fresh_mask) r = rank_in(a.region0, Llen, last, key, ge);
+      if (fresh_mask) r = rank_in(a.region0, Llen, last, top, key, ge);
       bool keep = (ge >> 1) != (key >> 1) && r < Lq;
       if constexpr (BLOOM) {
         // an entry is set for this lane if it held a smaller tag: an
@@ -1851,6 +1863,11 @@ void search_kernel(SearchArgs a) {
       cur = best;
       curkey = bestkey;
       __syncthreads();
+      if (Llen > 256) {
+        top[0] = Lc[255];
+        top[1] = Lc[min(511u, Llen - 1)];
+        top[2] = Lc[min(767u, Llen - 1)];
+      }
       if constexpr (PHASES) ph[5] += phase_clock() - t4;
     }
     if constexpr (PHASES) tp = phase_clock();
