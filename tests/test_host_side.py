@@ -1,7 +1,8 @@
 """Host-side pieces (no GPU): the seeded serving request stream, the
-autotuner's choice rule, and the packed adjacency storage of the index
-files."""
+autotuner's choice rule, the launch autotuner's take orders, and the packed
+adjacency storage of the index files."""
 import numpy as np
+import pytest
 
 import synth
 from paper_2401_11324_amd import serving
@@ -104,3 +105,19 @@ def test_mixed_batch_recipe():
     lo = L[k < 16]  # not raised to k
     med = np.median(np.log(lo))
     assert abs(med - 0.5 * (np.log(16) + np.log(256))) < 0.05
+
+
+def test_take_orders():
+    """The launch autotuner's take orders: 'given' keeps the batch order,
+    'longest_first' is a permutation with non-increasing L and the batch's
+    order among equal L (stable); an unknown name is an error."""
+    from paper_2401_11324_amd import tuning
+    Lq = np.array([32, 256, 16, 256, 100, 32, 1024, 16])
+    assert tuning.order_of("given", Lq) is None
+    o = tuning.order_of("longest_first", Lq)
+    assert o.dtype == np.int32
+    assert sorted(o.tolist()) == list(range(len(Lq)))
+    assert np.all(np.diff(Lq[o]) <= 0)
+    assert o.tolist() == [6, 1, 3, 4, 0, 5, 2, 7]
+    with pytest.raises(ValueError):
+        tuning.order_of("shortest_first", Lq)
