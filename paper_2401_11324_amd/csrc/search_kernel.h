@@ -1216,6 +1216,41 @@ __device__ __forceinline__ void merge_live(
   if (keep && r + rn < Lq) Lc[r + rn] = kk;
 }
 
+// The merge of a single live key x of worklist rank r (wave-uniform; the
+// usual merge): entries r .. Lq-2 move right by one, the entry at Lq-1 of
+// a full list drops out, and x takes position r.  No histogram and no
+// ranking among live keys; the same in-place order of reads before writes
+// as merge_live, and the same spare slot of Nb for a lane with nothing to
+// store.
+template <int NS>
+__device__ __forceinline__ void merge_one(uint64_t* Lc, uint64_t* Nb,
+                                          int lane, uint32_t B, uint32_t sup,
+                                          uint32_t Lq, uint32_t nsup,
+                                          uint32_t s0, uint32_t r,
+                                          uint64_t x) {
+  uint64_t v[NS][kPer];
+#pragma unroll
+  for (int sr = 0; sr < NS; ++sr) {
+    const uint32_t o = (NS == 1 || (uint32_t)sr < nsup ? sr * sup : 0u) +
+                       B * lane;
+    if (NS == 1 || ((uint32_t)sr >= s0 && (uint32_t)sr < nsup))
+      load_block(Lc + o, v[sr]);
+  }
+#pragma unroll
+  for (int sr = 0; sr < NS; ++sr) {
+    if ((uint32_t)sr >= nsup || (uint32_t)sr < s0) continue;
+    const uint32_t j0 = sr * sup + B * lane;
+#pragma unroll
+    for (int t = 0; t < kPer; ++t) {
+      const uint32_t j = j0 + t;
+      const bool ok = (NS > 1 || (uint32_t)t < B) && j >= r && j + 1 < Lq;
+      uint64_t* dst = ok ? Lc + j + 1 : Nb + lane;
+      *dst = v[sr][t];
+    }
+  }
+  if (lane == 0) Lc[r] = x;
+}
+
 // Lanes past R hold no neighbour.
 __device__ __forceinline__ uint32_t row_mask(const SearchArgs& a, int lane,
                                              uint32_t nb) {
@@ -1851,14 +1886,23 @@ void search_kernel(SearchArgs a) {
           1u + (Llen > sup) + (Llen > 2u * sup) + (Llen > 3u * sup);
       const uint32_t s0 = (rmin >= sup) + (rmin >= 2u * sup) +
                           (rmin >= 3u * sup);
-      if (nsup == 1)
-        merge_live<1>(Lc, Nb, Hw, lane, B, sup, Lq, nsup, s0, keep, kk, idx,
-                      r, nv);
-      else
-        merge_live<kPer>(Lc, Nb, Hw, lane, B, sup, Lq, nsup, s0, keep, kk,
-                         idx, r, nv);
-      // clear the histogram bytes used (positions rmin .. Llen)
-      for (uint32_t t = rmin / 4 + lane; t <= Llen / 4; t += kWave) Hw[t] = 0u;
+      if (nv == 1) {
+        // one live key: b, of rank rb (below Lq, as every live key's)
+        if (nsup == 1)
+          merge_one<1>(Lc, Nb, lane, B, sup, Lq, nsup, s0, rb, bkey);
+        else
+          merge_one<kPer>(Lc, Nb, lane, B, sup, Lq, nsup, s0, rb, bkey);
+      } else {
+        if (nsup == 1)
+          merge_live<1>(Lc, Nb, Hw, lane, B, sup, Lq, nsup, s0, keep, kk,
+                        idx, r, nv);
+        else
+          merge_live<kPer>(Lc, Nb, Hw, lane, B, sup, Lq, nsup, s0, keep, kk,
+                           idx, r, nv);
+        // clear the histogram bytes used (positions rmin .. Llen)
+        for (uint32_t t = rmin / 4 + lane; t <= Llen / 4; t += kWave)
+          Hw[t] = 0u;
+      }
       Llen = min(Lq, Llen + nv);
       cur = best;
       curkey = bestkey;
