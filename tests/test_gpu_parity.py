@@ -134,6 +134,17 @@ def test_search_bit_exact(small_indexes, name, k, L):
     run_and_compare(ix, gi, q, k, L, label=f"{name} k={k} L={L}")
 
 
+@pytest.mark.parametrize("L", [255, 256, 257, 511, 512, 513, 767, 768, 769])
+def test_search_at_super_row_boundaries(small_indexes, L):
+    """Worklist sizes on both sides of each super-row boundary (256 entries
+    a super-row once L > 256): the merges of one live key and of several
+    move entries across super-rows, and the first-level entries of the rank
+    are clamped to the last entry; the search stays bit-exact with the
+    oracle (3,000 points, so every worklist fills)."""
+    ix, q, gi = small_indexes["u8-d128-m32"]
+    run_and_compare(ix, gi, q, 10, L, label=f"u8-d128-m32 k=10 L={L}")
+
+
 @pytest.mark.parametrize("table", ["f16", "u8"])
 @pytest.mark.parametrize("name", list(SMALL))
 @pytest.mark.parametrize("k,L", [(1, 1), (10, 16), (5, 33), (10, 100),
